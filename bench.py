@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the PEIFE-linear hot path on one MI355X.
+
+One step = one complete Parareal solve (paper Algorithm 1) of the 2D FP64
+workload: 255 x 255 interior Q1 nodes on the unit square, D = 0.1, T = 2,
+forcing = 8 separable sine modes with random wavenumbers, N(0,1) amplitudes
+and cos(omega t) time factors (omega ~ U(1, 20)), u0 = 0, N = 64 slices,
+J = 32 fine steps per slice, 3-stage ETD-RK with random nodes, stopping at a
+1e-8 relative jump.  A step builds both phi tables, the coarse forcing and
+sweep, and runs every fine pass (quadrature + per-axis DST on the matrix
+cores + fused diagonal update) and correction sweep until the jump test
+holds; inputs are resident in HBM before the timed region.
+
+Reported value: fine DOF*stage updates per second over whole steps,
+(fine passes per step) * DOF * N * J * q / seconds per step.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fine DOF·stage updates/s + Parareal wall time to 1e-8 jump, learned vs plain G"
+PEAK_FP64_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
+
+
+def workload_name(p):
+    return (f"2D Q1 {p.n[0]}x{p.n[1]} interior nodes, D={p.D}, T={p.T}, "
+            f"{len(p.forcing)} sine modes, N={p.N} slices x J={p.J} fine steps, "
+            f"{p.q}-stage ETD-RK (random nodes), FP64, Parareal to {p.tol:g} relative jump")
+
+
+def cpu_baseline(prob, slices: int):
+    """The FP64 oracle (as it stands) on the first `slices` slices of the same
+    workload: both phi tables, the coarse sweep and every fine pass of
+    Algorithm 1 until the same jump test holds."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle.eife import Discretization
+    from oracle.parareal import parareal
+
+    sub = prob.with_(N=slices, T=prob.dT * slices)
+    t0 = time.perf_counter()
+    d = Discretization(sub)
+    tF = d.tables(sub.dt, sub.c_fine)
+    tG = d.tables(sub.dT, sub.c_coarse)
+    r = parareal(d, d.initial(), sub.t0, sub.N, sub.J, tF, tG, K_max=sub.K_max, tol=sub.tol)
+    sec = time.perf_counter() - t0
+    updates = r.iterations * sub.dof * sub.N * sub.J * sub.q
+    threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": updates / sec, "unit": "fine DOF·stage updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"oracle Parareal (phi tables, coarse sweep, {r.iterations} fine passes) on "
+                       f"the first {slices} of {prob.N} slices, {sec:.1f} s, BLAS threads "
+                       f"{threads}, host {cpu}, os.cpu_count()={os.cpu_count()}"),
+            "seconds": sec}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slices", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method shards by time slice; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as wl
+    from paper_2412_01138_amd import peifem
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    prob = wl.config(2)
+    g = peifem.Grid.from_problem(prob)
+    P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
+                       prob.K_max, prob.tol)
+    nwork = g.solve_workspace_bytes(P)
+    work = g.workspace(nwork)
+    U = g.empty_states(prob.N + 1)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        g.parareal_solve(P, U=U, work=work)
+    torch.cuda.synchronize()
+
+    g.set_timing(True)
+    reports = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, rep = g.parareal_solve(P, U=U, work=work)
+        reports.append(rep)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    stats = g.get_timing()
+    g.set_timing(False)
+
+    ms_per_step = sec * 1e3 / args.steps
+    iters = reports[-1].iterations
+    fine_updates = prob.dof * prob.N * prob.J * prob.q
+    value = iters * fine_updates / (ms_per_step / 1e3)
+    fine_ms = sum(r.ms_fine for r in reports) / len(reports)
+
+    tr = stats["transform"]
+    avg_ms = tr["ms"] / max(tr["launches"], 1)
+    flops_per_launch = tr["flops"] / max(tr["launches"], 1)
+    achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
+    kernels = {}
+    for name, st in stats.items():
+        if st["launches"] == 0:
+            continue
+        a_ms = st["ms"] / st["launches"]
+        kernels[name] = {"launches": st["launches"], "avg_ms": a_ms,
+                         "flops_per_launch": st["flops"] / st["launches"],
+                         "bytes_per_launch": st["bytes"] / st["launches"],
+                         "TFLOP/s": st["flops"] / st["launches"] / (a_ms / 1e3) / 1e12,
+                         "GB/s": st["bytes"] / st["launches"] / (a_ms / 1e3) / 1e9}
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "transform_traffic.json")
+    if os.path.exists(tfile):
+        try:
+            traffic = json.load(open(tfile)).get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "fine DOF·stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload_name(prob), "dof": prob.dof, "N": prob.N, "J": prob.J,
+                   "q": prob.q, "tol": prob.tol, "seed": prob.seed},
+        "parareal": {"iterations": iters, "converged": bool(reports[-1].converged),
+                     "jumps": [reports[-1].jumps[i] for i in range(iters)],
+                     "wall_ms_to_tol_plain_G": ms_per_step,
+                     "wall_ms_to_tol_learned_G": None,
+                     "ms_tables": sum(r.ms_tables for r in reports) / len(reports),
+                     "ms_coarse": sum(r.ms_coarse for r in reports) / len(reports),
+                     "ms_fine_per_pass": fine_ms / max(iters, 1),
+                     "ms_sweep": sum(r.ms_sweep for r in reports) / len(reports),
+                     "fine_pass_updates_per_s": fine_updates / (fine_ms / max(iters, 1) / 1e3)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "k_gemm_f64 (per-axis DST-I pass)",
+                     "avg_launch_ms": avg_ms, "flops_per_launch": flops_per_launch},
+        "kernels": kernels,
+        "cpu_baseline": None,
+        "host": platform.node(),
+    }
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_slices)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,253 @@
+/*
+ * peifem.h -- C ABI of the MI355X (gfx950) library for the Parareal
+ * exponential-integrator Q1 finite element method (PEIFE-linear) for
+ *
+ *     u_t = D * Laplace(u) + f(t, x)  on a box in R^d (d = 1..3),
+ *     u = 0 on the boundary, u(t0) = u0                    (paper, eq. (2.1))
+ *
+ * Everything runs in spectral space: the state of a time slice is the
+ * coefficient vector W of u_h in the M-orthonormal eigenbasis of the Q1 mass
+ * and stiffness matrices (the basis that diagonalises both at once, paper
+ * Section 2.3, closing paragraph).  In that basis L_h acts as D*lambda_k on
+ * coefficient k and the Euclidean norm of W is the L2 norm of u_h.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Status: PE_OK (0) on success, a negative pe_status otherwise; the
+ *    message of the last failure of the calling thread is pe_last_error().
+ *    No C++ exception crosses this ABI.
+ *  - Memory: every pointer named d_* is DEVICE memory owned by the caller
+ *    (the library never frees it); pointers named h_* or without prefix
+ *    (small parameter arrays) are HOST memory, read during the call only.
+ *    A pe_grid owns only its own small device tables; pe_free_grid releases
+ *    them.
+ *  - Layout: a state (one slice) is n_1*...*n_d coefficients in C order
+ *    (last axis fastest), mode k_a = 1..n_a stored at index k_a - 1.  Arrays
+ *    of slices are [slice][n_1]...[n_d], contiguous.
+ *  - Precision: PE_FP64 grids hold double states; PE_SPLIT_BF16 grids hold
+ *    float states and run the transforms as split-bf16 products with fp32
+ *    accumulation.  Phase tables (E, B) are always double, and so are norms.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls
+ *    enqueue work and return without synchronising, except where stated.
+ *    A pe_grid must not be used by two host threads at once.
+ */
+#ifndef PEIFEM_H
+#define PEIFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pe_status;
+#define PE_OK 0
+#define PE_E_ARG (-1)         /* invalid argument (sizes, null pointers, nodes) */
+#define PE_E_HIP (-2)         /* a HIP runtime call failed */
+#define PE_E_WORKSPACE (-3)   /* workspace smaller than required */
+#define PE_E_NUMERIC (-4)     /* a non-finite norm was produced */
+#define PE_E_UNSUPPORTED (-5) /* feature not available for this grid */
+
+#define PE_MAX_DIM 3
+#define PE_MAX_STAGES 8
+#define PE_MAX_TERMS 64
+#define PE_MAX_ITERS 64
+
+typedef enum { PE_FP64 = 0, PE_SPLIT_BF16 = 1 } pe_precision;
+
+typedef struct pe_grid_s *pe_grid;
+
+/* Separable descriptors.  One term is
+ *     amp * tau(t) * prod_a X_a(x_a),
+ *     tau(t) = exp(alpha t) cos(omega t + phase) (p0 + p1 t + p2 t^2 + p3 t^3),
+ *     X_a(x) = (q0 + q1 x + q2 x^2) sin(kappa x + phase).
+ * A pure polynomial space factor uses kappa = 0, phase = pi/2. */
+typedef struct {
+  double kappa;
+  double phase;
+  double poly[3];
+} pe_space_factor;
+
+typedef struct {
+  double alpha;
+  double omega;
+  double phase;
+  double poly[4];
+} pe_time_factor;
+
+typedef struct {
+  double amp;
+  pe_time_factor time;
+  pe_space_factor space[PE_MAX_DIM];
+} pe_term;
+
+/* --------------------------------------------------------------------- */
+
+/* Build a grid: n[a] interior Q1 nodes on [lo[a], hi[a]] (n[a] + 1 elements
+ * of width h_a = (hi - lo)/(n + 1), paper Section 2.1, eq. (2.2)), diffusion
+ * coefficient D > 0.  Computes on the device, per axis, the closed-form
+ * eigenvalues lambda_a(k) = (6/h^2)(1 - cos t_k)/(2 + cos t_k), the mass
+ * eigenvalues mu_a(k) = (h/3)(2 + cos t_k), t_k = k pi/(n + 1), and the
+ * orthonormal DST-I matrix S_a[k][j] = sqrt(2/(n+1)) sin(jk pi/(n+1)) (plus
+ * its bf16 hi/lo split for PE_SPLIT_BF16).  quad_q (1..8) is the number of
+ * Gauss-Legendre points per element and axis used for load vectors.
+ * Errors: PE_E_ARG for dim outside 1..3, n < 1, n > 8191, hi <= lo, D <= 0,
+ * bad precision or quad_q; PE_E_HIP on allocation failure.  On success *out
+ * receives the handle.  Synchronises `stream`. */
+pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double *lo,
+                       const double *hi, double D, int32_t precision, int32_t quad_q,
+                       void *stream);
+
+/* Release a grid and its device tables (NULL is ignored). */
+void pe_free_grid(pe_grid g);
+
+/* Set the forcing f (paper eq. (2.1)) as n_terms (0..PE_MAX_TERMS) separable
+ * terms (host array).  Builds on the device the 1D load tables
+ * C_{m,a}[j] = int X_{m,a}(x) phi_j(x) dx by the grid's Gauss rule (the load
+ * vector of P_h f, paper eq. (2.6)).  Errors: PE_E_ARG.  Synchronises. */
+pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream);
+
+/* Exponential Runge-Kutta tables for step h > 0 and s (1..PE_MAX_STAGES)
+ * distinct nodes c[0..s-1] in [0, 1] (host):
+ *     d_E[k]       = exp(-h D lambda_k)
+ *     d_B[i*DOF+k] = h * b_i(h D lambda_k),
+ *     b_i(z) = int_0^1 exp(-z (1 - theta)) l_i(theta) dtheta       (eq. (2.7))
+ * in FP64, with l_i the Lagrange basis of the nodes; DOF = prod n_a and
+ * lambda_k = sum_a lambda_a(k_a).  d_E holds DOF doubles, d_B s*DOF.
+ * Errors: PE_E_ARG (h <= 0, s out of range, nodes not distinct or outside
+ * [0,1], null pointers). */
+pe_status pe_phi_tables(pe_grid g, double h, int32_t s, const double *c, double *d_E, double *d_B,
+                        void *stream);
+
+/* Spectral coefficients of P_h v for a time-independent separable function v
+ * (n_terms terms; the time factors are ignored): d_W (one state) receives
+ * (kron_a Q_a)^T F_v, F_v the load vector of v by the grid's Gauss rule.
+ * This is how u0 enters (u_h(t0) = P_h u0, eq. (2.2)).  n_terms = 0 writes
+ * zeros.  Needs pe_project_workspace_bytes() of d_work. */
+size_t pe_project_workspace_bytes(pe_grid g);
+pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W, void *d_work,
+                     size_t work_bytes, void *stream);
+
+/* Fine propagator F on all slices at once (paper, Section 2.3: F is J steps
+ * of eq. (2.6) with step dt = dT/J and q nodes):
+ *     d_Uout[n] = F^J(d_Uin[n]; t0 + n*dT),   n = 0..n_slices-1.
+ * d_Uin and d_Uout are [n_slices][DOF] states (they must not overlap);
+ * cF[0..q-1] (host) are the stage nodes, d_EF / d_BF the tables of
+ * pe_phi_tables(g, dT/J, q, cF).  Each step evaluates the load vector of f at
+ * the q stage times on the full grid (Gauss quadrature), transforms it to
+ * spectral space by d dense per-axis DST products on the matrix cores, and
+ * applies the diagonal update  V <- E V + sum_i B_i g_i.  Needs at least
+ * pe_fine_workspace_bytes(g, q) bytes of d_work (unless f has no terms); more workspace lets more
+ * (slice, step, stage) fields be transformed per launch (the value for
+ * `fields` fields is pe_fine_workspace_bytes(g, fields)).
+ * Errors: PE_E_ARG, PE_E_WORKSPACE, PE_E_HIP. */
+size_t pe_fine_workspace_bytes(pe_grid g, int64_t fields);
+pe_status pe_fine_propagate(pe_grid g, int32_t n_slices, double t0, double dT, int32_t J,
+                            int32_t q, const double *cF, const double *d_EF, const double *d_BF,
+                            const void *d_Uin, void *d_Uout, void *d_work, size_t work_bytes,
+                            void *stream);
+
+/* Coarse propagator G and the Parareal correction (paper Algorithm 1 and
+ * eq. (2.8)), G(v; T_n) = E_G v + r_n (+ d_corr[n]) with
+ *     r_n = dT sum_i b_i(dT D lambda) P_h f(T_n + c_i dT),   T_n = t0 + n dT.
+ *  - compute_r != 0: first fill d_r[n] (n = 0..N-1) with r_n (all slices in
+ *    parallel); compute_r == 0 reuses d_r as given.
+ *  - d_Uprev == NULL (plain coarse sweep: the sequential coarse start of Algorithm 1):
+ *        d_U[n+1] = G(d_U[n]; T_n),                 n = 0..N-1
+ *  - d_Uprev != NULL and d_Fout != NULL (correction sweep, eq. (2.8)):
+ *        d_U[n+1] = G(d_U[n]) + d_Fout[n] - G(d_Uprev[n])
+ *    d_U[0] is read, never written.  d_U, d_Uprev are [N+1][DOF] states,
+ *    d_Fout, d_r and d_corr (nullable: no learned correction) [N][DOF].
+ *  - d_norms (nullable, 2 doubles, device): d_norms[0] = sum over n = 1..N of
+ *    ||d_U[n] - d_Uprev[n]||^2 (0 without d_Uprev), d_norms[1] = sum over
+ *    n = 1..N of ||d_U[n]||^2, accumulated in FP64 in a fixed order (bitwise
+ *    repeatable).
+ * Needs pe_coarse_workspace_bytes(g, N, p) bytes of d_work (a smaller
+ * workspace still works when it holds the norm partials and p stage fields;
+ * r_n is then computed a few slices at a time). */
+size_t pe_coarse_workspace_bytes(pe_grid g, int32_t n_slices, int32_t p);
+pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int32_t p,
+                          const double *cG, const double *d_EG, const double *d_BG,
+                          int32_t compute_r, void *d_r, const void *d_corr, const void *d_Uprev,
+                          const void *d_Fout, void *d_U, double *d_norms, void *d_work,
+                          size_t work_bytes, void *stream);
+
+/* Parareal driver (paper Algorithm 1).  Stopping rule (the paper leaves it
+ * open): after iteration k the relative jump
+ *     ||U^(k) - U^(k-1)|| / ||U^(k)||    (all slice ends n = 1..N, FP64)
+ * is compared with tol; the loop stops when jump <= tol (converged = 1) or
+ * after K_max fine passes (converged = 0, still PE_OK). */
+typedef struct {
+  double t0;
+  double T;
+  int32_t N;                   /* coarse slices */
+  int32_t J;                   /* fine steps per slice */
+  int32_t p;                   /* coarse stages */
+  int32_t q;                   /* fine stages */
+  double cG[PE_MAX_STAGES];
+  double cF[PE_MAX_STAGES];
+  int32_t K_max;               /* 1..PE_MAX_ITERS fine passes at most */
+  double tol;
+  const void *d_corr;          /* nullable [N][DOF] learned coarse correction */
+} pe_solve_params;
+
+typedef struct {
+  int32_t iterations;          /* fine passes performed */
+  int32_t converged;
+  double jumps[PE_MAX_ITERS];  /* jumps[k-1]: relative jump of iterate k */
+  double ms_tables;            /* phi tables (both step sizes) */
+  double ms_coarse;            /* r_n and the initial coarse sweep */
+  double ms_fine;              /* all fine passes */
+  double ms_sweep;             /* correction sweeps + norms */
+  double ms_total;
+} pe_solve_report;
+
+/* d_U0: initial state (one state, nullable = zero); d_U receives the last
+ * iterate [N+1][DOF].  Needs pe_solve_workspace_bytes(g, P) of d_work.
+ * Synchronises `stream` once per iteration (one 16-byte read-back of the
+ * jump norms).  Errors: PE_E_ARG, PE_E_WORKSPACE, PE_E_HIP, PE_E_NUMERIC
+ * (non-finite jump). */
+size_t pe_solve_workspace_bytes(pe_grid g, const pe_solve_params *P);
+pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U0, void *d_U,
+                            void *d_work, size_t work_bytes, pe_solve_report *rep, void *stream);
+
+/* Kernel timing, for benchmarks.  While enabled, the library brackets every
+ * launch of its main kernels with HIP events recorded on the launch stream
+ * and accumulates, per kernel class, the launch count, the summed event time
+ * and the algorithmic work of those launches: flops of the dense transform
+ * (2 * DOF * n_a per field and axis pass, unpadded sizes) and HBM bytes
+ * (each array read or written once, unpadded).  pe_set_timing(g, 1) enables
+ * and resets the counters, pe_set_timing(g, 0) disables.  pe_get_timing
+ * waits for the recorded events and fills out[0..PE_K_COUNT-1].  Errors:
+ * PE_E_ARG, PE_E_HIP. */
+typedef enum {
+  PE_K_TRANSFORM = 0, /* per-axis DST products (matrix cores) */
+  PE_K_LOAD = 1,      /* stage load-vector quadrature */
+  PE_K_UPDATE = 2,    /* fused diagonal update */
+  PE_K_SWEEP = 3,     /* coarse / correction sweep with norms */
+  PE_K_COUNT = 4
+} pe_kernel_class;
+
+typedef struct {
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} pe_kernel_stat;
+
+pe_status pe_set_timing(pe_grid g, int32_t enable);
+pe_status pe_get_timing(pe_grid g, pe_kernel_stat *out);
+
+/* Grid queries. */
+int64_t pe_grid_dof(pe_grid g);
+int32_t pe_grid_precision(pe_grid g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *pe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEIFEM_H */

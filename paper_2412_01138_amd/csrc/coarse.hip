@@ -1,0 +1,188 @@
+// Coarse propagator G, the Parareal correction sweep and the jump norms.
+//
+// Paper Section 2.3: G(v; T_n) = exp(-dT L_h) v + dT sum_i b_i(-dT L_h)
+// P_h f(T_n + c_i dT) -- in spectral space G(v) = E_G v + r_n with the
+// state-independent forcing response r_n.  Algorithm 1 runs G sequentially
+// over the slices; eq. (2.8) is the correction
+//     U^{n+1,(k+1)} = G(U^{n,(k+1)}) + Fbar^{n+1} - G(U^{n,(k)}).
+// The sweep is a first-order linear recurrence per coefficient: one thread
+// owns one coefficient and walks n = 0..N-1, reading each slice once
+// (coalesced across threads).  The squared norms of the jump and of the new
+// iterate are accumulated in FP64 with a fixed reduction order.
+#include <algorithm>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int J, int s,
+                          const double *c, const double *d_E, const double *d_B, const void *d_Uin,
+                          void *d_Uout, void *d_work, size_t work_bytes, hipStream_t st);
+
+constexpr int SWEEP_BS = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block-wide sum of two values in a fixed order; result valid in thread 0.
+__device__ inline void block_sum2(double &a, double &b) {
+  __shared__ double sa[SWEEP_BS / 64], sb[SWEEP_BS / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sa[wave] = a;
+    sb[wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0, y = 0;
+    for (int w = 0; w < SWEEP_BS / 64; ++w) {
+      x += sa[w];
+      y += sb[w];
+    }
+    a = x;
+    b = y;
+  }
+}
+
+template <typename TS>
+__global__ __launch_bounds__(SWEEP_BS) void k_sweep(const double *__restrict__ E,
+                                                    const TS *__restrict__ r,
+                                                    const TS *__restrict__ corr,
+                                                    const TS *__restrict__ Uprev,
+                                                    const TS *__restrict__ Fout, TS *U, int N,
+                                                    int64_t dof, double *partials) {
+  int64_t k = int64_t(blockIdx.x) * SWEEP_BS + threadIdx.x;
+  double acc_jump = 0.0, acc_norm = 0.0;
+  if (k < dof) {
+    const double e = E[k];
+    double u = double(U[k]);
+    double up = Uprev ? double(Uprev[k]) : 0.0;
+    const bool correct = Uprev != nullptr && Fout != nullptr;
+    for (int n = 0; n < N; ++n) {
+      const int64_t o = int64_t(n) * dof + k;
+      double base = double(r[o]);
+      if (corr) base += double(corr[o]);
+      double gnew = e * u + base;                 // G(U^{n,(k+1)})
+      double next = gnew;
+      if (correct) {
+        double gold = e * up + base;              // G(U^{n,(k)})
+        next = (gnew + double(Fout[o])) - gold;   // eq. (2.8)
+      }
+      TS stored = TS(next);
+      U[o + dof] = stored;
+      double nv = double(stored);
+      if (Uprev) {
+        double upn = double(Uprev[o + dof]);
+        double dlt = nv - upn;
+        acc_jump += dlt * dlt;
+        up = upn;
+      }
+      acc_norm += nv * nv;
+      u = nv;
+    }
+  }
+  if (partials) {
+    block_sum2(acc_jump, acc_norm);
+    if (threadIdx.x == 0) {
+      partials[2 * blockIdx.x] = acc_jump;
+      partials[2 * blockIdx.x + 1] = acc_norm;
+    }
+  }
+}
+
+// One block: out[0..1] = sums of the block partials, in a fixed order.
+__global__ __launch_bounds__(SWEEP_BS) void k_reduce_partials(const double *partials, int nblocks,
+                                                              double *out) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += SWEEP_BS) {
+    a += partials[2 * i];
+    b += partials[2 * i + 1];
+  }
+  block_sum2(a, b);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+static size_t partial_bytes(pe_grid g) {
+  int64_t nb = (g->dof + SWEEP_BS - 1) / SWEEP_BS;
+  return Arena::need(sizeof(double) * 2 * size_t(nb));
+}
+
+pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const void *d_corr,
+                const void *d_Uprev, const void *d_Fout, void *d_U, double *d_norms,
+                double *partials, hipStream_t st) {
+  int nb = int((g->dof + SWEEP_BS - 1) / SWEEP_BS);
+  const double sb = g->precision == PE_FP64 ? 8.0 : 4.0;
+  int arrays = 2 + (d_corr ? 1 : 0) + (d_Uprev ? 2 : 0);   // r, U write, corr, Uprev, Fout
+  TimedScope ts(g, PE_K_SWEEP, 0.0, double(N) * double(g->dof) * sb * arrays + g->dof * 8.0, st);
+  if (g->precision == PE_FP64)
+    k_sweep<double><<<nb, SWEEP_BS, 0, st>>>(
+        d_EG, static_cast<const double *>(d_r), static_cast<const double *>(d_corr),
+        static_cast<const double *>(d_Uprev), static_cast<const double *>(d_Fout),
+        static_cast<double *>(d_U), N, g->dof, d_norms ? partials : nullptr);
+  else
+    k_sweep<float><<<nb, SWEEP_BS, 0, st>>>(
+        d_EG, static_cast<const float *>(d_r), static_cast<const float *>(d_corr),
+        static_cast<const float *>(d_Uprev), static_cast<const float *>(d_Fout),
+        static_cast<float *>(d_U), N, g->dof, d_norms ? partials : nullptr);
+  PE_HIP(hipGetLastError());
+  if (d_norms) {
+    k_reduce_partials<<<1, SWEEP_BS, 0, st>>>(partials, nb, d_norms);
+    PE_HIP(hipGetLastError());
+  }
+  return PE_OK;
+}
+
+size_t coarse_partials_bytes(pe_grid g) { return partial_bytes(g); }
+
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" {
+
+size_t pe_coarse_workspace_bytes(pe_grid g, int32_t n_slices, int32_t p) {
+  if (!g || n_slices < 1 || p < 1) return 0;
+  return partial_bytes(g) + 256 + pe_fine_workspace_bytes(g, int64_t(n_slices) * p);
+}
+
+pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int32_t p,
+                          const double *cG, const double *d_EG, const double *d_BG,
+                          int32_t compute_r, void *d_r, const void *d_corr, const void *d_Uprev,
+                          const void *d_Fout, void *d_U, double *d_norms, void *d_work,
+                          size_t work_bytes, void *stream) {
+  clear_error();
+  if (!g || !d_EG || !d_r || !d_U) return set_error(PE_E_ARG, "null argument");
+  if (n_slices < 1) return set_error(PE_E_ARG, "n_slices must be >= 1");
+  if ((d_Uprev == nullptr) != (d_Fout == nullptr))
+    return set_error(PE_E_ARG, "d_Uprev and d_Fout must be given together");
+  if (d_Uprev == d_U && d_U) return set_error(PE_E_ARG, "d_Uprev must differ from d_U");
+  hipStream_t st = as_stream(stream);
+  Arena ar(d_work, work_bytes);
+  double *partials = nullptr;
+  if (d_norms) {
+    if (!d_work) return set_error(PE_E_ARG, "norms need a workspace");
+    partials = ar.take<double>(partial_bytes(g) / sizeof(double));
+    if (!partials) return set_error(PE_E_WORKSPACE, "workspace too small for the norm partials");
+  }
+  if (compute_r) {
+    if (!cG || !d_BG) return set_error(PE_E_ARG, "null coarse nodes/tables");
+    if (p < 1 || p > PE_MAX_STAGES) return set_error(PE_E_ARG, "p must be 1..%d", PE_MAX_STAGES);
+    if (!(dT > 0) || !std::isfinite(dT)) return set_error(PE_E_ARG, "bad dT");
+    size_t off = (ar.off + 255) & ~size_t(255);
+    void *rest = d_work ? static_cast<char *>(d_work) + off : nullptr;
+    size_t rest_bytes = work_bytes > off ? work_bytes - off : 0;
+    PE_TRY(run_propagation(g, n_slices, t0, dT, dT, 1, p, cG, d_EG, d_BG, nullptr, d_r, rest,
+                           rest_bytes, st));
+  }
+  return sweep(g, n_slices, d_EG, d_r, d_corr, d_Uprev, d_Fout, d_U, d_norms, partials, st);
+}
+
+}  // extern "C"

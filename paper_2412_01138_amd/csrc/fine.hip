@@ -1,0 +1,384 @@
+// Fine propagator F on all Parareal slices at once, and the projection P_h.
+//
+// Paper eq. (2.6): one EIFE-linear step
+//     W <- exp(-h D lambda) W + h sum_i b_i(h D lambda) ghat(t + c_i h),
+// ghat(t) = Q^T F(t) the spectral coefficients of P_h f(t), F(t) the Q1 load
+// vector.  Section 2.3: F^J is J such steps of size dt = dT/J with q nodes,
+// applied to every slice n in parallel (Algorithm 1, the parallel line).
+//
+// Because the forcing does not depend on the state (linear problem), the
+// load vectors of all (slice, step, stage) fields of a batch are evaluated
+// and transformed together (large launches), and the diagonal update then
+// walks the steps of the batch in order, keeping each coefficient's state in
+// a register.
+#include <algorithm>
+#include <vector>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+// coef[f][m] = amp_m tau_m(t_f) for every field f of the batch
+__global__ void k_time_coefs(FieldBatch b, const DevTerm *terms, int n_terms, double *coef,
+                             int64_t count) {
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < count * n_terms;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+  int64_t f = idx / n_terms;
+  int m = int(idx - f * n_terms);
+  int64_t per_slice = int64_t(b.jc) * b.s;
+  int n = b.n0 + int(f / per_slice);
+  int rem = int(f - (f / per_slice) * per_slice);
+  int j = b.j0 + rem / b.s;
+  int i = rem - (rem / b.s) * b.s;
+  double t = ((b.t0 + double(n) * b.dT) + double(j) * b.dt) + b.c[i] * b.dt;
+  DevTerm tm = terms[m];
+  double poly = tm.p[0] + t * (tm.p[1] + t * (tm.p[2] + t * tm.p[3]));
+  coef[idx] = tm.amp * exp(tm.alpha * t) * cos(tm.omega * t + tm.phase) * poly;
+  }
+}
+
+struct Dims {
+  int d;
+  int n[PE_MAX_DIM];
+  int np[PE_MAX_DIM];
+};
+
+static Dims dims_of(pe_grid g) {
+  Dims D{};
+  D.d = g->dim;
+  for (int a = 0; a < PE_MAX_DIM; ++a) {
+    D.n[a] = a < g->dim ? g->ax[a].n : 1;
+    D.np[a] = a < g->dim ? g->ax[a].np : 1;
+  }
+  return D;
+}
+
+// Load vectors of `count` fields on the padded grid (pads = 0):
+//   F_f[j] = sum_m coef[f][m] prod_a C_a[m][j_a]
+// (the tensor Gauss rule applied to a separable term factorises into 1D
+// rules, so C_a are the per-axis element-quadrature loads).
+template <typename TG>
+__global__ void k_load_fields(Dims D, const double *__restrict__ C0, const double *__restrict__ C1,
+                              const double *__restrict__ C2, int n_terms,
+                              const double *__restrict__ coef, TG *__restrict__ out, int64_t dofp,
+                              int64_t total) {
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+  int64_t f = idx / dofp;
+  int64_t p = idx - f * dofp;
+  int j[3] = {0, 0, 0};
+  int64_t r = p;
+  for (int a = D.d - 1; a >= 0; --a) {
+    j[a] = int(r % D.np[a]);
+    r /= D.np[a];
+  }
+  bool inside = true;
+  for (int a = 0; a < D.d; ++a) inside = inside && (j[a] < D.n[a]);
+  double v = 0.0;
+  if (inside) {
+    const double *cf = coef + f * n_terms;
+    for (int m = 0; m < n_terms; ++m) {
+      double prod = cf[m] * C0[int64_t(m) * D.np[0] + j[0]];
+      if (D.d > 1) prod *= C1[int64_t(m) * D.np[1] + j[1]];
+      if (D.d > 2) prod *= C2[int64_t(m) * D.np[2] + j[2]];
+      v += prod;
+    }
+  }
+  out[idx] = TG(v);
+  }
+}
+
+// The fused diagonal update of eq. (2.6) over the jc steps of a batch, for
+// every slice and every (unpadded) coefficient k:
+//     V <- E_k V + sum_i B_ik sigma_k G[f(n, j, i)][p(k)]
+// sigma_k = prod_a 1/sqrt(mu_a(k_a)) turns DST coefficients into
+// M-orthonormal ones.  Uin == nullptr means a zero initial state.
+template <typename TS, typename TG>
+__global__ void k_update(Dims D, const double *__restrict__ sig0, const double *__restrict__ sig1,
+                         const double *__restrict__ sig2, const double *__restrict__ E,
+                         const double *__restrict__ B, int s, const TS *Uin, TS *Uout,
+                         const TG *__restrict__ G, int nslices, int jc, int64_t dof,
+                         int64_t dofp) {
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < int64_t(nslices) * dof;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+  int64_t n = idx / dof;
+  int64_t k = idx - n * dof;
+  int kk[3] = {0, 0, 0};
+  int64_t r = k;
+  for (int a = D.d - 1; a >= 0; --a) {
+    kk[a] = int(r % D.n[a]);
+    r /= D.n[a];
+  }
+  int64_t p = 0;
+  for (int a = 0; a < D.d; ++a) p = p * D.np[a] + kk[a];
+  double sig = sig0[kk[0]];
+  if (D.d > 1) sig *= sig1[kk[1]];
+  if (D.d > 2) sig *= sig2[kk[2]];
+  double e = E[k];
+  double bs[PE_MAX_STAGES];
+  for (int i = 0; i < s; ++i) bs[i] = B[int64_t(i) * dof + k] * sig;
+  double V = Uin ? double(Uin[idx]) : 0.0;
+  const TG *Gn = G + (n * jc) * int64_t(s) * dofp + p;
+  for (int j = 0; j < jc; ++j) {
+    double v = e * V;
+    for (int i = 0; i < s; ++i) v += bs[i] * double(Gn[(int64_t(j) * s + i) * dofp]);
+    V = v;
+  }
+  Uout[idx] = TS(V);
+  }
+}
+
+template <typename TS>
+__global__ void k_decay(const double *__restrict__ E, const TS *Uin, TS *Uout, int nslices, int jc,
+                        int64_t dof) {
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < int64_t(nslices) * dof;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+    int64_t k = idx % dof;
+    double e = E[k];
+    double V = Uin ? double(Uin[idx]) : 0.0;
+    for (int j = 0; j < jc; ++j) V = e * V;
+    Uout[idx] = TS(V);
+  }
+}
+
+// W[k] = sigma_k G[p(k)]  (projection output, one field)
+template <typename TS, typename TG>
+__global__ void k_scale_compact(Dims D, const double *sig0, const double *sig1, const double *sig2,
+                                const TG *G, TS *W, int64_t dof) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < dof;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    int kk[3] = {0, 0, 0};
+    int64_t r = k;
+    for (int a = D.d - 1; a >= 0; --a) {
+      kk[a] = int(r % D.n[a]);
+      r /= D.n[a];
+    }
+    int64_t p = 0;
+    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + kk[a];
+    double sig = sig0[kk[0]];
+    if (D.d > 1) sig *= sig1[kk[1]];
+    if (D.d > 2) sig *= sig2[kk[2]];
+    W[k] = TS(sig * double(G[p]));
+  }
+}
+
+// Flat launches use grid-stride loops over at most 2^16 blocks (HIP limits a
+// grid dimension to 2^32 work-items).
+static inline unsigned blocks_for(int64_t n, int bs = 256) {
+  int64_t b = (n + bs - 1) / bs;
+  return unsigned(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+static pe_status launch_load(pe_grid g, double *const *C, int n_terms, const double *coef,
+                             void *out, int64_t count, hipStream_t st) {
+  Dims D = dims_of(g);
+  int64_t total = count * g->dofp;
+  const double sb = g->precision == PE_FP64 ? 8.0 : 4.0;
+  TimedScope ts(g, PE_K_LOAD, 0.0, double(count) * double(g->dof) * sb, st);
+  if (g->precision == PE_FP64)
+    k_load_fields<double><<<blocks_for(total), 256, 0, st>>>(
+        D, C[0], C[1], C[2], n_terms, coef, static_cast<double *>(out), g->dofp, total);
+  else
+    k_load_fields<float><<<blocks_for(total), 256, 0, st>>>(
+        D, C[0], C[1], C[2], n_terms, coef, static_cast<float *>(out), g->dofp, total);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+static pe_status transform(pe_grid g, int64_t count, void *work0, void *work1, void **result,
+                           hipStream_t st) {
+  if (g->precision == PE_FP64) {
+    double *r = nullptr;
+    PE_TRY(dst_fields_f64(g, count, static_cast<double *>(work0), static_cast<double *>(work1), &r,
+                          st));
+    *result = r;
+  } else {
+    float *r = nullptr;
+    PE_TRY(dst_fields_split(g, count, static_cast<float *>(work0), static_cast<float *>(work1), &r,
+                            st));
+    *result = r;
+  }
+  return PE_OK;
+}
+
+pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
+                             double *coef, void **result, hipStream_t st) {
+  int64_t count = b.count();
+  int64_t nc = count * g->n_terms;
+  k_time_coefs<<<blocks_for(nc), 256, 0, st>>>(b, g->d_terms, g->n_terms, coef, count);
+  PE_HIP(hipGetLastError());
+  PE_TRY(launch_load(g, g->d_C, g->n_terms, coef, work0, count, st));
+  return transform(g, count, work0, work1, result, st);
+}
+
+static size_t per_field_bytes(pe_grid g) {
+  return 2 * field_bytes(g) + sizeof(double) * size_t(std::max(g->n_terms, 1));
+}
+
+// Run the batches of one F pass (or of the coarse forcing, with a zero
+// initial state): slices [0, N), J steps of size dt starting at t0 + n dT.
+pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int J, int s,
+                          const double *c, const double *d_E, const double *d_B, const void *d_Uin,
+                          void *d_Uout, void *d_work, size_t work_bytes, hipStream_t st) {
+  const int64_t dof = g->dof;
+  const bool fp64 = g->precision == PE_FP64;
+  const size_t sbytes = fp64 ? sizeof(double) : sizeof(float);
+  Dims D = dims_of(g);
+  if (g->n_terms == 0) {
+    // no forcing: pure decay, J steps at once
+    int64_t tot = int64_t(N) * dof;
+    if (fp64)
+      k_decay<double><<<blocks_for(tot), 256, 0, st>>>(d_E, static_cast<const double *>(d_Uin),
+                                                        static_cast<double *>(d_Uout), N, J, dof);
+    else
+      k_decay<float><<<blocks_for(tot), 256, 0, st>>>(d_E, static_cast<const float *>(d_Uin),
+                                                       static_cast<float *>(d_Uout), N, J, dof);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+  }
+  size_t pf = per_field_bytes(g);
+  size_t overhead = 3 * 256;
+  if (work_bytes < overhead + pf * size_t(s))
+    return set_error(PE_E_WORKSPACE, "workspace %zu B below the minimum %zu B", work_bytes,
+                     overhead + pf * size_t(s));
+  int64_t fit = int64_t((work_bytes - overhead) / pf);
+  int64_t total = int64_t(N) * J * s;
+  int Nb, Jc;
+  if (fit >= total) {
+    Nb = N;
+    Jc = J;
+  } else if (fit >= int64_t(N) * s) {
+    Nb = N;
+    Jc = int(fit / (int64_t(N) * s));
+  } else {
+    Nb = int(fit / s);
+    Jc = 1;
+  }
+  int64_t maxf = int64_t(Nb) * Jc * s;
+  Arena ar(d_work, work_bytes);
+  double *coef = ar.take<double>(size_t(maxf) * std::max(g->n_terms, 1));
+  char *w0 = ar.take<char>(size_t(maxf) * field_bytes(g));
+  char *w1 = ar.take<char>(size_t(maxf) * field_bytes(g));
+  if (!coef || !w0 || !w1) return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+
+  for (int n0 = 0; n0 < N; n0 += Nb) {
+    int nb = std::min(Nb, N - n0);
+    for (int j0 = 0; j0 < J; j0 += Jc) {
+      int jc = std::min(Jc, J - j0);
+      FieldBatch b{};
+      b.n0 = n0;
+      b.nslices = nb;
+      b.j0 = j0;
+      b.jc = jc;
+      b.s = s;
+      b.t0 = t0;
+      b.dT = dT;
+      b.dt = dt;
+      for (int i = 0; i < s; ++i) b.c[i] = c[i];
+      void *res = nullptr;
+      PE_TRY(load_and_transform(g, b, w0, w1, coef, &res, st));
+      const char *uin = (j0 == 0) ? static_cast<const char *>(d_Uin)
+                                  : static_cast<const char *>(d_Uout);
+      if (uin) uin += size_t(n0) * dof * sbytes;
+      char *uout = static_cast<char *>(d_Uout) + size_t(n0) * dof * sbytes;
+      int64_t tot = int64_t(nb) * dof;
+      // state read + write, jc*s stage fields read, tables read once
+      TimedScope ts(g, PE_K_UPDATE, 0.0,
+                    double(tot) * sbytes * (2.0 + double(jc) * s) + double(1 + s) * dof * 8.0, st);
+      if (fp64)
+        k_update<double, double><<<blocks_for(tot), 256, 0, st>>>(
+            D, g->ax[0].d_sig, g->ax[1].d_sig, g->ax[2].d_sig, d_E, d_B, s,
+            reinterpret_cast<const double *>(uin), reinterpret_cast<double *>(uout),
+            static_cast<const double *>(res), nb, jc, dof, g->dofp);
+      else
+        k_update<float, float><<<blocks_for(tot), 256, 0, st>>>(
+            D, g->ax[0].d_sig, g->ax[1].d_sig, g->ax[2].d_sig, d_E, d_B, s,
+            reinterpret_cast<const float *>(uin), reinterpret_cast<float *>(uout),
+            static_cast<const float *>(res), nb, jc, dof, g->dofp);
+      PE_HIP(hipGetLastError());
+    }
+  }
+  return PE_OK;
+}
+
+pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst, hipStream_t st);
+DevTerm to_dev_term(const pe_term &t);
+
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" {
+
+size_t pe_fine_workspace_bytes(pe_grid g, int64_t fields) {
+  if (!g || fields < 1) return 0;
+  return 3 * 256 + size_t(fields) * per_field_bytes(g) + 3 * 256;
+}
+
+pe_status pe_fine_propagate(pe_grid g, int32_t n_slices, double t0, double dT, int32_t J,
+                            int32_t q, const double *cF, const double *d_EF, const double *d_BF,
+                            const void *d_Uin, void *d_Uout, void *d_work, size_t work_bytes,
+                            void *stream) {
+  clear_error();
+  if (!g || !cF || !d_EF || !d_BF || !d_Uin || !d_Uout) return set_error(PE_E_ARG, "null argument");
+  if (n_slices < 1 || J < 1) return set_error(PE_E_ARG, "n_slices and J must be >= 1");
+  if (q < 1 || q > PE_MAX_STAGES) return set_error(PE_E_ARG, "q must be 1..%d", PE_MAX_STAGES);
+  if (!(dT > 0) || !std::isfinite(dT) || !std::isfinite(t0)) return set_error(PE_E_ARG, "bad dT/t0");
+  if (d_Uin == d_Uout) return set_error(PE_E_ARG, "d_Uin and d_Uout must not overlap");
+  if (g->n_terms > 0 && !d_work) return set_error(PE_E_ARG, "null workspace");
+  return run_propagation(g, n_slices, t0, dT, dT / J, J, q, cF, d_EF, d_BF, d_Uin, d_Uout, d_work,
+                         work_bytes, as_stream(stream));
+}
+
+size_t pe_project_workspace_bytes(pe_grid g) {
+  if (!g) return 0;
+  size_t b = 8 * 256 + 2 * field_bytes(g);
+  for (int a = 0; a < g->dim; ++a) b += sizeof(double) * PE_MAX_TERMS * g->ax[a].np;
+  b += sizeof(double) * PE_MAX_TERMS + sizeof(DevTerm) * PE_MAX_TERMS;
+  return b;
+}
+
+pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W, void *d_work,
+                     size_t work_bytes, void *stream) {
+  clear_error();
+  if (!g || !d_W) return set_error(PE_E_ARG, "null argument");
+  if (n_terms < 0 || n_terms > PE_MAX_TERMS) return set_error(PE_E_ARG, "n_terms out of range");
+  if (n_terms > 0 && (!terms || !d_work)) return set_error(PE_E_ARG, "null terms/workspace");
+  hipStream_t st = as_stream(stream);
+  size_t sbytes = g->precision == PE_FP64 ? sizeof(double) : sizeof(float);
+  if (n_terms == 0) {
+    PE_HIP(hipMemsetAsync(d_W, 0, size_t(g->dof) * sbytes, st));
+    return PE_OK;
+  }
+  if (work_bytes < pe_project_workspace_bytes(g))
+    return set_error(PE_E_WORKSPACE, "workspace %zu B below %zu B", work_bytes,
+                     pe_project_workspace_bytes(g));
+  Arena ar(d_work, work_bytes);
+  double *C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};
+  for (int a = 0; a < g->dim; ++a) C[a] = ar.take<double>(size_t(n_terms) * g->ax[a].np);
+  double *coef = ar.take<double>(n_terms);
+  char *w0 = ar.take<char>(field_bytes(g));
+  char *w1 = ar.take<char>(field_bytes(g));
+  if (!coef || !w0 || !w1) return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  PE_TRY(build_loads(g, n_terms, terms, C, st));
+  std::vector<double> amps(n_terms);
+  for (int m = 0; m < n_terms; ++m) amps[m] = terms[m].amp;
+  PE_HIP(hipMemcpyAsync(coef, amps.data(), sizeof(double) * n_terms, hipMemcpyHostToDevice, st));
+  PE_TRY(launch_load(g, C, n_terms, coef, w0, 1, st));
+  void *res = nullptr;
+  PE_TRY(transform(g, 1, w0, w1, &res, st));
+  Dims D = dims_of(g);
+  if (g->precision == PE_FP64)
+    k_scale_compact<double, double><<<blocks_for(g->dof), 256, 0, st>>>(
+        D, g->ax[0].d_sig, g->ax[1].d_sig, g->ax[2].d_sig, static_cast<const double *>(res),
+        static_cast<double *>(d_W), g->dof);
+  else
+    k_scale_compact<float, float><<<blocks_for(g->dof), 256, 0, st>>>(
+        D, g->ax[0].d_sig, g->ax[1].d_sig, g->ax[2].d_sig, static_cast<const float *>(res),
+        static_cast<float *>(d_W), g->dof);
+  PE_HIP(hipGetLastError());
+  PE_HIP(hipStreamSynchronize(st));   // amps is host memory read by the copy
+  return PE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,429 @@
+// Grid set-up, forcing load tables and exponential Runge-Kutta tables.
+//
+// Paper, Section 2.1: tensor Q1 space on a uniform box mesh; Section 2.3
+// (closing paragraph): the Q1 mass and stiffness matrices are diagonalised
+// simultaneously by one orthogonal matrix.  In 1D both are polynomials in
+// tridiag(1, 0, 1), whose orthonormal eigenvectors are the DST-I vectors
+// s_k(j) = sqrt(2/(n+1)) sin(jk pi/(n+1)); the mass eigenvalue is
+// mu(k) = (h/3)(2 + cos t_k) and the stiffness/mass ratio is
+// lambda(k) = (6/h^2)(1 - cos t_k)/(2 + cos t_k), t_k = k pi/(n + 1).
+// Eq. (2.7): b_i(z) = int_0^1 exp(-z(1 - theta)) l_i(theta) dtheta.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+static thread_local std::string g_err;
+
+pe_status set_error(pe_status st, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+void clear_error() { g_err.clear(); }
+
+size_t field_bytes(pe_grid g) {
+  return size_t(g->dofp) * (g->precision == PE_FP64 ? sizeof(double) : sizeof(float));
+}
+
+// ------------------------------------------------------------------ kernels
+
+// bf16 round-to-nearest-even of a float, as raw bits
+__device__ inline uint16_t f32_to_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(r >> 16);
+}
+__device__ inline float bf16_bits_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+__global__ void k_axis_eig(int n, double h, double *lam, double *sig) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double kk = double(k + 1);
+  double s = sinpi(kk / (2.0 * (n + 1)));          // sin(t_k / 2)
+  double c = cospi(kk / double(n + 1));            // cos(t_k)
+  double mu = h / 3.0 * (2.0 + c);
+  lam[k] = 12.0 / (h * h) * s * s / (2.0 + c);     // (6/h^2)(1 - cos)/(2 + cos)
+  sig[k] = 1.0 / sqrt(mu);
+}
+
+__global__ void k_dst_matrix(int n, int np, double *S, uint16_t *Shi, uint16_t *Slo) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int k = blockIdx.y;
+  if (j >= np) return;
+  double v = 0.0;
+  if (j < n && k < n) {
+    long long m = (long long)(k + 1) * (j + 1) % (2LL * (n + 1));   // exact angle reduction
+    v = sqrt(2.0 / (n + 1)) * sinpi(double(m) / double(n + 1));
+  }
+  S[(size_t)k * np + j] = v;
+  if (Shi) {
+    float f = float(v);
+    uint16_t hb = f32_to_bf16_bits(f);
+    float rem = float(v - double(bf16_bits_to_f32(hb)));
+    Shi[(size_t)k * np + j] = hb;
+    Slo[(size_t)k * np + j] = f32_to_bf16_bits(rem);
+  }
+}
+
+struct GaussRule {
+  int q;
+  double x[8], w[8];   // nodes / weights on [0, 1]
+};
+
+// C[m][j] = int X_m(x) phi_j(x) dx, j = 0..np-1 (zero for j >= n), by the
+// q-point Gauss rule on the two elements around interior node j (global
+// node j + 1): element [x_j, x_{j+1}] carries the hat as xi, element
+// [x_{j+1}, x_{j+2}] as 1 - xi.
+struct SpaceParams {
+  double kappa, phase, q0, q1, q2;
+};
+
+__global__ void k_load_1d(int n, int np, double lo, double h, GaussRule rule,
+                          const SpaceParams *sp, int n_terms, double *C) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int m = blockIdx.y;
+  if (j >= np || m >= n_terms) return;
+  double acc = 0.0;
+  if (j < n) {
+    SpaceParams p = sp[m];
+    for (int g = 0; g < rule.q; ++g) {
+      double xi = rule.x[g];
+      double xl = lo + h * (double(j) + xi);        // left element
+      double xr = lo + h * (double(j + 1) + xi);    // right element
+      double Xl = (p.q0 + xl * (p.q1 + xl * p.q2)) * sin(p.kappa * xl + p.phase);
+      double Xr = (p.q0 + xr * (p.q1 + xr * p.q2)) * sin(p.kappa * xr + p.phase);
+      acc += rule.w[g] * (Xl * xi + Xr * (1.0 - xi));
+    }
+    acc *= h;
+  }
+  C[(size_t)m * np + j] = acc;
+}
+
+struct PhiArgs {
+  int s;
+  double h, D;
+  double A[PE_MAX_STAGES][PE_MAX_STAGES];   // A[i][j] = a_ij (j)! : l_i = sum_j a_ij th^j
+};
+
+// phi_j(-z) for j = 1..s: Taylor series below z = 2, the recurrence
+// phi_j = (1/(j-1)! - phi_{j-1}) / z from phi_0 = e^{-z} above.
+__device__ inline void phi_all(double z, int s, double *phi) {
+  if (z < 2.0) {
+    double x = -z;
+    double fact = 1.0;   // j!
+    for (int j = 1; j <= s; ++j) {
+      fact *= j;
+      double p = 1.0;
+      for (int m = 32; m >= 1; --m) p = 1.0 + x * p / double(j + m);
+      phi[j - 1] = p / fact;
+    }
+  } else {
+    double prev = exp(-z);
+    double inv_fact = 1.0;   // 1/(j-1)!
+    for (int j = 1; j <= s; ++j) {
+      double cur = (inv_fact - prev) / z;
+      phi[j - 1] = cur;
+      prev = cur;
+      inv_fact /= j;
+    }
+  }
+}
+
+__global__ void k_phi_tables(int dim, int n0, int n1, int n2, const double *lam0,
+                             const double *lam1, const double *lam2, PhiArgs a, double *E,
+                             double *B, int64_t dof) {
+  int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= dof) return;
+  double lam;
+  if (dim == 1) {
+    lam = lam0[k];
+  } else if (dim == 2) {
+    lam = lam0[k / n1] + lam1[k % n1];
+  } else {
+    int64_t k2 = k % n2, r = k / n2;
+    lam = lam0[r / n1] + lam1[r % n1] + lam2[k2];
+  }
+  double z = a.h * a.D * lam;
+  double phi[PE_MAX_STAGES];
+  phi_all(z, a.s, phi);
+  E[k] = exp(-z);
+  for (int i = 0; i < a.s; ++i) {
+    double b = 0.0;
+    for (int j = 0; j < a.s; ++j) b += a.A[i][j] * phi[j];
+    B[(size_t)i * dof + k] = a.h * b;
+  }
+}
+
+// ------------------------------------------------------------ host helpers
+
+// Gauss-Legendre nodes/weights on [0, 1] by Newton's method on P_q.
+static GaussRule gauss_rule(int q) {
+  GaussRule r{};
+  r.q = q;
+  for (int i = 0; i < q; ++i) {
+    long double x = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (q + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = x;
+      for (int k = 2; k <= q; ++k) {
+        long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (q == 1) { p1 = x; p0 = 1; }
+      dp = q * (x * p1 - p0) / (x * x - 1);
+      long double dx = p1 / dp;
+      x -= dx;
+      if (fabsl(dx) < 1e-30L) break;
+    }
+    long double w = 2 / ((1 - x * x) * dp * dp);
+    r.x[q - 1 - i] = double((x + 1) / 2);
+    r.w[q - 1 - i] = double(w / 2);
+  }
+  return r;
+}
+
+// Lagrange coefficients a_ij (l_i(th) = sum_j a_ij th^j) times j!, in long
+// double; fails for repeated nodes.
+static pe_status lagrange_A(int s, const double *c, double A[PE_MAX_STAGES][PE_MAX_STAGES]) {
+  for (int i = 0; i < s; ++i) {
+    long double poly[PE_MAX_STAGES + 1] = {0};
+    poly[0] = 1;
+    int deg = 0;
+    long double denom = 1;
+    for (int m = 0; m < s; ++m) {
+      if (m == i) continue;
+      long double d = (long double)c[i] - c[m];
+      if (d == 0) return set_error(PE_E_ARG, "stage nodes must be distinct (c[%d] == c[%d])", i, m);
+      for (int p = deg + 1; p >= 1; --p) poly[p] = poly[p - 1] - c[m] * poly[p];
+      poly[0] = -c[m] * poly[0];
+      ++deg;
+      denom *= d;
+    }
+    long double fact = 1;
+    for (int j = 0; j < s; ++j) {
+      if (j > 0) fact *= j;
+      A[i][j] = double(poly[j] / denom * fact);
+    }
+  }
+  return PE_OK;
+}
+
+static void free_grid_tables(pe_grid g) {
+  for (int a = 0; a < PE_MAX_DIM; ++a) {
+    hipFree(g->ax[a].d_lam);
+    hipFree(g->ax[a].d_sig);
+    hipFree(g->ax[a].d_S);
+    hipFree(g->ax[a].d_Shi);
+    hipFree(g->ax[a].d_Slo);
+    hipFree(g->d_C[a]);
+  }
+  hipFree(g->d_terms);
+}
+
+pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst, hipStream_t st) {
+  GaussRule rule = gauss_rule(g->quad_q);
+  std::vector<SpaceParams> sp(std::max(n_terms, 1));
+  SpaceParams *d_sp = nullptr;
+  PE_HIP(hipMalloc(&d_sp, sizeof(SpaceParams) * sp.size()));
+  for (int a = 0; a < g->dim; ++a) {
+    for (int m = 0; m < n_terms; ++m) {
+      const pe_space_factor &f = terms[m].space[a];
+      sp[m] = SpaceParams{f.kappa, f.phase, f.poly[0], f.poly[1], f.poly[2]};
+    }
+    hipError_t e = hipMemcpyAsync(d_sp, sp.data(), sizeof(SpaceParams) * n_terms,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { hipFree(d_sp); PE_HIP(e); }
+    const Axis &ax = g->ax[a];
+    dim3 grid((ax.np + 127) / 128, n_terms);
+    if (n_terms > 0)
+      k_load_1d<<<grid, 128, 0, st>>>(ax.n, ax.np, ax.lo, ax.h, rule, d_sp, n_terms, dst[a]);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { hipFree(d_sp); PE_HIP(e); }
+  }
+  hipFree(d_sp);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+DevTerm to_dev_term(const pe_term &t) {
+  DevTerm d;
+  d.amp = t.amp;
+  d.alpha = t.time.alpha;
+  d.omega = t.time.omega;
+  d.phase = t.time.phase;
+  for (int i = 0; i < 4; ++i) d.p[i] = t.time.poly[i];
+  return d;
+}
+
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" {
+
+const char *pe_last_error(void) { return g_err.c_str(); }
+
+int64_t pe_grid_dof(pe_grid g) { return g ? g->dof : -1; }
+
+static void drop_pending(pe_grid g) {
+  for (auto &p : g->pending) {
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  g->pending.clear();
+}
+
+pe_status pe_set_timing(pe_grid g, int32_t enable) {
+  clear_error();
+  if (!g) return set_error(PE_E_ARG, "null grid");
+  if (enable) {
+    PE_HIP(hipDeviceSynchronize());
+    drop_pending(g);
+    for (auto &s : g->stats) s = pe_kernel_stat{};
+  }
+  g->timing = enable != 0;
+  return PE_OK;
+}
+
+pe_status pe_get_timing(pe_grid g, pe_kernel_stat *out) {
+  clear_error();
+  if (!g || !out) return set_error(PE_E_ARG, "null argument");
+  for (auto &p : g->pending) {
+    PE_HIP(hipEventSynchronize(p.stop));
+    float ms = 0;
+    PE_HIP(hipEventElapsedTime(&ms, p.start, p.stop));
+    pe_kernel_stat &s = g->stats[p.cls];
+    s.launches += 1;
+    s.ms += ms;
+    s.flops += p.flops;
+    s.bytes += p.bytes;
+  }
+  drop_pending(g);
+  for (int i = 0; i < PE_K_COUNT; ++i) out[i] = g->stats[i];
+  return PE_OK;
+}
+int32_t pe_grid_precision(pe_grid g) { return g ? g->precision : -1; }
+
+pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double *lo,
+                       const double *hi, double D, int32_t precision, int32_t quad_q,
+                       void *stream) {
+  clear_error();
+  if (!out || !n || !lo || !hi) return set_error(PE_E_ARG, "null argument");
+  *out = nullptr;
+  if (dim < 1 || dim > PE_MAX_DIM) return set_error(PE_E_ARG, "dim must be 1..3 (got %d)", dim);
+  if (!(D > 0) || !std::isfinite(D)) return set_error(PE_E_ARG, "D must be > 0");
+  if (precision != PE_FP64 && precision != PE_SPLIT_BF16)
+    return set_error(PE_E_ARG, "unknown precision %d", precision);
+  if (quad_q < 1 || quad_q > 8) return set_error(PE_E_ARG, "quad_q must be 1..8");
+  for (int a = 0; a < dim; ++a) {
+    if (n[a] < 1 || n[a] > 8191) return set_error(PE_E_ARG, "n[%d] must be 1..8191", a);
+    if (!(hi[a] > lo[a])) return set_error(PE_E_ARG, "hi[%d] must exceed lo[%d]", a, a);
+  }
+  hipStream_t st = as_stream(stream);
+  pe_grid g = new pe_grid_s();
+  g->dim = dim;
+  g->precision = precision;
+  g->quad_q = quad_q;
+  g->D = D;
+  g->dof = 1;
+  g->dofp = 1;
+  auto fail = [&](pe_status s) {
+    free_grid_tables(g);
+    delete g;
+    return s;
+  };
+  for (int a = 0; a < dim; ++a) {
+    Axis &ax = g->ax[a];
+    ax.n = n[a];
+    ax.np = pad_up(n[a]);
+    ax.lo = lo[a];
+    ax.hi = hi[a];
+    ax.h = (hi[a] - lo[a]) / (n[a] + 1);
+    g->dof *= ax.n;
+    g->dofp *= ax.np;
+    size_t s2 = size_t(ax.np) * ax.np;
+    hipError_t e = hipMalloc(&ax.d_lam, sizeof(double) * ax.n);
+    if (e == hipSuccess) e = hipMalloc(&ax.d_sig, sizeof(double) * ax.n);
+    if (e == hipSuccess) e = hipMalloc(&ax.d_S, sizeof(double) * s2);
+    if (e == hipSuccess && precision == PE_SPLIT_BF16) {
+      e = hipMalloc(&ax.d_Shi, sizeof(uint16_t) * s2);
+      if (e == hipSuccess) e = hipMalloc(&ax.d_Slo, sizeof(uint16_t) * s2);
+    }
+    if (e != hipSuccess)
+      return fail(set_error(PE_E_HIP, "grid table allocation failed: %s", hipGetErrorString(e)));
+    k_axis_eig<<<(ax.n + 127) / 128, 128, 0, st>>>(ax.n, ax.h, ax.d_lam, ax.d_sig);
+    k_dst_matrix<<<dim3((ax.np + 127) / 128, ax.np), 128, 0, st>>>(ax.n, ax.np, ax.d_S, ax.d_Shi,
+                                                                    ax.d_Slo);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess)
+    return fail(set_error(PE_E_HIP, "grid set-up kernels failed: %s", hipGetErrorString(e)));
+  *out = g;
+  return PE_OK;
+}
+
+void pe_free_grid(pe_grid g) {
+  if (!g) return;
+  drop_pending(g);
+  free_grid_tables(g);
+  delete g;
+}
+
+pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream) {
+  clear_error();
+  if (!g) return set_error(PE_E_ARG, "null grid");
+  if (n_terms < 0 || n_terms > PE_MAX_TERMS)
+    return set_error(PE_E_ARG, "n_terms must be 0..%d", PE_MAX_TERMS);
+  if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");
+  hipStream_t st = as_stream(stream);
+  for (int a = 0; a < PE_MAX_DIM; ++a) {
+    hipFree(g->d_C[a]);
+    g->d_C[a] = nullptr;
+  }
+  hipFree(g->d_terms);
+  g->d_terms = nullptr;
+  g->n_terms = n_terms;
+  if (n_terms == 0) return PE_OK;
+  for (int m = 0; m < n_terms; ++m) g->h_terms[m] = to_dev_term(terms[m]);
+  PE_HIP(hipMalloc(&g->d_terms, sizeof(DevTerm) * n_terms));
+  PE_HIP(hipMemcpyAsync(g->d_terms, g->h_terms, sizeof(DevTerm) * n_terms, hipMemcpyHostToDevice,
+                        st));
+  for (int a = 0; a < g->dim; ++a)
+    PE_HIP(hipMalloc(&g->d_C[a], sizeof(double) * size_t(n_terms) * g->ax[a].np));
+  return build_loads(g, n_terms, terms, g->d_C, st);
+}
+
+pe_status pe_phi_tables(pe_grid g, double h, int32_t s, const double *c, double *d_E, double *d_B,
+                        void *stream) {
+  clear_error();
+  if (!g || !c || !d_E || !d_B) return set_error(PE_E_ARG, "null argument");
+  if (!(h > 0) || !std::isfinite(h)) return set_error(PE_E_ARG, "h must be > 0");
+  if (s < 1 || s > PE_MAX_STAGES) return set_error(PE_E_ARG, "s must be 1..%d", PE_MAX_STAGES);
+  for (int i = 0; i < s; ++i)
+    if (!(c[i] >= 0.0 && c[i] <= 1.0)) return set_error(PE_E_ARG, "node c[%d] outside [0,1]", i);
+  PhiArgs a{};
+  a.s = s;
+  a.h = h;
+  a.D = g->D;
+  PE_TRY(lagrange_A(s, c, a.A));
+  hipStream_t st = as_stream(stream);
+  int64_t blocks = (g->dof + 255) / 256;
+  k_phi_tables<<<dim3(unsigned(blocks)), 256, 0, st>>>(
+      g->dim, g->ax[0].n, g->ax[1].n, g->ax[2].n, g->ax[0].d_lam, g->ax[1].d_lam,
+      g->ax[2].d_lam, a, d_E, d_B, g->dof);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+}  // extern "C"

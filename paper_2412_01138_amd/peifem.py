@@ -1,0 +1,322 @@
+"""ctypes binding of libpeifem (the C ABI declared in include/peifem.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch supplies device memory (tensor data pointers) and the
+HIP stream; if the library is missing this module raises instead of falling
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpeifem.so")
+
+PE_OK = 0
+PE_E_ARG = -1
+PE_E_HIP = -2
+PE_E_WORKSPACE = -3
+PE_E_NUMERIC = -4
+PE_E_UNSUPPORTED = -5
+PE_MAX_DIM = 3
+PE_MAX_STAGES = 8
+PE_MAX_TERMS = 64
+PE_MAX_ITERS = 64
+PE_FP64 = 0
+PE_SPLIT_BF16 = 1
+
+EXPORTS = [
+    "pe_init_grid", "pe_free_grid", "pe_set_forcing", "pe_phi_tables",
+    "pe_project_workspace_bytes", "pe_project", "pe_fine_workspace_bytes",
+    "pe_fine_propagate", "pe_coarse_workspace_bytes", "pe_coarse_sweep",
+    "pe_solve_workspace_bytes", "pe_parareal_solve", "pe_grid_dof",
+    "pe_grid_precision", "pe_last_error", "pe_set_timing", "pe_get_timing",
+]
+PE_K_TRANSFORM, PE_K_LOAD, PE_K_UPDATE, PE_K_SWEEP, PE_K_COUNT = 0, 1, 2, 3, 4
+KERNEL_CLASSES = ("transform", "load", "update", "sweep")
+
+
+class PeifemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"peifem error {status}: {msg}")
+        self.status = status
+
+
+class SpaceFactor(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("phase", ctypes.c_double),
+                ("poly", ctypes.c_double * 3)]
+
+
+class TimeFactor(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("omega", ctypes.c_double),
+                ("phase", ctypes.c_double), ("poly", ctypes.c_double * 4)]
+
+
+class Term(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("time", TimeFactor),
+                ("space", SpaceFactor * PE_MAX_DIM)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("t0", ctypes.c_double), ("T", ctypes.c_double), ("N", ctypes.c_int32),
+                ("J", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("cG", ctypes.c_double * PE_MAX_STAGES), ("cF", ctypes.c_double * PE_MAX_STAGES),
+                ("K_max", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("d_corr", ctypes.c_void_p)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("jumps", ctypes.c_double * PE_MAX_ITERS), ("ms_tables", ctypes.c_double),
+                ("ms_coarse", ctypes.c_double), ("ms_fine", ctypes.c_double),
+                ("ms_sweep", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libpeifem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.pe_init_grid.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), dp, dp, dbl, i32, i32, vp]
+    L.pe_free_grid.argtypes = [vp]
+    L.pe_free_grid.restype = None
+    L.pe_set_forcing.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
+    L.pe_phi_tables.argtypes = [vp, dbl, i32, dp, vp, vp, vp]
+    L.pe_project_workspace_bytes.argtypes = [vp]
+    L.pe_project_workspace_bytes.restype = sz
+    L.pe_project.argtypes = [vp, i32, ctypes.POINTER(Term), vp, vp, sz, vp]
+    L.pe_fine_workspace_bytes.argtypes = [vp, i64]
+    L.pe_fine_workspace_bytes.restype = sz
+    L.pe_fine_propagate.argtypes = [vp, i32, dbl, dbl, i32, i32, dp, vp, vp, vp, vp, vp, sz, vp]
+    L.pe_coarse_workspace_bytes.argtypes = [vp, i32, i32]
+    L.pe_coarse_workspace_bytes.restype = sz
+    L.pe_coarse_sweep.argtypes = [vp, i32, dbl, dbl, i32, dp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                  vp, sz, vp]
+    L.pe_solve_workspace_bytes.argtypes = [vp, ctypes.POINTER(SolveParams)]
+    L.pe_solve_workspace_bytes.restype = sz
+    L.pe_parareal_solve.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp, sz,
+                                    ctypes.POINTER(SolveReport), vp]
+    L.pe_grid_dof.argtypes = [vp]
+    L.pe_grid_dof.restype = i64
+    L.pe_grid_precision.argtypes = [vp]
+    L.pe_grid_precision.restype = i32
+    L.pe_set_timing.argtypes = [vp, i32]
+    L.pe_get_timing.argtypes = [vp, ctypes.POINTER(KernelStat)]
+    L.pe_last_error.argtypes = []
+    L.pe_last_error.restype = ctypes.c_char_p
+    for name in ("pe_init_grid", "pe_set_forcing", "pe_phi_tables", "pe_project",
+                 "pe_fine_propagate", "pe_coarse_sweep", "pe_parareal_solve", "pe_set_timing",
+                 "pe_get_timing"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != PE_OK:
+        msg = load_library().pe_last_error().decode(errors="replace")
+        raise PeifemError(status, msg)
+
+
+def _dbl_array(vals: Sequence[float]):
+    arr = (ctypes.c_double * max(1, len(vals)))(*[float(v) for v in vals])
+    return arr
+
+
+def to_c_terms(terms) -> Tuple[ctypes.Array, int]:
+    """Separable descriptors (objects with amp / time / space attributes, as
+    in the workloads module) -> a ctypes pe_term array."""
+    terms = list(terms)
+    if len(terms) > PE_MAX_TERMS:
+        raise ValueError(f"at most {PE_MAX_TERMS} terms")
+    arr = (Term * max(1, len(terms)))()
+    for i, t in enumerate(terms):
+        arr[i].amp = t.amp
+        tf = t.time
+        arr[i].time.alpha = tf.alpha
+        arr[i].time.omega = tf.omega
+        arr[i].time.phase = tf.phase
+        for j in range(4):
+            arr[i].time.poly[j] = tf.poly[j]
+        for a, sf in enumerate(t.space):
+            arr[i].space[a].kappa = sf.kappa
+            arr[i].space[a].phase = sf.phase
+            for j in range(3):
+                arr[i].space[a].poly[j] = sf.poly[j]
+        for a in range(len(t.space), PE_MAX_DIM):
+            arr[i].space[a].kappa = 0.0
+            arr[i].space[a].phase = math.pi / 2
+            arr[i].space[a].poly[0] = 1.0
+    return arr, len(terms)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Grid:
+    """A pe_grid handle plus its forcing."""
+
+    def __init__(self, n: Sequence[int], lo: Sequence[float], hi: Sequence[float], D: float,
+                 precision: str = "fp64", quad_q: int = 3, device: str = "cuda:0", stream=None):
+        import torch
+        self.L = load_library()
+        self.device = torch.device(device)
+        self.n = tuple(int(v) for v in n)
+        self.dim = len(self.n)
+        self.precision = precision
+        prec = {"fp64": PE_FP64, "split_bf16": PE_SPLIT_BF16}[precision]
+        self.state_dtype = torch.float64 if prec == PE_FP64 else torch.float32
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        nn = (ctypes.c_int32 * len(self.n))(*self.n)
+        with torch.cuda.device(self.device):
+            _check(self.L.pe_init_grid(ctypes.byref(handle), self.dim, nn, _dbl_array(lo),
+                                       _dbl_array(hi), float(D), prec, int(quad_q),
+                                       _stream(stream)))
+        self.h = handle
+        self.dof = int(self.L.pe_grid_dof(self.h))
+
+    @classmethod
+    def from_problem(cls, prob, quad_q: int = 3, device: str = "cuda:0", stream=None) -> "Grid":
+        g = cls(prob.n, prob.lo, prob.hi, prob.D, prob.precision, quad_q, device, stream)
+        g.set_forcing(prob.forcing)
+        return g
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pe_free_grid(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers --------------------------------------------------------
+    def empty_states(self, count: int):
+        import torch
+        return torch.empty((count,) + self.n, dtype=self.state_dtype, device=self.device)
+
+    def workspace(self, nbytes: int):
+        import torch
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+
+    # -- instrumentation --------------------------------------------------
+    def set_timing(self, enable: bool):
+        _check(self.L.pe_set_timing(self.h, 1 if enable else 0))
+
+    def get_timing(self) -> dict:
+        arr = (KernelStat * PE_K_COUNT)()
+        _check(self.L.pe_get_timing(self.h, arr))
+        return {name: dict(launches=int(arr[i].launches), ms=float(arr[i].ms),
+                           flops=float(arr[i].flops), bytes=float(arr[i].bytes))
+                for i, name in enumerate(KERNEL_CLASSES)}
+
+    # -- calls ----------------------------------------------------------
+    def set_forcing(self, terms):
+        arr, m = to_c_terms(terms)
+        _check(self.L.pe_set_forcing(self.h, m, arr, _stream(self.stream)))
+
+    def phi_tables(self, h: float, c: Sequence[float]):
+        import torch
+        s = len(c)
+        E = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        B = torch.empty((s,) + self.n, dtype=torch.float64, device=self.device)
+        _check(self.L.pe_phi_tables(self.h, float(h), s, _dbl_array(c), _ptr(E), _ptr(B),
+                                    _stream(self.stream)))
+        return E, B
+
+    def project(self, terms):
+        arr, m = to_c_terms(terms)
+        W = self.empty_states(1)[0]
+        nb = self.L.pe_project_workspace_bytes(self.h)
+        work = self.workspace(nb)
+        _check(self.L.pe_project(self.h, m, arr, _ptr(W), _ptr(work), nb, _stream(self.stream)))
+        return W
+
+    def fine_workspace_bytes(self, fields: int) -> int:
+        return int(self.L.pe_fine_workspace_bytes(self.h, int(fields)))
+
+    def fine_propagate(self, Uin, t0: float, dT: float, J: int, c: Sequence[float], E, B,
+                       Uout=None, work=None):
+        n_slices = Uin.shape[0]
+        if Uout is None:
+            Uout = self.empty_states(n_slices)
+        if work is None:
+            work = self.workspace(self.fine_workspace_bytes(n_slices * J * len(c)))
+        _check(self.L.pe_fine_propagate(self.h, n_slices, float(t0), float(dT), int(J), len(c),
+                                        _dbl_array(c), _ptr(E), _ptr(B), _ptr(Uin), _ptr(Uout),
+                                        _ptr(work), work.numel(), _stream(self.stream)))
+        return Uout
+
+    def coarse_sweep(self, U, t0: float, dT: float, c: Sequence[float], E, B, r, compute_r=True,
+                     corr=None, Uprev=None, Fout=None, norms=None, work=None):
+        N = U.shape[0] - 1
+        if work is None:
+            work = self.workspace(self.L.pe_coarse_workspace_bytes(self.h, N, len(c)))
+        _check(self.L.pe_coarse_sweep(self.h, N, float(t0), float(dT), len(c), _dbl_array(c),
+                                      _ptr(E), _ptr(B), 1 if compute_r else 0, _ptr(r),
+                                      _ptr(corr), _ptr(Uprev), _ptr(Fout), _ptr(U), _ptr(norms),
+                                      _ptr(work), work.numel(), _stream(self.stream)))
+        return U
+
+    def solve_params(self, t0, T, N, J, cG, cF, K_max, tol, corr=None) -> SolveParams:
+        P = SolveParams()
+        P.t0, P.T, P.N, P.J = float(t0), float(T), int(N), int(J)
+        P.p, P.q = len(cG), len(cF)
+        for i, v in enumerate(cG):
+            P.cG[i] = v
+        for i, v in enumerate(cF):
+            P.cF[i] = v
+        P.K_max, P.tol = int(K_max), float(tol)
+        P.d_corr = _ptr(corr)
+        return P
+
+    def solve_workspace_bytes(self, P: SolveParams) -> int:
+        return int(self.L.pe_solve_workspace_bytes(self.h, ctypes.byref(P)))
+
+    def parareal_solve(self, P: SolveParams, U0=None, U=None, work=None):
+        if U is None:
+            U = self.empty_states(P.N + 1)
+        if work is None:
+            work = self.workspace(self.solve_workspace_bytes(P))
+        rep = SolveReport()
+        _check(self.L.pe_parareal_solve(self.h, ctypes.byref(P), _ptr(U0), _ptr(U), _ptr(work),
+                                        work.numel(), ctypes.byref(rep), _stream(self.stream)))
+        return U, rep
+
+
+def solve_problem(prob, K_max: Optional[int] = None, tol: Optional[float] = None,
+                  corr=None, device: str = "cuda:0"):
+    """Grid + forcing + P_h u0 + Algorithm 1 for a workloads.Problem."""
+    g = Grid.from_problem(prob, device=device)
+    U0 = g.project(prob.u0) if prob.u0 else None
+    P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
+                       prob.K_max if K_max is None else K_max, prob.tol if tol is None else tol, corr)
+    U, rep = g.parareal_solve(P, U0=U0)
+    return g, U, rep
