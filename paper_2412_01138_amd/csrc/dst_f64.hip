@@ -1,161 +1,518 @@
-// Per-axis DST-I products of batches of padded fields in FP64 on the matrix
-// cores (v_mfma_f64_16x16x4f64).
+// Per-axis DST-I passes in FP64 on the matrix cores (v_mfma_f64_16x16x4f64).
 //
-// The tensor-product transform (kron_a S_a) F of a d-D field is d mode
-// products, one per axis (paper Section 2.3, closing paragraph: the mass and
-// stiffness matrices are diagonalised by one orthogonal matrix and applied
-// with tensor-product operations).  Every mode product is a row-major GEMM
-// C = A * B with A contiguous along k and B contiguous along n:
-//   last axis   : X viewed as [rows][np]   ->  C[r][k] = sum_j X[r][j] S[j][k]
-//   other axes  : X viewed as [outer][np][inner]
-//                 -> C_o[k][i] = sum_j S[k][j] X_o[j][i]   (batched over o)
-// S is symmetric, so the same matrix serves as either operand.
+// The transform (kron_a S_a) F of a d-D field is d mode products, one per
+// axis (paper Section 2.3, closing paragraph: mass and stiffness matrices are
+// diagonalised by one orthogonal matrix applied with tensor products).  Each
+// mode product is done on the even/odd fold of its axis (see pe_internal.h):
+// two dense half-size products per axis, i.e. half the multiply-adds of the
+// plain dense product, all of it on MFMA.
+//
+//   last axis  ("LAST"): X viewed as [R][np]
+//       Y[r][h*Kh + i] = sum_p fold_h(X[r][.])[p] * Sh[h][i][p]      (A = folded X, B = ShT[h])
+//   other axis ("MID"):  X viewed as [O][np][I]
+//       Y[o][h*Kh + i][t] = sum_p Sh[h][i][p] * fold_h(X[o][.][t])[p] (A = Sh[h], B = folded X)
+//
+// The first pass of a batch may generate its input instead of reading it:
+// the stage load vectors are evaluated tile by tile from the per-axis
+// quadrature tables inside the A-operand loader, so the nodal load fields
+// never travel through HBM.
+//
+// Block: 256 threads = 4 waves in 2 x 2, block tile BM x BN, wave tile
+// (BM/2) x (BN/2), k-step KB = 16, LDS double-buffered with register
+// prefetch (one barrier per k-step).  MFMA f64 16x16x4 lane layout: lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] and receives C[l/16 + 4r][l%16].
+#include <algorithm>
+
 #include "pe_internal.h"
 
 namespace pe {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Block tile BM x BN, k-step KB, 4 waves in a WAVES_M x WAVES_N arrangement.
-// LDS holds the A tile k-major (As[k][m]) and the B tile k-major (Bs[k][n])
-// so that the 16 lanes of an MFMA operand read 16 consecutive doubles.
-//
-// MFMA f64 16x16x4 lane layout: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; it receives C[l/16 + 4*r][l%16], r = 0..3.
-template <int BM, int BN, int KB, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ A, int64_t lda,
-                                                  int64_t sA, const double *__restrict__ B,
-                                                  int64_t ldb, int64_t sB, double *__restrict__ C,
-                                                  int64_t ldc, int64_t sC, int M, int N, int K,
-                                                  int tiles_n, int64_t tiles_per_batch) {
-  constexpr int WM = BM / WAVES_M;
-  constexpr int WN = BN / WAVES_N;
-  constexpr int TM = WM / 16;
-  constexpr int TN = WN / 16;
-  constexpr int APAD = 4, BPAD = 4;
-  __shared__ double As[KB][BM + APAD];
-  __shared__ double Bs[KB][BN + BPAD];
+constexpr int KB = 16;
+constexpr int NT = 256;
+constexpr int GEN_MAX_TERMS = 16;
+constexpr int GEN_MAX_CF = 4096;   // doubles of one folded half table kept in LDS
 
-  const int64_t bid = blockIdx.x;
-  const int64_t batch = bid / tiles_per_batch;
-  const int64_t t = bid - batch * tiles_per_batch;
-  const int tm = int(t / tiles_n), tn = int(t - int64_t(tm) * tiles_n);
-  A += batch * sA;
-  B += batch * sB;
-  C += batch * sC;
-  const int m0 = tm * BM, n0 = tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-  const int lr = lane & 15, lk = lane >> 4;
+template <int BM, int BN>
+struct Cfg {
+  static constexpr int TM = BM / 32;           // MFMA tiles per wave along M
+  static constexpr int TN = BN / 32;           // ... along N
+  static constexpr int B_PER = KB * BN / NT;   // B elements per thread per k-step
+  static constexpr int TPR = NT / BM;          // threads per A row
+  static constexpr int CPT = KB / TPR;         // A columns per thread
+};
 
-  d4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+template <int BM, int BN>
+struct Smem {
+  double A[2][KB][BM + 1];   // k-major A tiles
+  double B[2][KB][BN + 1];   // k-major B tiles
+};
 
-  for (int k0 = 0; k0 < K; k0 += KB) {
-    // A tile: BM rows x KB columns (contiguous in k) -> As[k][m]
+template <int BM, int BN>
+__device__ inline void mma_stage(const double (&As)[KB][BM + 1], const double (&Bs)[KB][BN + 1],
+                                 d4 (&acc)[BM / 32][BN / 32], int wm, int wn, int lr, int lk) {
+  constexpr int TM = BM / 32, TN = BN / 32;
 #pragma unroll
-    for (int e = tid; e < BM * KB; e += 256) {
-      int m = e / KB, k = e - (e / KB) * KB;
-      double v = 0.0;
-      if (m0 + m < M) v = A[int64_t(m0 + m) * lda + k0 + k];
-      As[k][m] = v;
+  for (int kk = 0; kk < KB; kk += 4) {
+    double a[TM], b[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a[i] = As[kk + lk][wm * (BM / 2) + i * 16 + lr];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) b[j] = Bs[kk + lk][wn * (BN / 2) + j * 16 + lr];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Even/odd fold of a nodal line at folded index p, split into the two raw
+// loads (issued early, in-bounds clamped indices, no dependent arithmetic)
+// and the combination (done later, when the k-step is written to LDS).
+struct FoldIdx {
+  int pa, pb;        // clamped node indices of x_p and its mirror x_{n-1-p}
+  bool has_a, has_b;
+};
+
+__device__ inline FoldIdx fold_idx(int n, int H, int h, int p) {
+  FoldIdx f;
+  f.pa = p < n ? p : n - 1;
+  f.pb = n - 1 - p > 0 ? n - 1 - p : 0;
+  f.has_a = p < H || (h == 0 && p == H && (n & 1));
+  f.has_b = p < H;
+  return f;
+}
+
+__device__ inline double fold_val(double a, double b, int h, bool has_a, bool has_b) {
+  const double av = has_a ? a : 0.0;
+  const double bv = has_b ? (h == 0 ? b : -b) : 0.0;
+  return av + bv;
+}
+
+// Blocks are handed to the 8 XCDs round-robin by block index; remapping the
+// index gives every XCD a contiguous range of logical tiles, so the tiles of
+// one field (both halves, all column tiles) share that XCD's L2.
+__device__ inline int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  if (nblocks % 8 != 0) return bid;
+  return (bid % 8) * (nblocks / 8) + bid / 8;
+}
+
+struct LastArgs {
+  const double *X;     // [R][np] nodal input (unused when generating)
+  double *Y;           // [R][np] output
+  int64_t R;
+  int np, n, H, Kh;
+  const double *ShT;   // [2][Kh][Kh]
+  int tiles_m, tiles_n;
+  // generation (GEN kernels)
+  int d;               // dimension
+  int64_t rows_per_field;
+  int np0, np1;
+  GenSrc gen;
+};
+
+// ---------------------------------------------------------------- LAST pass
+// GM = 0: read nodal input; GM > 0: generate it from at most GM forcing terms
+// (factors of the unused terms are zero).
+template <int BM, int BN, int GM>
+__global__ __launch_bounds__(NT) void k_pass_last(LastArgs a) {
+  constexpr bool GEN = GM > 0;
+  using C = Cfg<BM, BN>;
+  __shared__ Smem<BM, BN> sm;
+  extern __shared__ double cf_lds[];   // GEN: folded last-axis table of this half, [M][Kh]
+
+  int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = int(bid % a.tiles_n);
+  bid /= a.tiles_n;
+  const int h = int(bid % 2);
+  const int64_t tm = bid / 2;
+  const int64_t m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+
+  // thread -> A row ra, columns ca0 .. ca0 + CPT - 1 of each k-step
+  const int ra = t / C::TPR;
+  const int ca0 = (t % C::TPR) * C::CPT;
+  const int64_t grow = m0 + ra;
+  const bool row_ok = grow < a.R;
+
+  // GEN: the load tile of a k-step is the product rf[BM x GM] * cf[GM x KB]
+  // of the row factors rf[r][m] = coef[f][m] * prod_{a<d-1} C_a[m][j_a] and
+  // the folded last-axis table cf (kept in LDS), computed with 16x16x4
+  // MFMAs.  Each lane holds its MFMA A-operands rf[row][term] in registers.
+  constexpr int RW = BM / 4;                 // rows generated per wave
+  constexpr int RT = RW / 16 > 0 ? RW / 16 : 1;
+  constexpr int GK = GM > 0 ? GM / 4 : 1;    // MFMA k-steps over the terms
+  double rfa[RT][GK];
+  if constexpr (GEN) {
+    const int M = a.gen.M;
+    const int ncf = M * a.Kh;
+    const double *cf_src = a.gen.Cf + int64_t(h) * ncf;
+    double stage[GEN_MAX_CF / NT];
+#pragma unroll
+    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
+      int e = t + q * NT;
+      stage[q] = cf_src[e < ncf ? e : ncf - 1];
     }
-    // B tile: KB rows x BN columns (contiguous in n) -> Bs[k][n]
+    const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
+    const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
 #pragma unroll
-    for (int e = tid; e < KB * BN; e += 256) {
-      int k = e / BN, n = e - (e / BN) * BN;
-      double v = 0.0;
-      if (n0 + n < N) v = B[int64_t(k0 + k) * ldb + n0 + n];
-      Bs[k][n] = v;
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t gr0 = m0 + wave * RW + rt * 16 + lr;
+      const bool ok = gr0 < a.R;
+      const int64_t gr = ok ? gr0 : a.R - 1;
+      const int64_t f = gr / a.rows_per_field;
+      const int64_t rem = gr - f * a.rows_per_field;
+      int j0 = 0, j1 = 0;
+      if (a.d == 2) j0 = int(rem);
+      if (a.d == 3) {
+        j0 = int(rem / a.np1);
+        j1 = int(rem - int64_t(j0) * a.np1);
+      }
+#pragma unroll
+      for (int kk = 0; kk < GK; ++kk) {
+        const int m = lk + 4 * kk;
+        const int mm = m < M ? m : M - 1;
+        double v = a.gen.coef[f * M + mm];
+        if (C0) v *= C0[int64_t(mm) * a.np0 + j0];
+        if (C1) v *= C1[int64_t(mm) * a.np1 + j1];
+        rfa[rt][kk] = (m < M && ok) ? v : 0.0;
+      }
     }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < KB; kk += 4) {
-      double a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kk + lk][wm * WM + i * 16 + lr];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kk + lk][wn * WN + j * 16 + lr];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
+      int e = t + q * NT;
+      if (e < ncf) cf_lds[e] = stage[q];
     }
     __syncthreads();
   }
 
+  // prefetch registers: raw loads only; the arithmetic happens in store()
+  double ra_a[GEN ? 1 : C::CPT], ra_b[GEN ? 1 : C::CPT], rb[C::B_PER];
+  const double *xrow = GEN ? nullptr : a.X + (row_ok ? grow : a.R - 1) * a.np;
+  auto load = [&](int k0) {
+    if constexpr (!GEN) {
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+      for (int c = 0; c < C::CPT; ++c) {
+        FoldIdx fi = fold_idx(a.n, a.H, h, k0 + ca0 + c);
+        ra_a[c] = xrow[fi.pa];
+        ra_b[c] = xrow[fi.pb];
+      }
+    }
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      int col = n0 + wn * WN + j * 16 + lr;
-      if (col >= N) continue;
+    for (int q = 0; q < C::B_PER; ++q) {
+      int e = t + q * NT;
+      int k = e / BN, nl = e % BN;
+      int col = n0 + nl;
+      rb[q] = a.ShT[(int64_t(h) * a.Kh + k0 + k) * a.Kh + (col < a.Kh ? col : a.Kh - 1)];
+    }
+  };
+  auto store = [&](int buf, int k0) {
+    if constexpr (GEN) {
+      const int Mm1 = a.gen.M - 1;
+      double cfb[GK];
+#pragma unroll
+      for (int kk = 0; kk < GK; ++kk) {
+        const int term = lk + 4 * kk;
+        cfb[kk] = cf_lds[(term < Mm1 ? term : Mm1) * a.Kh + k0 + lr];
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        d4 gacc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk)
+          gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(rfa[rt][kk], cfb[kk], gacc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sm.A[buf][lr][wave * RW + rt * 16 + lk + 4 * r] = gacc[r];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < C::CPT; ++c) {
+        FoldIdx fi = fold_idx(a.n, a.H, h, k0 + ca0 + c);
+        sm.A[buf][ca0 + c][ra] = row_ok ? fold_val(ra_a[c], ra_b[c], h, fi.has_a, fi.has_b) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < C::B_PER; ++q) {
+      int e = t + q * NT;
+      int col = n0 + e % BN;
+      sm.B[buf][e / BN][e % BN] = col < a.Kh ? rb[q] : 0.0;
+    }
+  };
+
+  d4 acc[C::TM][C::TN];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = a.Kh / KB;
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load((kt + 1) * KB);
+    mma_stage<BM, BN>(sm.A[buf], sm.B[buf], acc, wm, wn, lr, lk);
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * KB);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      int col = n0 + wn * (BN / 2) + j * 16 + lr;
+      if (col >= a.Kh) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = m0 + wm * WM + i * 16 + lk + 4 * r;
-        if (row < M) C[int64_t(row) * ldc + col] = acc[i][j][r];
+        int64_t row = m0 + wm * (BM / 2) + i * 16 + lk + 4 * r;
+        if (row < a.R) a.Y[row * a.np + h * a.Kh + col] = acc[i][j][r];
       }
     }
 }
 
-constexpr int G_BM = 64, G_BN = 64, G_KB = 16;
+// ----------------------------------------------------------------- MID pass
+struct MidArgs {
+  const double *X;     // [O][np][I]
+  double *Y;           // [O][np][I]
+  int64_t O, I;
+  int np, n, H, Kh;
+  const double *Sh;    // [2][Kh][Kh]
+  int tiles_m, tiles_n;
+};
 
-static pe_status gemm_f64(const double *A, int64_t lda, int64_t sA, const double *B, int64_t ldb,
-                          int64_t sB, double *C, int64_t ldc, int64_t sC, int M, int N, int K,
-                          int64_t batch, hipStream_t st) {
-  if (K % G_KB != 0) return set_error(PE_E_ARG, "internal: K=%d not a multiple of %d", K, G_KB);
-  int tiles_m = (M + G_BM - 1) / G_BM;
-  int tiles_n = (N + G_BN - 1) / G_BN;
-  int64_t per = int64_t(tiles_m) * tiles_n;
-  if (per <= 0 || batch <= 0) return PE_OK;
-  // a grid dimension holds at most 2^32 work-items: launch batch chunks
-  const int64_t max_blocks = (int64_t(1) << 24) - 1;
-  if (per > max_blocks) return set_error(PE_E_ARG, "internal: GEMM tile count too large");
-  int64_t bchunk = max_blocks / per;
-  for (int64_t b0 = 0; b0 < batch; b0 += bchunk) {
-    int64_t nb = batch - b0 < bchunk ? batch - b0 : bchunk;
-    k_gemm_f64<G_BM, G_BN, G_KB, 2, 2><<<dim3(unsigned(per * nb)), 256, 0, st>>>(
-        A + b0 * sA, lda, sA, B + b0 * sB, ldb, sB, C + b0 * sC, ldc, sC, M, N, K, tiles_n, per);
+template <int BM, int BN>
+__global__ __launch_bounds__(NT) void k_pass_mid(MidArgs a) {
+  using C = Cfg<BM, BN>;
+  __shared__ Smem<BM, BN> sm;
+
+  int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = int(bid % a.tiles_n);
+  bid /= a.tiles_n;
+  const int tm = int(bid % a.tiles_m);
+  bid /= a.tiles_m;
+  const int h = int(bid % 2);
+  const int64_t o = bid / 2;
+  const int m0 = tm * BM;
+  const int64_t n0 = int64_t(tn) * BN;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+  const double *X = a.X + o * a.np * a.I;
+  const double *S = a.Sh + int64_t(h) * a.Kh * a.Kh;
+
+  const int ra = t / C::TPR;
+  const int ca0 = (t % C::TPR) * C::CPT;
+
+  const bool arow_ok = m0 + ra < a.Kh;
+  const double *Srow = S + int64_t(arow_ok ? m0 + ra : a.Kh - 1) * a.Kh;
+
+  // prefetch registers: raw loads only; the fold happens in store()
+  double pa[C::CPT], rxa[C::B_PER], rxb[C::B_PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < C::CPT; ++c) pa[c] = Srow[k0 + ca0 + c];
+#pragma unroll
+    for (int q = 0; q < C::B_PER; ++q) {
+      int e = t + q * NT;
+      int k = e / BN, nl = e % BN;
+      int64_t col = n0 + nl;
+      const double *x = X + (col < a.I ? col : a.I - 1);
+      FoldIdx fi = fold_idx(a.n, a.H, h, k0 + k);
+      rxa[q] = x[int64_t(fi.pa) * a.I];
+      rxb[q] = x[int64_t(fi.pb) * a.I];
+    }
+  };
+  auto store = [&](int buf, int k0) {
+#pragma unroll
+    for (int c = 0; c < C::CPT; ++c) sm.A[buf][ca0 + c][ra] = arow_ok ? pa[c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < C::B_PER; ++q) {
+      int e = t + q * NT;
+      int k = e / BN, nl = e % BN;
+      FoldIdx fi = fold_idx(a.n, a.H, h, k0 + k);
+      double v = fold_val(rxa[q], rxb[q], h, fi.has_a, fi.has_b);
+      sm.B[buf][k][nl] = (n0 + nl < a.I) ? v : 0.0;
+    }
+  };
+
+  d4 acc[C::TM][C::TN];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = a.Kh / KB;
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load((kt + 1) * KB);
+    mma_stage<BM, BN>(sm.A[buf], sm.B[buf], acc, wm, wn, lr, lk);
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * KB);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  double *Y = a.Y + o * a.np * a.I;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      int64_t col = n0 + wn * (BN / 2) + j * 16 + lr;
+      if (col >= a.I) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = m0 + wm * (BM / 2) + i * 16 + lk + 4 * r;
+        if (row < a.Kh) Y[int64_t(h * a.Kh + row) * a.I + col] = acc[i][j][r];
+      }
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+static int pick(int64_t extent) { return extent >= 128 ? 128 : (extent >= 64 ? 64 : 32); }
+
+constexpr int64_t MAX_BLOCKS = (int64_t(1) << 24) - 1;   // 2^32 work-items per grid dimension
+
+template <int BM, int BN, int GM>
+static pe_status launch_last_t(LastArgs a, size_t dyn, hipStream_t st) {
+  constexpr bool GEN = GM > 0;
+  const int64_t per_row_tile = int64_t(a.tiles_n) * 2;
+  // row chunks: whole fields when generating, at most MAX_BLOCKS blocks
+  int64_t max_tm = MAX_BLOCKS / per_row_tile;
+  if (GEN) {
+    int64_t fields_per_chunk = std::max<int64_t>(1, max_tm * BM / a.rows_per_field);
+    max_tm = fields_per_chunk * a.rows_per_field / BM;
+    if (max_tm < 1 || (fields_per_chunk * a.rows_per_field) % BM != 0)
+      max_tm = (a.R + BM - 1) / BM;   // single launch (small batches)
+  }
+  const int64_t total_tm = a.tiles_m;
+  for (int64_t tm0 = 0; tm0 < total_tm; tm0 += max_tm) {
+    int64_t ntm = std::min(max_tm, total_tm - tm0);
+    if (ntm * per_row_tile > MAX_BLOCKS) return set_error(PE_E_ARG, "internal: LAST grid too large");
+    LastArgs b = a;
+    int64_t r0 = tm0 * BM;
+    b.R = std::min<int64_t>(a.R - r0, ntm * BM);
+    b.tiles_m = int(ntm);
+    if (!GEN) b.X = a.X + r0 * a.np;
+    b.Y = a.Y + r0 * a.np;
+    if (GEN) b.gen.coef = a.gen.coef + (r0 / a.rows_per_field) * a.gen.M;
+    k_pass_last<BM, BN, GM><<<dim3(unsigned(ntm * per_row_tile)), NT, dyn, st>>>(b);
     PE_HIP(hipGetLastError());
   }
   return PE_OK;
 }
 
-// d mode products of `count` padded fields; buffers ping-pong.
-pe_status dst_fields_f64(pe_grid g, int64_t count, double *buf0, double *buf1, double **result,
-                         hipStream_t st) {
+template <int GM>
+static pe_status launch_last(LastArgs a, hipStream_t st) {
+  int bm = a.R >= 128 ? 128 : 64;
+  int bn = pick(a.Kh);
+  a.tiles_m = int((a.R + bm - 1) / bm);
+  a.tiles_n = (a.Kh + bn - 1) / bn;
+  size_t dyn = GM > 0 ? sizeof(double) * size_t(a.gen.M) * a.Kh : 0;
+#define PE_LAST(BMv, BNv) \
+  if (bm == BMv && bn == BNv) return launch_last_t<BMv, BNv, GM>(a, dyn, st);
+  PE_LAST(128, 128) PE_LAST(128, 64) PE_LAST(128, 32)
+  PE_LAST(64, 128) PE_LAST(64, 64) PE_LAST(64, 32)
+#undef PE_LAST
+  return set_error(PE_E_ARG, "internal: no LAST tile for %d x %d", bm, bn);
+}
+
+template <int BM, int BN>
+static pe_status launch_mid_t(MidArgs a, hipStream_t st) {
+  const int64_t per_o = int64_t(a.tiles_m) * a.tiles_n * 2;
+  const int64_t max_o = std::max<int64_t>(1, MAX_BLOCKS / per_o);
+  if (per_o > MAX_BLOCKS) return set_error(PE_E_ARG, "internal: MID grid too large");
+  for (int64_t o0 = 0; o0 < a.O; o0 += max_o) {
+    MidArgs b = a;
+    b.O = std::min(max_o, a.O - o0);
+    b.X = a.X + o0 * a.np * a.I;
+    b.Y = a.Y + o0 * a.np * a.I;
+    k_pass_mid<BM, BN><<<dim3(unsigned(b.O * per_o)), NT, 0, st>>>(b);
+    PE_HIP(hipGetLastError());
+  }
+  return PE_OK;
+}
+
+static pe_status launch_mid(MidArgs a, hipStream_t st) {
+  int bm = pick(a.Kh);
+  int bn = pick(a.I);
+  a.tiles_m = (a.Kh + bm - 1) / bm;
+  a.tiles_n = int((a.I + bn - 1) / bn);
+#define PE_MID(BMv, BNv) \
+  if (bm == BMv && bn == BNv) return launch_mid_t<BMv, BNv>(a, st);
+  PE_MID(128, 128) PE_MID(128, 64) PE_MID(128, 32)
+  PE_MID(64, 128) PE_MID(64, 64) PE_MID(64, 32)
+  PE_MID(32, 128) PE_MID(32, 64) PE_MID(32, 32)
+#undef PE_MID
+  return set_error(PE_E_ARG, "internal: no MID tile for %d x %d", bm, bn);
+}
+
+bool gen_supported(pe_grid g, int n_terms) {
+  const Axis &last = g->ax[g->dim - 1];
+  return n_terms >= 1 && n_terms <= GEN_MAX_TERMS && int64_t(n_terms) * last.Kh <= GEN_MAX_CF;
+}
+
+pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
+                         double **result, hipStream_t st) {
   double *in = buf0, *out = buf1;
   const int d = g->dim;
-  for (int a = d - 1; a >= 0; --a) {
-    const Axis &ax = g->ax[a];
+  for (int ax_i = d - 1; ax_i >= 0; --ax_i) {
+    const Axis &ax = g->ax[ax_i];
     int64_t inner = 1, outer = count;
-    for (int b = a + 1; b < d; ++b) inner *= g->ax[b].np;
-    for (int b = 0; b < a; ++b) outer *= g->ax[b].np;
-    // algorithmic work of this pass: 2 n_a flops per coefficient, one read
-    // and one write of every (unpadded) field
-    TimedScope ts(g, PE_K_TRANSFORM, 2.0 * double(count) * double(g->dof) * ax.n,
-                  2.0 * double(count) * double(g->dof) * sizeof(double), st);
-    if (a == d - 1) {
-      int64_t rows = outer;   // inner == 1
-      // row chunks keep the grid below 2^24 blocks of 256 work-items
-      const int64_t max_rows = int64_t(1) << 26;
-      for (int64_t r0 = 0; r0 < rows; r0 += max_rows) {
-        int64_t nr = rows - r0 < max_rows ? rows - r0 : max_rows;
-        PE_TRY(gemm_f64(in + r0 * ax.np, ax.np, 0, ax.d_S, ax.np, 0, out + r0 * ax.np, ax.np, 0,
-                        int(nr), ax.np, ax.np, 1, st));
+    for (int b = ax_i + 1; b < d; ++b) inner *= g->ax[b].np;
+    for (int b = 0; b < ax_i; ++b) outer *= g->ax[b].np;
+    // algorithmic work of the folded pass per line of n nodes:
+    // ceil(n/2)^2 + floor(n/2)^2 multiply-adds; every field read and written once
+    double lines = double(count) * double(g->dof) / ax.n;
+    double fl = 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
+    TimedScope ts(g, PE_K_TRANSFORM, fl, 2.0 * double(count) * double(g->dof) * sizeof(double), st);
+    if (ax_i == d - 1) {
+      LastArgs a{};
+      a.X = in;
+      a.Y = out;
+      a.R = outer;
+      a.np = ax.np;
+      a.n = ax.n;
+      a.H = ax.H;
+      a.Kh = ax.Kh;
+      a.ShT = ax.d_ShT;
+      a.d = d;
+      a.rows_per_field = outer / count;
+      a.np0 = g->ax[0].np;
+      a.np1 = d >= 2 ? g->ax[1].np : 1;
+      if (gen) {
+        a.gen = *gen;
+        if (gen->M <= 4)
+          PE_TRY(launch_last<4>(a, st));
+        else if (gen->M <= 8)
+          PE_TRY(launch_last<8>(a, st));
+        else if (gen->M <= 12)
+          PE_TRY(launch_last<12>(a, st));
+        else
+          PE_TRY(launch_last<16>(a, st));
+      } else {
+        PE_TRY(launch_last<0>(a, st));
       }
     } else {
-      if (inner > 0x7fffffff) return set_error(PE_E_ARG, "internal: inner extent too large");
-      PE_TRY(gemm_f64(ax.d_S, ax.np, 0, in, inner, ax.np * inner, out, inner, ax.np * inner, ax.np,
-                      int(inner), ax.np, outer, st));
+      MidArgs a{};
+      a.X = in;
+      a.Y = out;
+      a.O = outer;
+      a.I = inner;
+      a.np = ax.np;
+      a.n = ax.n;
+      a.H = ax.H;
+      a.Kh = ax.Kh;
+      a.Sh = ax.d_Sh;
+      PE_TRY(launch_mid(a, st));
     }
-    double *tmp = in;
-    in = out;
-    out = tmp;
+    std::swap(in, out);
   }
   *result = in;
   return PE_OK;

@@ -41,6 +41,7 @@ struct Dims {
   int d;
   int n[PE_MAX_DIM];
   int np[PE_MAX_DIM];
+  int Kh[PE_MAX_DIM];
 };
 
 static Dims dims_of(pe_grid g) {
@@ -49,6 +50,7 @@ static Dims dims_of(pe_grid g) {
   for (int a = 0; a < PE_MAX_DIM; ++a) {
     D.n[a] = a < g->dim ? g->ax[a].n : 1;
     D.np[a] = a < g->dim ? g->ax[a].np : 1;
+    D.Kh[a] = a < g->dim ? g->ax[a].Kh : 1;
   }
   return D;
 }
@@ -109,8 +111,8 @@ __global__ void k_update(Dims D, const double *__restrict__ sig0, const double *
     kk[a] = int(r % D.n[a]);
     r /= D.n[a];
   }
-  int64_t p = 0;
-  for (int a = 0; a < D.d; ++a) p = p * D.np[a] + kk[a];
+  int64_t p = 0;   // position of mode k in the folded mode order of every axis
+  for (int a = 0; a < D.d; ++a) p = p * D.np[a] + fold_pos(kk[a], D.Kh[a]);
   double sig = sig0[kk[0]];
   if (D.d > 1) sig *= sig1[kk[1]];
   if (D.d > 2) sig *= sig2[kk[2]];
@@ -141,7 +143,7 @@ __global__ void k_decay(const double *__restrict__ E, const TS *Uin, TS *Uout, i
   }
 }
 
-// W[k] = sigma_k G[p(k)]  (projection output, one field)
+// W[k] = sigma_k G[p(k)]  (projection output, one field; p(k) = folded position)
 template <typename TS, typename TG>
 __global__ void k_scale_compact(Dims D, const double *sig0, const double *sig1, const double *sig2,
                                 const TG *G, TS *W, int64_t dof) {
@@ -154,7 +156,7 @@ __global__ void k_scale_compact(Dims D, const double *sig0, const double *sig1, 
       r /= D.n[a];
     }
     int64_t p = 0;
-    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + kk[a];
+    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + fold_pos(kk[a], D.Kh[a]);
     double sig = sig0[kk[0]];
     if (D.d > 1) sig *= sig1[kk[1]];
     if (D.d > 2) sig *= sig2[kk[2]];
@@ -185,12 +187,12 @@ static pe_status launch_load(pe_grid g, double *const *C, int n_terms, const dou
   return PE_OK;
 }
 
-static pe_status transform(pe_grid g, int64_t count, void *work0, void *work1, void **result,
-                           hipStream_t st) {
+static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *work0, void *work1,
+                           void **result, hipStream_t st) {
   if (g->precision == PE_FP64) {
     double *r = nullptr;
-    PE_TRY(dst_fields_f64(g, count, static_cast<double *>(work0), static_cast<double *>(work1), &r,
-                          st));
+    PE_TRY(dst_fields_f64(g, count, gen, static_cast<double *>(work0), static_cast<double *>(work1),
+                          &r, st));
     *result = r;
   } else {
     float *r = nullptr;
@@ -207,8 +209,18 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
   int64_t nc = count * g->n_terms;
   k_time_coefs<<<blocks_for(nc), 256, 0, st>>>(b, g->d_terms, g->n_terms, coef, count);
   PE_HIP(hipGetLastError());
+  if (g->precision == PE_FP64 && gen_supported(g, g->n_terms)) {
+    // quadrature fused into the first transform pass
+    GenSrc gs;
+    gs.C0 = g->dim >= 2 ? g->d_C[0] : nullptr;
+    gs.C1 = g->dim >= 3 ? g->d_C[1] : nullptr;
+    gs.coef = coef;
+    gs.Cf = g->d_Cf;
+    gs.M = g->n_terms;
+    return transform(g, count, &gs, work0, work1, result, st);
+  }
   PE_TRY(launch_load(g, g->d_C, g->n_terms, coef, work0, count, st));
-  return transform(g, count, work0, work1, result, st);
+  return transform(g, count, nullptr, work0, work1, result, st);
 }
 
 static size_t per_field_bytes(pe_grid g) {
@@ -335,6 +347,7 @@ size_t pe_project_workspace_bytes(pe_grid g) {
   size_t b = 8 * 256 + 2 * field_bytes(g);
   for (int a = 0; a < g->dim; ++a) b += sizeof(double) * PE_MAX_TERMS * g->ax[a].np;
   b += sizeof(double) * PE_MAX_TERMS + sizeof(DevTerm) * PE_MAX_TERMS;
+  b += sizeof(double) * 2 * PE_MAX_TERMS * g->ax[g->dim - 1].Kh;
   return b;
 }
 
@@ -357,16 +370,29 @@ pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W
   double *C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};
   for (int a = 0; a < g->dim; ++a) C[a] = ar.take<double>(size_t(n_terms) * g->ax[a].np);
   double *coef = ar.take<double>(n_terms);
+  double *Cf = ar.take<double>(2 * size_t(n_terms) * g->ax[g->dim - 1].Kh);
   char *w0 = ar.take<char>(field_bytes(g));
   char *w1 = ar.take<char>(field_bytes(g));
-  if (!coef || !w0 || !w1) return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  if (!coef || !Cf || !w0 || !w1)
+    return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
   PE_TRY(build_loads(g, n_terms, terms, C, st));
   std::vector<double> amps(n_terms);
   for (int m = 0; m < n_terms; ++m) amps[m] = terms[m].amp;
   PE_HIP(hipMemcpyAsync(coef, amps.data(), sizeof(double) * n_terms, hipMemcpyHostToDevice, st));
-  PE_TRY(launch_load(g, C, n_terms, coef, w0, 1, st));
   void *res = nullptr;
-  PE_TRY(transform(g, 1, w0, w1, &res, st));
+  if (g->precision == PE_FP64 && gen_supported(g, n_terms)) {
+    PE_TRY(fold_table(g, C[g->dim - 1], n_terms, Cf, st));
+    GenSrc gs;
+    gs.C0 = g->dim >= 2 ? C[0] : nullptr;
+    gs.C1 = g->dim >= 3 ? C[1] : nullptr;
+    gs.coef = coef;
+    gs.Cf = Cf;
+    gs.M = n_terms;
+    PE_TRY(transform(g, 1, &gs, w0, w1, &res, st));
+  } else {
+    PE_TRY(launch_load(g, C, n_terms, coef, w0, 1, st));
+    PE_TRY(transform(g, 1, nullptr, w0, w1, &res, st));
+  }
   Dims D = dims_of(g);
   if (g->precision == PE_FP64)
     k_scale_compact<double, double><<<blocks_for(g->dof), 256, 0, st>>>(

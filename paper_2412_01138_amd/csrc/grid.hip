@@ -55,23 +55,49 @@ __global__ void k_axis_eig(int n, double h, double *lam, double *sig) {
   sig[k] = 1.0 / sqrt(mu);
 }
 
-__global__ void k_dst_matrix(int n, int np, double *S, uint16_t *Shi, uint16_t *Slo) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  int k = blockIdx.y;
-  if (j >= np) return;
+// Odd (h = 0) and even (h = 1) halves of the orthonormal DST-I matrix:
+// Sh[h][i][p] = S[2i+1+h][p+1] (1-based S), restricted to the folded inputs
+// that exist (p < H, plus the middle node p = H for the odd half when n is
+// odd); ShT is the transpose of each half.  Optional bf16 hi/lo split.
+__global__ void k_dst_half(int n, int Kh, int H, double *Sh, double *ShT, uint16_t *Shi,
+                           uint16_t *Slo) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  int h = blockIdx.z;
+  if (p >= Kh) return;
+  int k = 2 * i + 1 + h;   // 1-based mode
+  bool valid = k <= n && (p < H || (h == 0 && p == H && (n & 1)));
   double v = 0.0;
-  if (j < n && k < n) {
-    long long m = (long long)(k + 1) * (j + 1) % (2LL * (n + 1));   // exact angle reduction
+  if (valid) {
+    long long m = (long long)k * (p + 1) % (2LL * (n + 1));   // exact angle reduction
     v = sqrt(2.0 / (n + 1)) * sinpi(double(m) / double(n + 1));
   }
-  S[(size_t)k * np + j] = v;
+  size_t o = (size_t(h) * Kh + i) * Kh + p;
+  Sh[o] = v;
+  ShT[(size_t(h) * Kh + p) * Kh + i] = v;
   if (Shi) {
-    float f = float(v);
-    uint16_t hb = f32_to_bf16_bits(f);
-    float rem = float(v - double(bf16_bits_to_f32(hb)));
-    Shi[(size_t)k * np + j] = hb;
-    Slo[(size_t)k * np + j] = f32_to_bf16_bits(rem);
+    uint16_t hb = f32_to_bf16_bits(float(v));
+    Shi[o] = hb;
+    Slo[o] = f32_to_bf16_bits(float(v - double(bf16_bits_to_f32(hb))));
   }
+}
+
+// Cf[h][m][p]: the even/odd fold of the last-axis 1D load table C[m][j].
+__global__ void k_fold_table(const double *C, int np, int n, int H, int Kh, int n_terms,
+                             double *Cf) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int m = blockIdx.y;
+  if (p >= Kh || m >= n_terms) return;
+  const double *c = C + (size_t)m * np;
+  double u = 0.0, v = 0.0;
+  if (p < H) {
+    u = c[p] + c[n - 1 - p];
+    v = c[p] - c[n - 1 - p];
+  } else if (p == H && (n & 1)) {
+    u = c[p];
+  }
+  Cf[(size_t)m * Kh + p] = u;
+  Cf[(size_t(n_terms) + m) * Kh + p] = v;
 }
 
 struct GaussRule {
@@ -222,12 +248,14 @@ static void free_grid_tables(pe_grid g) {
   for (int a = 0; a < PE_MAX_DIM; ++a) {
     hipFree(g->ax[a].d_lam);
     hipFree(g->ax[a].d_sig);
-    hipFree(g->ax[a].d_S);
+    hipFree(g->ax[a].d_Sh);
+    hipFree(g->ax[a].d_ShT);
     hipFree(g->ax[a].d_Shi);
     hipFree(g->ax[a].d_Slo);
     hipFree(g->d_C[a]);
   }
   hipFree(g->d_terms);
+  hipFree(g->d_Cf);
 }
 
 pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst, hipStream_t st) {
@@ -251,6 +279,15 @@ pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst
     if (e != hipSuccess) { hipFree(d_sp); PE_HIP(e); }
   }
   hipFree(d_sp);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status fold_table(pe_grid g, const double *C_last, int n_terms, double *Cf, hipStream_t st) {
+  const Axis &ax = g->ax[g->dim - 1];
+  if (n_terms <= 0) return PE_OK;
+  k_fold_table<<<dim3((ax.Kh + 127) / 128, n_terms), 128, 0, st>>>(C_last, ax.np, ax.n, ax.H, ax.Kh,
+                                                                   n_terms, Cf);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }
@@ -345,16 +382,19 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
   for (int a = 0; a < dim; ++a) {
     Axis &ax = g->ax[a];
     ax.n = n[a];
-    ax.np = pad_up(n[a]);
+    ax.Kh = half_pad(n[a]);
+    ax.H = n[a] / 2;
+    ax.np = 2 * ax.Kh;
     ax.lo = lo[a];
     ax.hi = hi[a];
     ax.h = (hi[a] - lo[a]) / (n[a] + 1);
     g->dof *= ax.n;
     g->dofp *= ax.np;
-    size_t s2 = size_t(ax.np) * ax.np;
+    size_t s2 = size_t(2) * ax.Kh * ax.Kh;
     hipError_t e = hipMalloc(&ax.d_lam, sizeof(double) * ax.n);
     if (e == hipSuccess) e = hipMalloc(&ax.d_sig, sizeof(double) * ax.n);
-    if (e == hipSuccess) e = hipMalloc(&ax.d_S, sizeof(double) * s2);
+    if (e == hipSuccess) e = hipMalloc(&ax.d_Sh, sizeof(double) * s2);
+    if (e == hipSuccess) e = hipMalloc(&ax.d_ShT, sizeof(double) * s2);
     if (e == hipSuccess && precision == PE_SPLIT_BF16) {
       e = hipMalloc(&ax.d_Shi, sizeof(uint16_t) * s2);
       if (e == hipSuccess) e = hipMalloc(&ax.d_Slo, sizeof(uint16_t) * s2);
@@ -362,8 +402,8 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
     if (e != hipSuccess)
       return fail(set_error(PE_E_HIP, "grid table allocation failed: %s", hipGetErrorString(e)));
     k_axis_eig<<<(ax.n + 127) / 128, 128, 0, st>>>(ax.n, ax.h, ax.d_lam, ax.d_sig);
-    k_dst_matrix<<<dim3((ax.np + 127) / 128, ax.np), 128, 0, st>>>(ax.n, ax.np, ax.d_S, ax.d_Shi,
-                                                                    ax.d_Slo);
+    k_dst_half<<<dim3((ax.Kh + 127) / 128, ax.Kh, 2), 128, 0, st>>>(ax.n, ax.Kh, ax.H, ax.d_Sh,
+                                                                     ax.d_ShT, ax.d_Shi, ax.d_Slo);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -393,6 +433,8 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
   }
   hipFree(g->d_terms);
   g->d_terms = nullptr;
+  hipFree(g->d_Cf);
+  g->d_Cf = nullptr;
   g->n_terms = n_terms;
   if (n_terms == 0) return PE_OK;
   for (int m = 0; m < n_terms; ++m) g->h_terms[m] = to_dev_term(terms[m]);
@@ -401,7 +443,12 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
                         st));
   for (int a = 0; a < g->dim; ++a)
     PE_HIP(hipMalloc(&g->d_C[a], sizeof(double) * size_t(n_terms) * g->ax[a].np));
-  return build_loads(g, n_terms, terms, g->d_C, st);
+  PE_TRY(build_loads(g, n_terms, terms, g->d_C, st));
+  const Axis &last = g->ax[g->dim - 1];
+  PE_HIP(hipMalloc(&g->d_Cf, sizeof(double) * 2 * size_t(n_terms) * last.Kh));
+  PE_TRY(fold_table(g, g->d_C[g->dim - 1], n_terms, g->d_Cf, st));
+  PE_HIP(hipStreamSynchronize(st));
+  return PE_OK;
 }
 
 pe_status pe_phi_tables(pe_grid g, double h, int32_t s, const double *c, double *d_E, double *d_B,

@@ -13,21 +13,31 @@
 
 namespace pe {
 
-// Interior sizes are padded to a multiple of PAD in every device field so
-// that the transform tiles never straddle a ragged edge; padding entries are
-// kept at zero (the padded DST matrix has zero rows/columns there).
-constexpr int PAD = 32;
+// Even/odd folding of the DST-I.  With L = n + 1 and S[k][j] =
+// sqrt(2/L) sin(pi j k / L) (1-based), S[k][L - j] = (-1)^(k+1) S[k][j], so
+//   odd modes  k = 2i+1 : y = S_odd  u,  u_p = x_p + x_{n-1-p} (p < H), u_H = x_H (n odd)
+//   even modes k = 2i+2 : y = S_even v,  v_p = x_p - x_{n-1-p} (p < H)
+// (0-based node p, H = n/2 pairs): each axis transform is two dense products
+// of half size.  An axis of n nodes is stored with np = 2*Kh entries, Kh =
+// ceil(n/2) rounded up to 16: in nodal order before its transform, in
+// "folded mode order" after it (odd modes at [0, Kh), even modes at
+// [Kh, 2Kh)); unused entries are zero.
+constexpr int KHALF = 16;
 
-inline int pad_up(int n) { return (n + PAD - 1) / PAD * PAD; }
+inline int half_pad(int n) { return ((n + 1) / 2 + KHALF - 1) / KHALF * KHALF; }
+
+// position of mode index k (0-based, mode k+1) in folded mode order
+__host__ __device__ inline int fold_pos(int k, int Kh) { return (k & 1) ? Kh + (k >> 1) : (k >> 1); }
 
 struct Axis {
-  int n = 0, np = 0;
+  int n = 0, np = 0, Kh = 0, H = 0;
   double lo = 0, hi = 0, h = 0;
   double *d_lam = nullptr;       // [n]   generalized eigenvalues lambda_a(k)
   double *d_sig = nullptr;       // [n]   1/sqrt(mu_a(k)), mu_a the mass eigenvalues
-  double *d_S = nullptr;         // [np][np] orthonormal DST-I, zero padded
-  uint16_t *d_Shi = nullptr;     // [np][np] bf16 high part of S
-  uint16_t *d_Slo = nullptr;     // [np][np] bf16 low part of S (S - hi)
+  double *d_Sh = nullptr;        // [2][Kh][Kh]  Sh[h][i][p]: odd (h=0) / even (h=1) half of S
+  double *d_ShT = nullptr;       // [2][Kh][Kh]  transposed halves, ShT[h][p][i]
+  uint16_t *d_Shi = nullptr;     // [2][Kh][Kh] bf16 high part of Sh
+  uint16_t *d_Slo = nullptr;     // [2][Kh][Kh] bf16 low part of Sh (Sh - hi)
 };
 
 struct PendingTiming {
@@ -56,6 +66,7 @@ struct pe_grid_s {
   pe::DevTerm h_terms[PE_MAX_TERMS];
   pe::DevTerm *d_terms = nullptr;        // [n_terms]
   double *d_C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][np_a] 1D loads
+  double *d_Cf = nullptr;        // [2][n_terms][Kh_last] folded last-axis loads
   // kernel timing (benchmark instrumentation)
   bool timing = false;
   std::vector<pe::PendingTiming> pending;
@@ -121,12 +132,32 @@ struct FieldBatch {
 pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
                              double *coef, void **result, hipStream_t st);
 
-// Per-axis DST products of `count` padded fields (FP64): in -> out, d passes
-// ping-ponging between the two buffers; *result receives the final buffer.
-pe_status dst_fields_f64(pe_grid g, int64_t count, double *buf0, double *buf1, double **result,
-                         hipStream_t st);
+// Load-vector generation inside the first (last-axis) transform pass: the
+// nodal load of field f at node (j_0, .., j_{d-1}) is
+//   sum_m coef[f][m] prod_{a<d-1} C_a[m][j_a] * C_{d-1}[m][j_{d-1}],
+// and the pass consumes its fold along the last axis, built from the folded
+// last-axis table Cf[h][m][p].
+struct GenSrc {
+  const double *C0 = nullptr;     // [M][np_0]  (d >= 2)
+  const double *C1 = nullptr;     // [M][np_1]  (d == 3)
+  const double *coef = nullptr;   // [count][M]
+  const double *Cf = nullptr;     // [2][M][Kh_last]
+  int M = 0;
+};
+
+// Per-axis DST products of `count` padded fields (FP64).  With gen != null
+// the first pass generates its input (buf0 is then not read); otherwise
+// buf0 holds nodal fields.  Passes ping-pong between buf0 and buf1;
+// *result receives the buffer holding the coefficients (folded mode order).
+pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
+                         double **result, hipStream_t st);
 pe_status dst_fields_split(pe_grid g, int64_t count, float *buf0, float *buf1, float **result,
                            hipStream_t st);
+// true when the fused generation path can take n_terms terms
+bool gen_supported(pe_grid g, int n_terms);
+// Cf[h][m][p] from C[m][j] of the last axis (device)
+pe_status fold_table(pe_grid g, const double *C_last, int n_terms, double *Cf, hipStream_t st);
+pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst, hipStream_t st);
 
 // bytes of one padded stage field
 size_t field_bytes(pe_grid g);

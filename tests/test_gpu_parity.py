@@ -107,6 +107,20 @@ def test_fine_propagate(dim, n, N, J, s):
     assert rel(out, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("dim,n", [(1, (45,)), (2, (37, 70)), (3, (9, 20, 33))])
+def test_fine_propagate_many_terms(dim, n):
+    """More forcing terms than the fused quadrature path takes: the load
+    vectors are written by the separate quadrature kernel instead."""
+    pe = _peifem()
+    prob, d, Uin = _fine_case(dim, n, 2, 3, 3, seed=7, n_modes=20)
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    out = g.fine_propagate(_dev(Uin), prob.t0, prob.dT, prob.J, prob.c_fine, E, B).cpu().numpy()
+    tab = d.tables(prob.dt, prob.c_fine)
+    ref = np.stack([fine_prop(d, Uin[k], prob.t0 + k * prob.dT, tab, prob.J) for k in range(2)])
+    assert rel(out, ref) <= 1e-12
+
+
 def test_fine_propagate_batching_is_exact():
     """Smaller workspaces split the fields into more batches; every field is
     still computed by the same kernels, so the output is bitwise identical."""
