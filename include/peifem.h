@@ -222,11 +222,12 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
  * waits for the recorded events and fills out[0..PE_K_COUNT-1].  Errors:
  * PE_E_ARG, PE_E_HIP. */
 typedef enum {
-  PE_K_TRANSFORM = 0, /* per-axis DST products (matrix cores) */
-  PE_K_LOAD = 1,      /* stage load-vector quadrature */
-  PE_K_UPDATE = 2,    /* fused diagonal update */
-  PE_K_SWEEP = 3,     /* coarse / correction sweep with norms */
-  PE_K_COUNT = 4
+  PE_K_DST_LAST = 0,  /* last-axis DST pass (with fused load quadrature) */
+  PE_K_DST_MID = 1,   /* DST pass along any other axis */
+  PE_K_LOAD = 2,      /* separate stage load-vector quadrature */
+  PE_K_UPDATE = 3,    /* fused diagonal update */
+  PE_K_SWEEP = 4,     /* coarse / correction sweep with norms */
+  PE_K_COUNT = 5
 } pe_kernel_class;
 
 typedef struct {

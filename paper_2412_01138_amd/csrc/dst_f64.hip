@@ -471,7 +471,8 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
     // ceil(n/2)^2 + floor(n/2)^2 multiply-adds; every field read and written once
     double lines = double(count) * double(g->dof) / ax.n;
     double fl = 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
-    TimedScope ts(g, PE_K_TRANSFORM, fl, 2.0 * double(count) * double(g->dof) * sizeof(double), st);
+    TimedScope ts(g, ax_i == d - 1 ? PE_K_DST_LAST : PE_K_DST_MID, fl,
+                  2.0 * double(count) * double(g->dof) * sizeof(double), st);
     if (ax_i == d - 1) {
       LastArgs a{};
       a.X = in;

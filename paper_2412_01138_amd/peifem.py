@@ -36,8 +36,8 @@ EXPORTS = [
     "pe_solve_workspace_bytes", "pe_parareal_solve", "pe_grid_dof",
     "pe_grid_precision", "pe_last_error", "pe_set_timing", "pe_get_timing",
 ]
-PE_K_TRANSFORM, PE_K_LOAD, PE_K_UPDATE, PE_K_SWEEP, PE_K_COUNT = 0, 1, 2, 3, 4
-KERNEL_CLASSES = ("transform", "load", "update", "sweep")
+PE_K_DST_LAST, PE_K_DST_MID, PE_K_LOAD, PE_K_UPDATE, PE_K_SWEEP, PE_K_COUNT = 0, 1, 2, 3, 4, 5
+KERNEL_CLASSES = ("dst_last", "dst_mid", "load", "update", "sweep")
 
 
 class PeifemError(RuntimeError):
