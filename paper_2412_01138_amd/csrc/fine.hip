@@ -196,8 +196,16 @@ static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *wo
     *result = r;
   } else {
     float *r = nullptr;
-    PE_TRY(dst_fields_split(g, count, static_cast<float *>(work0), static_cast<float *>(work1), &r,
-                            st));
+    GenSrcF gf;
+    if (gen) {
+      gf.C0 = gen->C0;
+      gf.C1 = gen->C1;
+      gf.coef = gen->coef;
+      gf.Cf = gen->Cf;
+      gf.M = gen->M;
+    }
+    PE_TRY(dst_fields_split(g, count, gen ? &gf : nullptr, static_cast<float *>(work0),
+                            static_cast<float *>(work1), &r, st));
     *result = r;
   }
   return PE_OK;
@@ -209,7 +217,9 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
   int64_t nc = count * g->n_terms;
   k_time_coefs<<<blocks_for(nc), 256, 0, st>>>(b, g->d_terms, g->n_terms, coef, count);
   PE_HIP(hipGetLastError());
-  if (g->precision == PE_FP64 && gen_supported(g, g->n_terms)) {
+  const bool fused = g->precision == PE_FP64 ? gen_supported(g, g->n_terms)
+                                              : gen_supported_split(g, g->n_terms);
+  if (fused) {
     // quadrature fused into the first transform pass
     GenSrc gs;
     gs.C0 = g->dim >= 2 ? g->d_C[0] : nullptr;
@@ -380,7 +390,9 @@ pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W
   for (int m = 0; m < n_terms; ++m) amps[m] = terms[m].amp;
   PE_HIP(hipMemcpyAsync(coef, amps.data(), sizeof(double) * n_terms, hipMemcpyHostToDevice, st));
   void *res = nullptr;
-  if (g->precision == PE_FP64 && gen_supported(g, n_terms)) {
+  const bool fused = g->precision == PE_FP64 ? gen_supported(g, n_terms)
+                                              : gen_supported_split(g, n_terms);
+  if (fused) {
     PE_TRY(fold_table(g, C[g->dim - 1], n_terms, Cf, st));
     GenSrc gs;
     gs.C0 = g->dim >= 2 ? C[0] : nullptr;

@@ -19,10 +19,10 @@ namespace pe {
 //   even modes k = 2i+2 : y = S_even v,  v_p = x_p - x_{n-1-p} (p < H)
 // (0-based node p, H = n/2 pairs): each axis transform is two dense products
 // of half size.  An axis of n nodes is stored with np = 2*Kh entries, Kh =
-// ceil(n/2) rounded up to 16: in nodal order before its transform, in
+// ceil(n/2) rounded up to 32: in nodal order before its transform, in
 // "folded mode order" after it (odd modes at [0, Kh), even modes at
 // [Kh, 2Kh)); unused entries are zero.
-constexpr int KHALF = 16;
+constexpr int KHALF = 32;
 
 inline int half_pad(int n) { return ((n + 1) / 2 + KHALF - 1) / KHALF * KHALF; }
 
@@ -151,8 +151,18 @@ struct GenSrc {
 // *result receives the buffer holding the coefficients (folded mode order).
 pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
                          double **result, hipStream_t st);
-pe_status dst_fields_split(pe_grid g, int64_t count, float *buf0, float *buf1, float **result,
-                           hipStream_t st);
+// Split-bf16 variant (fp32 fields): each pass contracts the contiguous axis
+// and writes it outermost, so after d passes the axes are back in order.
+struct GenSrcF {
+  const double *C0 = nullptr;     // [M][np_0]  (d >= 2)
+  const double *C1 = nullptr;     // [M][np_1]  (d == 3)
+  const double *coef = nullptr;   // [count][M]
+  const double *Cf = nullptr;     // [2][M][Kh_last]
+  int M = 0;
+};
+pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,
+                           float **result, hipStream_t st);
+bool gen_supported_split(pe_grid g, int n_terms);
 // true when the fused generation path can take n_terms terms
 bool gen_supported(pe_grid g, int n_terms);
 // Cf[h][m][p] from C[m][j] of the last axis (device)

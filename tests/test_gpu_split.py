@@ -1,0 +1,81 @@
+"""Split-bf16 path (fp32 states, bf16 hi/lo transform products with fp32
+accumulation, FP64 tables and norms) vs the FP64 CPU oracle.
+
+Tolerance: 2e-5 relative L2 against the FP64 oracle, the stated target for
+the split-bf16 path.  Each product keeps about 16 significant bits of each
+operand pair (hi*hi + hi*lo + lo*hi), i.e. ~2^-17 relative per term; over
+d <= 3 axes of accumulation plus the fp32 state this stays near 1e-5.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.eife import Discretization
+from oracle.parareal import fine_prop, parareal
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SPLIT_TOL = 2e-5
+
+
+def _peifem():
+    from paper_2412_01138_amd import peifem
+    return peifem
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def _dev32(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
+
+
+@pytest.mark.parametrize("dim,n", [(1, (63,)), (2, (37, 70)), (3, (9, 33, 20)), (3, (31, 63, 17))])
+def test_split_project(dim, n):
+    pe = _peifem()
+    prob = wl.tiny_problem(dim, n, seed=12, u0_modes=3, precision="split_bf16")
+    g = pe.Grid.from_problem(prob)
+    W = g.project(prob.u0)
+    assert W.dtype == torch.float32
+    ref = Discretization(prob).initial()
+    assert rel(W.cpu().numpy(), ref) <= SPLIT_TOL
+
+
+@pytest.mark.parametrize("dim,n,N,J,s,modes", [
+    (1, (100,), 3, 5, 3, 4),
+    (2, (37, 70), 3, 4, 3, 4),
+    (2, (64, 64), 2, 3, 4, 20),
+    (3, (9, 33, 20), 2, 3, 4, 5),
+    (3, (31, 63, 17), 2, 2, 3, 40),       # more terms than the fused path takes
+])
+def test_split_fine_propagate(dim, n, N, J, s, modes):
+    pe = _peifem()
+    prob = wl.tiny_problem(dim, n, seed=3, s=s, N=N, J=J, n_modes=modes, T=0.9,
+                           precision="split_bf16")
+    d = Discretization(prob)
+    rng = np.random.default_rng(4)
+    Uin = rng.normal(size=(N,) + prob.n)
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    out = g.fine_propagate(_dev32(Uin), prob.t0, prob.dT, J, prob.c_fine, E, B)
+    assert out.dtype == torch.float32
+    tab = d.tables(prob.dt, prob.c_fine)
+    ref = np.stack([fine_prop(d, Uin[k], prob.t0 + k * prob.dT, tab, J) for k in range(N)])
+    assert rel(out.cpu().numpy(), ref) <= SPLIT_TOL
+
+
+@pytest.mark.parametrize("dim,n", [(2, (45, 38)), (3, (15, 31, 9))])
+def test_split_parareal(dim, n):
+    pe = _peifem()
+    prob = wl.tiny_problem(dim, n, seed=51, N=5, J=4, s=3, u0_modes=2, precision="split_bf16")
+    g, U, rep = pe.solve_problem(prob, K_max=6, tol=1e-5)
+    d = Discretization(prob)
+    r = parareal(d, d.initial(), prob.t0, prob.N, prob.J, d.tables(prob.dt, prob.c_fine),
+                 d.tables(prob.dT, prob.c_coarse), K_max=6, tol=1e-5)
+    assert rep.converged and rep.iterations == r.iterations
+    assert rel(U.cpu().numpy(), r.iterates[-1]) <= SPLIT_TOL
