@@ -173,6 +173,79 @@ pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int
                           const void *d_Fout, void *d_U, double *d_norms, void *d_work,
                           size_t work_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned coarse correction (an addition to the paper's method).
+ *
+ * G~(v; T_n) = E_G v + r_n + delta_n with, for every mode k,
+ *     delta_{n,k} = sigma * dT * NN(x),   sigma = max_s |g_s|,
+ *     g_s = ghat_k(T_n + s dT / 7), s = 0..7   (spectral forcing samples),
+ *     x = [ln(z)/8, e^{-z}, phi_1(-z), 2 phi_2(-z), g_0/sigma .. g_7/sigma],
+ *     z = D lambda_k dT,  phi_1(-z) = (1 - e^{-z})/z,  phi_2(-z) = (z - 1 + e^{-z})/z^2,
+ * (delta = 0 where sigma = 0).  NN: 12 -> 64 -> 64 -> 64 (GELU x Phi(x)) -> 1,
+ * bf16 weights, fp32 accumulation, on the matrix cores.  Because delta does
+ * not depend on the state, the Parareal iterates k >= 1 are unchanged by it
+ * (Algorithm 1 with eq. (2.8) still converges to the fine solution): the
+ * correction only moves U^(0) and hence the iteration count.
+ * Parameters: PE_MLP_PARAMS floats, W1[12][64], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], w4[64], b4[1] (W[in][out]).  A pe_mlp holds fp32
+ * master weights, their bf16 copies and Adam moments on the device.
+ * Training rows: target (R_n - r_n)_k / (sigma dT), R_n = F^J(0), r_n = G(0)
+ * on slice n (the state-independent fine/coarse forcing responses). */
+#define PE_MLP_INPUTS 12
+#define PE_MLP_WIDTH 64
+#define PE_MLP_PARAMS 9217
+#define PE_MLP_SAMPLES 8
+
+typedef struct pe_mlp_s *pe_mlp;
+
+/* Create a network from PE_MLP_PARAMS host floats (its initial weights;
+ * Adam moments start at zero).  Synchronises.  Errors: PE_E_ARG, PE_E_HIP. */
+pe_status pe_mlp_create(pe_mlp *out, const float *h_params, void *stream);
+void pe_mlp_free(pe_mlp m);
+/* Copy the fp32 master weights to / from host memory (synchronises). */
+pe_status pe_mlp_get_params(pe_mlp m, float *h_params, void *stream);
+pe_status pe_mlp_set_params(pe_mlp m, const float *h_params, void *stream);
+
+/* y[r] = NN(x[r]) for rows of ready-made inputs d_x[rows][12] (fp32). */
+pe_status pe_mlp_forward(pe_mlp m, int64_t rows, const float *d_x, float *d_y, void *stream);
+
+/* One training step on a batch: mean squared error of NN(x) against d_t.
+ * Gradients are accumulated in a fixed order (bitwise repeatable).
+ * d_loss (nullable, 1 float) receives the batch loss, d_grad (nullable,
+ * PE_MLP_PARAMS floats) the batch gradient; apply != 0 then takes one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step count kept in
+ * the handle) with learning rate lr.  rows: 1 .. 2^24. */
+pe_status pe_mlp_train_step(pe_mlp m, int64_t rows, const float *d_x, const float *d_t, float lr,
+                            int32_t apply, float *d_loss, float *d_grad, void *stream);
+
+/* Spectral forcing samples for every slice: d_samples[8n + s][k] =
+ * ghat_k(t0 + n dT + s dT/7) (grid state dtype), n = 0..N-1, computed like
+ * the fine stages (quadrature + transform).  Needs
+ * pe_learned_samples_workspace_bytes(g, N) of d_work (smaller workspaces
+ * are used a few slices at a time). */
+size_t pe_learned_samples_workspace_bytes(pe_grid g, int32_t n_slices);
+pe_status pe_learned_samples(pe_grid g, int32_t n_slices, double t0, double dT, void *d_samples,
+                             void *d_work, size_t work_bytes, void *stream);
+
+/* Training rows from one solve's responses: for every (n, k) with
+ * sigma > rel_thresh * max sigma, write x (12 floats) and the target
+ * (R - r)_{n,k} / (sigma dT) to d_x / d_t, in (n, k) order, at most max_rows;
+ * *h_count (host) receives the number of qualifying rows (it can exceed
+ * max_rows: only the first max_rows are written).  d_R, d_r: [N][DOF].
+ * Needs pe_learned_rows_workspace_bytes(g, N) of d_work.  Synchronises. */
+size_t pe_learned_rows_workspace_bytes(pe_grid g, int32_t n_slices);
+pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double dT, const void *d_samples,
+                          const void *d_R, const void *d_r, double rel_thresh, float *d_x,
+                          float *d_t, int64_t max_rows, int64_t *h_count, void *d_work,
+                          size_t work_bytes, void *stream);
+
+/* delta_n for every slice and mode into d_corr[N][DOF] (state dtype).  If
+ * the network produces a non-finite value anywhere, d_corr is zeroed (plain
+ * coarse step) and *h_fallback (host, nullable) is set to 1.  Synchronises. */
+pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double dT,
+                                const void *d_samples, void *d_corr, int32_t *h_fallback,
+                                void *stream);
+
 /* Parareal driver (paper Algorithm 1).  Stopping rule (the paper leaves it
  * open): after iteration k the relative jump
  *     ||U^(k) - U^(k-1)|| / ||U^(k)||    (all slice ends n = 1..N, FP64)
@@ -189,7 +262,9 @@ typedef struct {
   double cF[PE_MAX_STAGES];
   int32_t K_max;               /* 1..PE_MAX_ITERS fine passes at most */
   double tol;
-  const void *d_corr;          /* nullable [N][DOF] learned coarse correction */
+  const void *d_corr;          /* nullable [N][DOF] additive coarse correction */
+  pe_mlp mlp;                  /* nullable: learned correction computed inside the
+                                  solve (ignored when d_corr is given) */
 } pe_solve_params;
 
 typedef struct {
@@ -201,10 +276,13 @@ typedef struct {
   double ms_fine;              /* all fine passes */
   double ms_sweep;             /* correction sweeps + norms */
   double ms_total;
+  double ms_learned;           /* forcing samples + network (inside ms_coarse) */
+  int32_t fallback;            /* 1: the network output was non-finite, plain G used */
 } pe_solve_report;
 
 /* d_U0: initial state (one state, nullable = zero); d_U receives the last
- * iterate [N+1][DOF].  Needs pe_solve_workspace_bytes(g, P) of d_work.
+ * iterate [N+1][DOF].  Needs pe_solve_workspace_bytes(g, P) of d_work (with
+ * P->mlp set this includes the forcing samples and the correction).
  * Synchronises `stream` once per iteration (one 16-byte read-back of the
  * jump norms).  Errors: PE_E_ARG, PE_E_WORKSPACE, PE_E_HIP, PE_E_NUMERIC
  * (non-finite jump). */

@@ -1,0 +1,309 @@
+// Learned coarse correction: forcing samples, training rows, correction.
+//
+// The network input of slice n and mode k uses the spectral forcing at the
+// eight times T_n + s dT / 7 (s = 0..7).  They are produced like the stage
+// fields of a fine pass (quadrature of the load vector + per-axis transform)
+// and stored in natural mode order.  Training rows pair those inputs with
+// the target (R_n - r_n)_k / (sigma dT), R_n = F^J(0) and r_n = G(0) of the
+// same slice; rows whose samples vanish carry no information and are skipped
+// (ordered, deterministic compaction).
+#include <algorithm>
+#include <cmath>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
+                             double *coef, void **result, hipStream_t st);
+
+// out[f][k] = sigma_k G[f][pos(k)] for `count` fields (natural mode order)
+template <typename T>
+__global__ void k_compact_fields(int d, int n0, int n1, int n2, int np0, int np1, int np2, int Kh0,
+                                 int Kh1, int Kh2, const double *s0, const double *s1,
+                                 const double *s2, const T *G, T *out, int64_t count, int64_t dof,
+                                 int64_t dofp) {
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < count * dof;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t f = idx / dof, k = idx - f * dof;
+    int kk[3] = {0, 0, 0};
+    int64_t r = k;
+    const int n[3] = {n0, n1, n2};
+    for (int a = d - 1; a >= 0; --a) {
+      kk[a] = int(r % n[a]);
+      r /= n[a];
+    }
+    const int np[3] = {np0, np1, np2}, Kh[3] = {Kh0, Kh1, Kh2};
+    int64_t p = 0;
+    for (int a = 0; a < d; ++a) p = p * np[a] + fold_pos(kk[a], Kh[a]);
+    double sg = s0[kk[0]];
+    if (d > 1) sg *= s1[kk[1]];
+    if (d > 2) sg *= s2[kk[2]];
+    out[idx] = T(sg * double(G[f * dofp + p]));
+  }
+}
+
+static unsigned nblk(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return unsigned(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+static size_t sample_field_bytes(pe_grid g) {
+  return 2 * field_bytes(g) + sizeof(double) * size_t(std::max(g->n_terms, 1));
+}
+
+// ------------------------------------------------------------ training rows
+struct RowsArgs {
+  int d, n0, n1, n2;
+  const double *lam0, *lam1, *lam2;
+  double D, dT;
+  const void *samples, *R, *r;
+  int fp64;
+  int64_t dof, total;
+};
+
+__device__ inline double rows_sigma(const RowsArgs &a, int64_t row, double *g) {
+  const int64_t n = row / a.dof, k = row - n * a.dof;
+  double sg = 0.0;
+  for (int q = 0; q < PE_MLP_SAMPLES; ++q) {
+    const int64_t o = (n * PE_MLP_SAMPLES + q) * a.dof + k;
+    g[q] = a.fp64 ? static_cast<const double *>(a.samples)[o]
+                  : double(static_cast<const float *>(a.samples)[o]);
+    sg = fmax(sg, fabs(g[q]));
+  }
+  return sg;
+}
+
+__global__ void k_rows_max(RowsArgs a, double *part) {
+  __shared__ double sm[256];
+  double mx = 0.0;
+  for (int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x; row < a.total;
+       row += int64_t(gridDim.x) * 256) {
+    double g[PE_MLP_SAMPLES];
+    mx = fmax(mx, rows_sigma(a, row, g));
+  }
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_rows_max_final(const double *part, int nb, double *out) {
+  double mx = 0.0;
+  for (int i = 0; i < nb; ++i) mx = fmax(mx, part[i]);
+  *out = mx;
+}
+
+// counts[b] = qualifying rows of block b (one row per thread)
+__global__ void k_rows_count(RowsArgs a, const double *smax, double rel, int *counts) {
+  __shared__ int sc[4];
+  const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  bool q = false;
+  if (row < a.total) {
+    double g[PE_MLP_SAMPLES];
+    const double sg = rows_sigma(a, row, g);
+    q = sg > rel * (*smax) && sg > 0.0;
+  }
+  const unsigned long long bal = __ballot(q);
+  if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = sc[0] + sc[1] + sc[2] + sc[3];
+}
+
+// exclusive scan of the block counts (one block, in order); total -> *total
+__global__ void k_rows_scan(const int *counts, int nb, int64_t *offsets, int64_t *total) {
+  if (threadIdx.x != 0) return;
+  int64_t acc = 0;
+  for (int i = 0; i < nb; ++i) {
+    offsets[i] = acc;
+    acc += counts[i];
+  }
+  *total = acc;
+}
+
+__device__ inline void zfeat(double z, float *f) {
+  const double e = exp(-z);
+  double p1, p2;
+  if (z < 1e-3) {
+    p1 = 1.0 - z / 2 + z * z / 6 - z * z * z / 24;
+    p2 = 0.5 - z / 6 + z * z / 24 - z * z * z / 120;
+  } else {
+    p1 = -expm1(-z) / z;
+    p2 = (z - 1.0 + e) / (z * z);
+  }
+  f[0] = float(log(z) / 8.0);
+  f[1] = float(e);
+  f[2] = float(p1);
+  f[3] = float(2.0 * p2);
+}
+
+__global__ void k_rows_write(RowsArgs a, const double *smax, double rel, const int64_t *offsets,
+                             int64_t max_rows, float *x, float *tg) {
+  __shared__ int sc[4];
+  const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  bool q = false;
+  double g[PE_MLP_SAMPLES];
+  double sg = 0.0;
+  if (row < a.total) {
+    sg = rows_sigma(a, row, g);
+    q = sg > rel * (*smax) && sg > 0.0;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(q);
+  if (lane == 0) sc[wave] = __popcll(bal);
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += sc[w];
+  const int local = before + __popcll(bal & ((1ull << lane) - 1ull));
+  const int64_t pos = offsets[blockIdx.x] + local;
+  if (!q || pos >= max_rows) return;
+  const int64_t n = row / a.dof, k = row - n * a.dof;
+  double lam;
+  if (a.d == 1) {
+    lam = a.lam0[k];
+  } else if (a.d == 2) {
+    lam = a.lam0[k / a.n1] + a.lam1[k % a.n1];
+  } else {
+    const int64_t k2 = k % a.n2, rr = k / a.n2;
+    lam = a.lam0[rr / a.n1] + a.lam1[rr % a.n1] + a.lam2[k2];
+  }
+  float f[PE_MLP_INPUTS];
+  zfeat(a.D * lam * a.dT, f);
+  for (int s = 0; s < PE_MLP_SAMPLES; ++s) f[4 + s] = float(g[s] / sg);
+  for (int i = 0; i < PE_MLP_INPUTS; ++i) x[pos * PE_MLP_INPUTS + i] = f[i];
+  const double Rv = a.fp64 ? static_cast<const double *>(a.R)[row]
+                           : double(static_cast<const float *>(a.R)[row]);
+  const double rv = a.fp64 ? static_cast<const double *>(a.r)[row]
+                           : double(static_cast<const float *>(a.r)[row]);
+  tg[pos] = float((Rv - rv) / (sg * a.dT));
+}
+
+static RowsArgs rows_args(pe_grid g, int N, double dT, const void *S, const void *R, const void *r) {
+  RowsArgs a{};
+  a.d = g->dim;
+  a.n0 = g->ax[0].n;
+  a.n1 = g->dim > 1 ? g->ax[1].n : 1;
+  a.n2 = g->dim > 2 ? g->ax[2].n : 1;
+  a.lam0 = g->ax[0].d_lam;
+  a.lam1 = g->ax[1].d_lam;
+  a.lam2 = g->ax[2].d_lam;
+  a.D = g->D;
+  a.dT = dT;
+  a.samples = S;
+  a.R = R;
+  a.r = r;
+  a.fp64 = g->precision == PE_FP64;
+  a.dof = g->dof;
+  a.total = int64_t(N) * g->dof;
+  return a;
+}
+
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" {
+
+size_t pe_learned_samples_workspace_bytes(pe_grid g, int32_t n_slices) {
+  if (!g || n_slices < 1) return 0;
+  return 4 * 256 + size_t(n_slices) * PE_MLP_SAMPLES * sample_field_bytes(g);
+}
+
+pe_status pe_learned_samples(pe_grid g, int32_t n_slices, double t0, double dT, void *d_samples,
+                             void *d_work, size_t work_bytes, void *stream) {
+  clear_error();
+  if (!g || !d_samples) return set_error(PE_E_ARG, "null argument");
+  if (n_slices < 1 || !(dT > 0)) return set_error(PE_E_ARG, "bad n_slices / dT");
+  hipStream_t st = as_stream(stream);
+  const size_t sb = g->precision == PE_FP64 ? sizeof(double) : sizeof(float);
+  if (g->n_terms == 0) {
+    PE_HIP(hipMemsetAsync(d_samples, 0, sb * size_t(n_slices) * PE_MLP_SAMPLES * g->dof, st));
+    return PE_OK;
+  }
+  if (!d_work) return set_error(PE_E_ARG, "null workspace");
+  const size_t per_slice = PE_MLP_SAMPLES * sample_field_bytes(g);
+  if (work_bytes < 4 * 256 + per_slice)
+    return set_error(PE_E_WORKSPACE, "workspace %zu B below %zu B", work_bytes, 4 * 256 + per_slice);
+  const int nb = int(std::min<size_t>(n_slices, (work_bytes - 4 * 256) / per_slice));
+  Arena ar(d_work, work_bytes);
+  double *coef = ar.take<double>(size_t(nb) * PE_MLP_SAMPLES * std::max(g->n_terms, 1));
+  char *w0 = ar.take<char>(size_t(nb) * PE_MLP_SAMPLES * field_bytes(g));
+  char *w1 = ar.take<char>(size_t(nb) * PE_MLP_SAMPLES * field_bytes(g));
+  if (!coef || !w0 || !w1) return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  for (int n0 = 0; n0 < n_slices; n0 += nb) {
+    FieldBatch b{};
+    b.n0 = n0;
+    b.nslices = std::min(nb, n_slices - n0);
+    b.j0 = 0;
+    b.jc = 1;
+    b.s = PE_MLP_SAMPLES;
+    b.t0 = t0;
+    b.dT = dT;
+    b.dt = dT;
+    for (int q = 0; q < PE_MLP_SAMPLES; ++q) b.c[q] = double(q) / 7.0;
+    void *res = nullptr;
+    PE_TRY(load_and_transform(g, b, w0, w1, coef, &res, st));
+    const int64_t count = b.count();
+    char *dst = static_cast<char *>(d_samples) + size_t(n0) * PE_MLP_SAMPLES * g->dof * sb;
+    const Axis *A = g->ax;
+    if (g->precision == PE_FP64)
+      k_compact_fields<double><<<nblk(count * g->dof), 256, 0, st>>>(
+          g->dim, A[0].n, A[1].n, A[2].n, A[0].np, A[1].np, A[2].np, A[0].Kh, A[1].Kh, A[2].Kh,
+          A[0].d_sig, A[1].d_sig, A[2].d_sig, static_cast<const double *>(res),
+          reinterpret_cast<double *>(dst), count, g->dof, g->dofp);
+    else
+      k_compact_fields<float><<<nblk(count * g->dof), 256, 0, st>>>(
+          g->dim, A[0].n, A[1].n, A[2].n, A[0].np, A[1].np, A[2].np, A[0].Kh, A[1].Kh, A[2].Kh,
+          A[0].d_sig, A[1].d_sig, A[2].d_sig, static_cast<const float *>(res),
+          reinterpret_cast<float *>(dst), count, g->dof, g->dofp);
+    PE_HIP(hipGetLastError());
+  }
+  return PE_OK;
+}
+
+size_t pe_learned_rows_workspace_bytes(pe_grid g, int32_t n_slices) {
+  if (!g || n_slices < 1) return 0;
+  const int64_t blocks = (int64_t(n_slices) * g->dof + 255) / 256;
+  return 8 * 256 + size_t(blocks) * (sizeof(int) + sizeof(int64_t)) + sizeof(double) * 65538 +
+         sizeof(int64_t);
+}
+
+pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double dT, const void *d_samples,
+                          const void *d_R, const void *d_r, double rel_thresh, float *d_x,
+                          float *d_t, int64_t max_rows, int64_t *h_count, void *d_work,
+                          size_t work_bytes, void *stream) {
+  clear_error();
+  if (!g || !d_samples || !d_R || !d_r || !d_x || !d_t || !h_count || !d_work)
+    return set_error(PE_E_ARG, "null argument");
+  if (n_slices < 1 || !(dT > 0) || max_rows < 0 || !(rel_thresh >= 0))
+    return set_error(PE_E_ARG, "bad arguments");
+  if (work_bytes < pe_learned_rows_workspace_bytes(g, n_slices))
+    return set_error(PE_E_WORKSPACE, "workspace too small");
+  hipStream_t st = as_stream(stream);
+  RowsArgs a = rows_args(g, n_slices, dT, d_samples, d_R, d_r);
+  const int64_t blocks = (a.total + 255) / 256;
+  if (blocks > (int64_t(1) << 24)) return set_error(PE_E_ARG, "too many rows");
+  Arena ar(d_work, work_bytes);
+  int *counts = ar.take<int>(blocks);
+  int64_t *offsets = ar.take<int64_t>(blocks);
+  const unsigned mb = nblk(a.total);
+  double *part = ar.take<double>(mb);
+  double *smax = ar.take<double>(1);
+  int64_t *total = ar.take<int64_t>(1);
+  if (!counts || !offsets || !part || !smax || !total)
+    return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  k_rows_max<<<mb, 256, 0, st>>>(a, part);
+  k_rows_max_final<<<1, 1, 0, st>>>(part, int(mb), smax);
+  k_rows_count<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, counts);
+  k_rows_scan<<<1, 64, 0, st>>>(counts, int(blocks), offsets, total);
+  k_rows_write<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, offsets, max_rows, d_x, d_t);
+  PE_HIP(hipGetLastError());
+  PE_HIP(hipMemcpyAsync(h_count, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  PE_HIP(hipStreamSynchronize(st));
+  return PE_OK;
+}
+
+}  // extern "C"

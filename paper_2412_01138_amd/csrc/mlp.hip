@@ -1,0 +1,642 @@
+// Per-mode coarse-correction network: bf16 weights, fp32 accumulation, all
+// layer products on the matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// NN: x[12] -> 64 -> 64 -> 64 (GELU: x Phi(x)) -> 1 (linear), parameters
+// W1[12][64] b1 W2[64][64] b2 W3[64][64] b3 w4[64] b4 (W[in][out]).
+//
+// Kernels work on tiles of 64 rows; each of the 4 waves owns 16 rows, so the
+// forward layers need no cross-wave exchange.  Layer l is C = A W: the MFMA
+// A operand is the activation tile (row-major, k contiguous), the B operand
+// the transposed weights Wt[out][in] (k contiguous).  Backward:
+//   dA_{l-1} = dZ_l W_l^T  (B operand = W_l[in][out] row-major),
+//   dW_l    += A_{l-1}^T dZ_l (A operand = A^T[in][row], B = dZ^T[out][row]),
+// with the row sums of the weight gradients taken on the matrix cores; every
+// block writes its partial gradient, a second kernel adds the partials in a
+// fixed order (bitwise-repeatable gradients).
+#include <cmath>
+#include <cstring>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int NIN = PE_MLP_INPUTS;   // 12
+constexpr int KIN = 32;              // padded input width (MFMA k-step)
+constexpr int WD = PE_MLP_WIDTH;     // 64
+constexpr int NP = PE_MLP_PARAMS;    // 9217
+constexpr int OW1 = 0, OB1 = OW1 + NIN * WD, OW2 = OB1 + WD, OB2 = OW2 + WD * WD, OW3 = OB2 + WD,
+              OB3 = OW3 + WD * WD, OW4 = OB3 + WD, OB4 = OW4 + WD;
+static_assert(OB4 + 1 == NP, "parameter layout");
+
+// packed bf16 weights (global): W1t[64][32], W2t[64][64], W3t[64][64],
+// W2n[64][64], W3n[64][64], w4[64]
+constexpr int PW1T = 0, PW2T = PW1T + WD * KIN, PW3T = PW2T + WD * WD, PW2N = PW3T + WD * WD,
+              PW3N = PW2N + WD * WD, PW4 = PW3N + WD * WD, PTOT = PW4 + WD;
+
+constexpr int LD1 = KIN + 8;   // LDS row stride (bf16) of 32-wide tiles
+constexpr int LD2 = WD + 8;    // ... of 64-wide tiles (16-byte pad: conflict-free b128 reads)
+constexpr int ROWS = 64;       // rows per tile
+constexpr int MNT = 256;
+constexpr int MAX_TRAIN_BLOCKS = 256;
+
+}  // namespace pe
+
+struct pe_mlp_s {
+  float *master = nullptr;     // [NP]
+  float *m = nullptr, *v = nullptr;
+  uint16_t *packed = nullptr;  // [PTOT] bf16
+  float *partials = nullptr;   // [MAX_TRAIN_BLOCKS][NP]
+  float *loss_part = nullptr;  // [MAX_TRAIN_BLOCKS]
+  float *grad = nullptr;       // [NP]
+  int *flag = nullptr;         // non-finite output seen by the last correction
+  int64_t step = 0;
+};
+
+namespace pe {
+
+__device__ inline uint16_t f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+__device__ inline float gelu(float x) { return 0.5f * x * erfcf(-x * 0.70710678118654752f); }
+__device__ inline float gelu_d(float x) {
+  return 0.5f * erfcf(-x * 0.70710678118654752f) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// One wave: C[16][64] += A[16][K] * Bt[64][K]^T.  Lane (lr, lk) receives
+// rows 4*lk + r, columns 16*j + lr.
+template <int K>
+__device__ inline void mm16x64(const uint16_t *A, int lda, const uint16_t *Bt, int ldb,
+                               f4 (&acc)[4], int lr, int lk) {
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + lr * lda + k0 + lk * 8);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt + (j * 16 + lr) * ldb + k0 + lk * 8);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+    }
+  }
+}
+
+struct WeightsLds {
+  uint16_t W1t[WD][LD1];
+  uint16_t W2t[WD][LD2], W3t[WD][LD2];
+  uint16_t W2n[WD][LD2], W3n[WD][LD2];
+  float w4[WD], b1[WD], b2[WD], b3[WD], b4;
+};
+
+__device__ inline void load_weights(WeightsLds &w, const uint16_t *packed, const float *master) {
+  for (int e = threadIdx.x; e < WD * KIN; e += MNT) w.W1t[e / KIN][e % KIN] = packed[PW1T + e];
+  for (int e = threadIdx.x; e < WD * WD; e += MNT) {
+    const int r = e / WD, c = e % WD;
+    w.W2t[r][c] = packed[PW2T + e];
+    w.W3t[r][c] = packed[PW3T + e];
+    w.W2n[r][c] = packed[PW2N + e];
+    w.W3n[r][c] = packed[PW3N + e];
+  }
+  for (int e = threadIdx.x; e < WD; e += MNT) {
+    w.w4[e] = bf2f(packed[PW4 + e]);
+    w.b1[e] = master[OB1 + e];
+    w.b2[e] = master[OB2 + e];
+    w.b3[e] = master[OB3 + e];
+  }
+  if (threadIdx.x == 0) w.b4 = master[OB4];
+}
+
+// z-features in FP64: [ln z / 8, e^{-z}, phi_1(-z), 2 phi_2(-z)]
+__device__ inline void z_features(double z, float *f) {
+  const double e = exp(-z);
+  double p1, p2;
+  if (z < 1e-3) {
+    p1 = 1.0 - z / 2 + z * z / 6 - z * z * z / 24;
+    p2 = 0.5 - z / 6 + z * z / 24 - z * z * z / 120;
+  } else {
+    p1 = -expm1(-z) / z;
+    p2 = (z - 1.0 + e) / (z * z);
+  }
+  f[0] = float(log(z) / 8.0);
+  f[1] = float(e);
+  f[2] = float(p1);
+  f[3] = float(2.0 * p2);
+}
+
+struct MlpRowSrc {
+  // rows from ready-made inputs
+  const float *x;          // [rows][12] or null
+  // rows from forcing samples (learned correction)
+  int dim, n0, n1, n2;
+  const double *lam0, *lam1, *lam2;
+  double D, dT;
+  const void *samples;     // [8N][DOF] state dtype
+  int fp64;
+  int64_t dof;
+};
+
+// Feature row -> x[12] (fp32) and sigma; returns false when the row is empty.
+__device__ inline void row_features(const MlpRowSrc &s, int64_t row, float *x, double &sigma) {
+  if (s.x) {
+    for (int i = 0; i < NIN; ++i) x[i] = s.x[row * NIN + i];
+    sigma = 1.0;
+    return;
+  }
+  const int64_t n = row / s.dof, k = row - n * s.dof;
+  double lam;
+  if (s.dim == 1) {
+    lam = s.lam0[k];
+  } else if (s.dim == 2) {
+    lam = s.lam0[k / s.n1] + s.lam1[k % s.n1];
+  } else {
+    const int64_t k2 = k % s.n2, r = k / s.n2;
+    lam = s.lam0[r / s.n1] + s.lam1[r % s.n1] + s.lam2[k2];
+  }
+  double g[PE_MLP_SAMPLES];
+  double sg = 0.0;
+  for (int q = 0; q < PE_MLP_SAMPLES; ++q) {
+    const int64_t o = (n * PE_MLP_SAMPLES + q) * s.dof + k;
+    g[q] = s.fp64 ? static_cast<const double *>(s.samples)[o]
+                  : double(static_cast<const float *>(s.samples)[o]);
+    sg = fmax(sg, fabs(g[q]));
+  }
+  z_features(s.D * lam * s.dT, x);
+  const double inv = sg > 0.0 ? 1.0 / sg : 0.0;
+  for (int q = 0; q < PE_MLP_SAMPLES; ++q) x[4 + q] = float(g[q] * inv);
+  sigma = sg;
+}
+
+// --------------------------------------------------------------- inference
+struct InferOut {
+  float *y;          // [rows] network output (pe_mlp_forward) or null
+  void *corr;        // [rows] delta (learned correction) or null
+  int fp64;
+  int *bad;          // set to 1 on a non-finite output
+};
+
+__global__ __launch_bounds__(MNT) void k_mlp_infer(const uint16_t *packed, const float *master,
+                                                   MlpRowSrc src, int64_t rows, InferOut out) {
+  __shared__ WeightsLds w;
+  __shared__ uint16_t X[ROWS][LD1];
+  __shared__ uint16_t H1[ROWS][LD2], H2[ROWS][LD2];
+  __shared__ float sig[ROWS];
+  load_weights(w, packed, master);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+  const int64_t ntiles = (rows + ROWS - 1) / ROWS;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();
+    if (t < ROWS) {
+      const int64_t row = tile * ROWS + t;
+      float x[NIN];
+      double sg = 0.0;
+      if (row < rows) {
+        row_features(src, row, x, sg);
+      } else {
+        for (int i = 0; i < NIN; ++i) x[i] = 0.f;
+      }
+      for (int i = 0; i < KIN; ++i) X[t][i] = i < NIN ? f2bf(x[i]) : uint16_t(0);
+      sig[t] = float(sg);
+    }
+    __syncthreads();
+    const int r0 = wave * 16;
+    f4 acc[4];
+    // layer 1
+    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    mm16x64<KIN>(&X[r0][0], LD1, &w.W1t[0][0], LD1, acc, lr, lk);
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r)
+        H1[r0 + 4 * lk + r][j * 16 + lr] = f2bf(gelu(acc[j][r] + w.b1[j * 16 + lr]));
+    __syncthreads();
+    // layer 2
+    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    mm16x64<WD>(&H1[r0][0], LD2, &w.W2t[0][0], LD2, acc, lr, lk);
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r)
+        H2[r0 + 4 * lk + r][j * 16 + lr] = f2bf(gelu(acc[j][r] + w.b2[j * 16 + lr]));
+    __syncthreads();
+    // layer 3 + linear output
+    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    mm16x64<WD>(&H2[r0][0], LD2, &w.W3t[0][0], LD2, acc, lr, lk);
+    float ys[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) ys[r] += gelu(acc[j][r] + w.b3[j * 16 + lr]) * w.w4[j * 16 + lr];
+    for (int r = 0; r < 4; ++r)
+      for (int off = 8; off >= 1; off >>= 1) ys[r] += __shfl_xor(ys[r], off, 16);
+    if (lr == 0) {
+      for (int r = 0; r < 4; ++r) {
+        const int lrow = r0 + 4 * lk + r;
+        const int64_t row = tile * ROWS + lrow;
+        if (row >= rows) continue;
+        const float y = ys[r] + w.b4;
+        if (out.y) out.y[row] = y;
+        if (out.corr) {
+          const double sg = sig[lrow];
+          double dlt = sg > 0.0 ? sg * src.dT * double(y) : 0.0;
+          if (!isfinite(dlt)) {
+            *out.bad = 1;
+            dlt = 0.0;
+          }
+          if (out.fp64)
+            static_cast<double *>(out.corr)[row] = dlt;
+          else
+            static_cast<float *>(out.corr)[row] = float(dlt);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- training
+struct TrainLds {
+  WeightsLds w;
+  uint16_t X[ROWS][LD1];
+  uint16_t XT[KIN][LD2];
+  uint16_t H1[ROWS][LD2], H2[ROWS][LD2];
+  uint16_t H1T[WD][LD2], H2T[WD][LD2];
+  uint16_t dZ3[ROWS][LD2], dZ2[ROWS][LD2];
+  uint16_t dZ3T[WD][LD2], dZ2T[WD][LD2], dZ1T[WD][LD2];
+  float tgt[ROWS];
+  float red[4][4][WD];   // [wave][quantity][col] bias/w4 partials
+  float lossw[4];
+};
+
+__global__ __launch_bounds__(MNT) void k_mlp_train(const uint16_t *packed, const float *master,
+                                                   const float *x, const float *tg, int64_t rows,
+                                                   int64_t rows_per_block, float *partials,
+                                                   float *loss_part) {
+  extern __shared__ char smem_raw[];
+  TrainLds &s = *reinterpret_cast<TrainLds *>(smem_raw);
+  load_weights(s.w, packed, master);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+  const int r0 = wave * 16;
+  const int64_t beg = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t end = beg + rows_per_block < rows ? beg + rows_per_block : rows;
+  const float inv_b = 2.0f / float(rows);
+
+  f4 gW1[4], gW2[4], gW3[4];
+  for (int j = 0; j < 4; ++j) gW1[j] = gW2[j] = gW3[j] = f4{0.f, 0.f, 0.f, 0.f};
+  float gb1[4] = {0, 0, 0, 0}, gb2[4] = {0, 0, 0, 0}, gb3[4] = {0, 0, 0, 0}, gw4[4] = {0, 0, 0, 0};
+  float gb4 = 0.f, lsum = 0.f;
+
+  for (int64_t base = beg; base < end; base += ROWS) {
+    __syncthreads();
+    if (t < ROWS) {
+      const int64_t row = base + t;
+      const bool ok = row < end;
+      for (int i = 0; i < KIN; ++i) {
+        const float v = (ok && i < NIN) ? x[row * NIN + i] : 0.f;
+        const uint16_t b = f2bf(v);
+        s.X[t][i] = b;
+        s.XT[i][t] = b;
+      }
+      s.tgt[t] = ok ? tg[row] : 0.f;
+    }
+    __syncthreads();
+    f4 z1[4], z2[4], z3[4];
+    for (int j = 0; j < 4; ++j) z1[j] = z2[j] = z3[j] = f4{0.f, 0.f, 0.f, 0.f};
+    mm16x64<KIN>(&s.X[r0][0], LD1, &s.w.W1t[0][0], LD1, z1, lr, lk);
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) {
+        z1[j][r] += s.w.b1[j * 16 + lr];
+        const uint16_t h = f2bf(gelu(z1[j][r]));
+        s.H1[r0 + 4 * lk + r][j * 16 + lr] = h;
+        s.H1T[j * 16 + lr][r0 + 4 * lk + r] = h;
+      }
+    __syncthreads();
+    mm16x64<WD>(&s.H1[r0][0], LD2, &s.w.W2t[0][0], LD2, z2, lr, lk);
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) {
+        z2[j][r] += s.w.b2[j * 16 + lr];
+        const uint16_t h = f2bf(gelu(z2[j][r]));
+        s.H2[r0 + 4 * lk + r][j * 16 + lr] = h;
+        s.H2T[j * 16 + lr][r0 + 4 * lk + r] = h;
+      }
+    __syncthreads();
+    mm16x64<WD>(&s.H2[r0][0], LD2, &s.w.W3t[0][0], LD2, z3, lr, lk);
+    float h3[4][4];
+    float ys[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) {
+        z3[j][r] += s.w.b3[j * 16 + lr];
+        h3[j][r] = gelu(z3[j][r]);
+        ys[r] += h3[j][r] * s.w.w4[j * 16 + lr];
+      }
+    for (int r = 0; r < 4; ++r)
+      for (int off = 8; off >= 1; off >>= 1) ys[r] += __shfl_xor(ys[r], off, 16);
+    // dL/dy per row (zero for padding rows)
+    float dy[4];
+    for (int r = 0; r < 4; ++r) {
+      const int lrow = r0 + 4 * lk + r;
+      const bool ok = base + lrow < end;
+      const float res = ok ? (ys[r] + s.w.b4 - s.tgt[lrow]) : 0.f;
+      dy[r] = res * inv_b;
+      if (lr == 0) lsum += res * res;
+    }
+    // output layer and dZ3
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) {
+        gw4[j] += h3[j][r] * dy[r];
+        const float d = dy[r] * s.w.w4[j * 16 + lr] * gelu_d(z3[j][r]);
+        gb3[j] += d;
+        const uint16_t b = f2bf(d);
+        s.dZ3[r0 + 4 * lk + r][j * 16 + lr] = b;
+        s.dZ3T[j * 16 + lr][r0 + 4 * lk + r] = b;
+      }
+    if (lr == 0)
+      for (int r = 0; r < 4; ++r) gb4 += dy[r];
+    __syncthreads();
+    // dW3 += H2^T dZ3 (rows of dW3 = in features 16*wave..)
+    mm16x64<ROWS>(&s.H2T[r0][0], LD2, &s.dZ3T[0][0], LD2, gW3, lr, lk);
+    // dA2 = dZ3 W3^T, dZ2
+    f4 da[4];
+    for (int j = 0; j < 4; ++j) da[j] = f4{0.f, 0.f, 0.f, 0.f};
+    mm16x64<WD>(&s.dZ3[r0][0], LD2, &s.w.W3n[0][0], LD2, da, lr, lk);
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const float d = da[j][r] * gelu_d(z2[j][r]);
+        gb2[j] += d;
+        const uint16_t b = f2bf(d);
+        s.dZ2[r0 + 4 * lk + r][j * 16 + lr] = b;
+        s.dZ2T[j * 16 + lr][r0 + 4 * lk + r] = b;
+      }
+    __syncthreads();
+    mm16x64<ROWS>(&s.H1T[r0][0], LD2, &s.dZ2T[0][0], LD2, gW2, lr, lk);
+    for (int j = 0; j < 4; ++j) da[j] = f4{0.f, 0.f, 0.f, 0.f};
+    mm16x64<WD>(&s.dZ2[r0][0], LD2, &s.w.W2n[0][0], LD2, da, lr, lk);
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const float d = da[j][r] * gelu_d(z1[j][r]);
+        gb1[j] += d;
+        s.dZ1T[j * 16 + lr][r0 + 4 * lk + r] = f2bf(d);
+      }
+    __syncthreads();
+    if (wave < KIN / 16) mm16x64<ROWS>(&s.XT[r0][0], LD2, &s.dZ1T[0][0], LD2, gW1, lr, lk);
+  }
+
+  // per-block partial gradient, flat parameter layout
+  float *P = partials + int64_t(blockIdx.x) * NP;
+  for (int j = 0; j < 4; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const int in = r0 + 4 * lk + r, out = j * 16 + lr;
+      P[OW3 + in * WD + out] = gW3[j][r];
+      P[OW2 + in * WD + out] = gW2[j][r];
+      if (wave < KIN / 16 && in < NIN) P[OW1 + in * WD + out] = gW1[j][r];
+    }
+  // column sums over the 4 row groups of a wave, then over the waves, in order
+  float vals[4][4];
+  for (int j = 0; j < 4; ++j) {
+    vals[0][j] = gb1[j];
+    vals[1][j] = gb2[j];
+    vals[2][j] = gb3[j];
+    vals[3][j] = gw4[j];
+  }
+  for (int q = 0; q < 4; ++q)
+    for (int j = 0; j < 4; ++j) {
+      float v = vals[q][j];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      vals[q][j] = v;
+    }
+  __syncthreads();
+  if (lk == 0)
+    for (int q = 0; q < 4; ++q)
+      for (int j = 0; j < 4; ++j) s.red[wave][q][j * 16 + lr] = vals[q][j];
+  // loss and b4 partials: lanes with lr == 0 hold them; sum in a fixed order
+  float lb[2] = {lsum, gb4};
+  for (int q = 0; q < 2; ++q) {
+    lb[q] += __shfl_xor(lb[q], 16, 64);
+    lb[q] += __shfl_xor(lb[q], 32, 64);
+  }
+  if (lane == 0) s.lossw[wave] = lb[0];
+  __shared__ float b4w[4];
+  if (lane == 0) b4w[wave] = lb[1];
+  __syncthreads();
+  if (t < WD) {
+    for (int q = 0; q < 4; ++q) {
+      const float v = ((s.red[0][q][t] + s.red[1][q][t]) + s.red[2][q][t]) + s.red[3][q][t];
+      const int off = q == 0 ? OB1 : q == 1 ? OB2 : q == 2 ? OB3 : OW4;
+      P[off + t] = v;
+    }
+  }
+  if (t == 0) {
+    P[OB4] = ((b4w[0] + b4w[1]) + b4w[2]) + b4w[3];
+    loss_part[blockIdx.x] = ((s.lossw[0] + s.lossw[1]) + s.lossw[2]) + s.lossw[3];
+  }
+}
+
+__global__ void k_mlp_reduce(const float *partials, const float *loss_part, int nb, int64_t rows,
+                             float *grad, float *loss_out, float *grad_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < NP) {
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += partials[int64_t(b) * NP + p];
+    grad[p] = s;
+    if (grad_out) grad_out[p] = s;
+  }
+  if (p == 0 && loss_out) {
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += loss_part[b];
+    *loss_out = s / float(rows);
+  }
+}
+
+__global__ void k_mlp_adam(float *w, float *m, float *v, const float *g, float lr, float c1,
+                           float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NP) return;
+  const float gi = g[p];
+  const float mi = 0.9f * m[p] + 0.1f * gi;
+  const float vi = 0.999f * v[p] + 0.001f * gi * gi;
+  m[p] = mi;
+  v[p] = vi;
+  w[p] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// bf16 copies of the weights in the kernels' layouts
+__global__ void k_mlp_pack(const float *w, uint16_t *pk) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < WD * KIN) {
+    const int o = e / KIN, i = e % KIN;
+    pk[PW1T + e] = i < NIN ? f2bf(w[OW1 + i * WD + o]) : uint16_t(0);
+  }
+  if (e < WD * WD) {
+    const int a = e / WD, b = e % WD;
+    pk[PW2T + e] = f2bf(w[OW2 + b * WD + a]);   // W2t[out=a][in=b]
+    pk[PW3T + e] = f2bf(w[OW3 + b * WD + a]);
+    pk[PW2N + e] = f2bf(w[OW2 + e]);            // W2n[in][out]
+    pk[PW3N + e] = f2bf(w[OW3 + e]);
+  }
+  if (e < WD) pk[PW4 + e] = f2bf(w[OW4 + e]);
+}
+
+static pe_status repack(pe_mlp m, hipStream_t st) {
+  k_mlp_pack<<<(WD * WD + 255) / 256, 256, 0, st>>>(m->master, m->packed);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status mlp_infer(pe_mlp m, const MlpRowSrc &src, int64_t rows, const InferOut &out,
+                    hipStream_t st) {
+  int64_t tiles = (rows + ROWS - 1) / ROWS;
+  unsigned blocks = unsigned(tiles < 4096 ? (tiles > 0 ? tiles : 1) : 4096);
+  k_mlp_infer<<<blocks, MNT, 0, st>>>(m->packed, m->master, src, rows, out);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" {
+
+pe_status pe_mlp_create(pe_mlp *out, const float *h_params, void *stream) {
+  clear_error();
+  if (!out || !h_params) return set_error(PE_E_ARG, "null argument");
+  *out = nullptr;
+  hipStream_t st = as_stream(stream);
+  pe_mlp m = new pe_mlp_s();
+  hipError_t e = hipMalloc(&m->master, sizeof(float) * NP);
+  if (e == hipSuccess) e = hipMalloc(&m->m, sizeof(float) * NP);
+  if (e == hipSuccess) e = hipMalloc(&m->v, sizeof(float) * NP);
+  if (e == hipSuccess) e = hipMalloc(&m->packed, sizeof(uint16_t) * PTOT);
+  if (e == hipSuccess) e = hipMalloc(&m->partials, sizeof(float) * NP * MAX_TRAIN_BLOCKS);
+  if (e == hipSuccess) e = hipMalloc(&m->loss_part, sizeof(float) * MAX_TRAIN_BLOCKS);
+  if (e == hipSuccess) e = hipMalloc(&m->grad, sizeof(float) * NP);
+  if (e == hipSuccess) e = hipMalloc(&m->flag, sizeof(int));
+  if (e == hipSuccess) e = hipMemcpyAsync(m->master, h_params, sizeof(float) * NP,
+                                          hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, sizeof(float) * NP, st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, sizeof(float) * NP, st);
+  if (e == hipSuccess) {
+    k_mlp_pack<<<(WD * WD + 255) / 256, 256, 0, st>>>(m->master, m->packed);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    pe_mlp_free(m);
+    return set_error(PE_E_HIP, "network allocation failed: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return PE_OK;
+}
+
+void pe_mlp_free(pe_mlp m) {
+  if (!m) return;
+  hipFree(m->master);
+  hipFree(m->m);
+  hipFree(m->v);
+  hipFree(m->packed);
+  hipFree(m->partials);
+  hipFree(m->loss_part);
+  hipFree(m->grad);
+  hipFree(m->flag);
+  delete m;
+}
+
+pe_status pe_mlp_get_params(pe_mlp m, float *h_params, void *stream) {
+  clear_error();
+  if (!m || !h_params) return set_error(PE_E_ARG, "null argument");
+  hipStream_t st = as_stream(stream);
+  PE_HIP(hipMemcpyAsync(h_params, m->master, sizeof(float) * NP, hipMemcpyDeviceToHost, st));
+  PE_HIP(hipStreamSynchronize(st));
+  return PE_OK;
+}
+
+pe_status pe_mlp_set_params(pe_mlp m, const float *h_params, void *stream) {
+  clear_error();
+  if (!m || !h_params) return set_error(PE_E_ARG, "null argument");
+  hipStream_t st = as_stream(stream);
+  PE_HIP(hipMemcpyAsync(m->master, h_params, sizeof(float) * NP, hipMemcpyHostToDevice, st));
+  PE_TRY(repack(m, st));
+  PE_HIP(hipStreamSynchronize(st));
+  return PE_OK;
+}
+
+pe_status pe_mlp_forward(pe_mlp m, int64_t rows, const float *d_x, float *d_y, void *stream) {
+  clear_error();
+  if (!m || !d_x || !d_y) return set_error(PE_E_ARG, "null argument");
+  if (rows < 1) return set_error(PE_E_ARG, "rows must be >= 1");
+  MlpRowSrc src{};
+  src.x = d_x;
+  InferOut out{};
+  out.y = d_y;
+  return mlp_infer(m, src, rows, out, as_stream(stream));
+}
+
+pe_status pe_mlp_train_step(pe_mlp m, int64_t rows, const float *d_x, const float *d_t, float lr,
+                            int32_t apply, float *d_loss, float *d_grad, void *stream) {
+  clear_error();
+  if (!m || !d_x || !d_t) return set_error(PE_E_ARG, "null argument");
+  if (rows < 1 || rows > (int64_t(1) << 24)) return set_error(PE_E_ARG, "rows must be 1..2^24");
+  hipStream_t st = as_stream(stream);
+  int64_t tiles = (rows + ROWS - 1) / ROWS;
+  int nb = int(tiles < MAX_TRAIN_BLOCKS ? tiles : MAX_TRAIN_BLOCKS);
+  int64_t tiles_per_block = (tiles + nb - 1) / nb;
+  nb = int((tiles + tiles_per_block - 1) / tiles_per_block);
+  size_t lds = sizeof(TrainLds);
+  static bool attr_set = false;
+  if (!attr_set) {
+    PE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mlp_train),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    attr_set = true;
+  }
+  k_mlp_train<<<nb, MNT, lds, st>>>(m->packed, m->master, d_x, d_t, rows,
+                                   tiles_per_block * ROWS, m->partials, m->loss_part);
+  PE_HIP(hipGetLastError());
+  k_mlp_reduce<<<(NP + 255) / 256, 256, 0, st>>>(m->partials, m->loss_part, nb, rows, m->grad,
+                                                 d_loss, d_grad);
+  PE_HIP(hipGetLastError());
+  if (apply) {
+    m->step += 1;
+    const float c1 = 1.0f - powf(0.9f, float(m->step));
+    const float c2 = 1.0f - powf(0.999f, float(m->step));
+    k_mlp_adam<<<(NP + 255) / 256, 256, 0, st>>>(m->master, m->m, m->v, m->grad, lr, c1, c2);
+    PE_HIP(hipGetLastError());
+    PE_TRY(repack(m, st));
+  }
+  return PE_OK;
+}
+
+pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double dT,
+                                const void *d_samples, void *d_corr, int32_t *h_fallback,
+                                void *stream) {
+  clear_error();
+  if (!g || !m || !d_samples || !d_corr) return set_error(PE_E_ARG, "null argument");
+  if (n_slices < 1 || !(dT > 0)) return set_error(PE_E_ARG, "bad n_slices / dT");
+  hipStream_t st = as_stream(stream);
+  MlpRowSrc src{};
+  src.x = nullptr;
+  src.dim = g->dim;
+  src.n0 = g->ax[0].n;
+  src.n1 = g->dim > 1 ? g->ax[1].n : 1;
+  src.n2 = g->dim > 2 ? g->ax[2].n : 1;
+  src.lam0 = g->ax[0].d_lam;
+  src.lam1 = g->ax[1].d_lam;
+  src.lam2 = g->ax[2].d_lam;
+  src.D = g->D;
+  src.dT = dT;
+  src.samples = d_samples;
+  src.fp64 = g->precision == PE_FP64;
+  src.dof = g->dof;
+  InferOut out{};
+  out.corr = d_corr;
+  out.fp64 = src.fp64;
+  out.bad = m->flag;
+  PE_HIP(hipMemsetAsync(m->flag, 0, sizeof(int), st));
+  PE_TRY(mlp_infer(m, src, int64_t(n_slices) * g->dof, out, st));
+  int bad = 0;
+  PE_HIP(hipMemcpyAsync(&bad, m->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  PE_HIP(hipStreamSynchronize(st));
+  if (bad) {
+    const size_t sb = src.fp64 ? sizeof(double) : sizeof(float);
+    PE_HIP(hipMemsetAsync(d_corr, 0, sb * size_t(n_slices) * g->dof, st));
+    PE_HIP(hipStreamSynchronize(st));
+  }
+  if (h_fallback) *h_fallback = bad ? 1 : 0;
+  return PE_OK;
+}
+
+}  // extern "C"

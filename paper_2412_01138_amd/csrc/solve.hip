@@ -32,7 +32,11 @@ static size_t fixed_bytes(pe_grid g, const pe_solve_params *P) {
   b += Arena::need(sb * dof * P->N);                        // r
   b += Arena::need(sizeof(double) * 2);                     // norms
   b += coarse_partials_bytes(g);
-  return b + 4 * 256;
+  if (P->mlp && !P->d_corr) {
+    b += Arena::need(sb * dof * P->N * PE_MLP_SAMPLES);     // forcing samples
+    b += Arena::need(sb * dof * P->N);                      // learned correction
+  }
+  return b + 6 * 256;
 }
 
 static pe_status check_params(pe_grid g, const pe_solve_params *P) {
@@ -88,8 +92,12 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
   char *r = ar.take<char>(sb * dof * N);
   double *norms = ar.take<double>(2);
   double *partials = ar.take<double>(coarse_partials_bytes(g) / sizeof(double));
-  if (!EF || !EG || !Ubuf || !Fout || !r || !norms || !partials)
+  const bool learn = P->mlp && !P->d_corr;
+  char *samples = learn ? ar.take<char>(sb * dof * N * PE_MLP_SAMPLES) : nullptr;
+  char *lcorr = learn ? ar.take<char>(sb * dof * N) : nullptr;
+  if (!EF || !EG || !Ubuf || !Fout || !r || !norms || !partials || (learn && (!samples || !lcorr)))
     return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  const void *corr = P->d_corr;
   double *BF = EF + dof, *BG = EG + dof;
   size_t off = (ar.off + 255) & ~size_t(255);
   void *fwork = static_cast<char *>(d_work) + off;
@@ -118,9 +126,29 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
     PE_HIP(hipMemcpyAsync(cur, d_U0, sb * dof, hipMemcpyDeviceToDevice, st));
   else
     PE_HIP(hipMemsetAsync(cur, 0, sb * dof, st));
-  // U^(0): r_n for all slices, then the sequential coarse sweep
+  // U^(0): r_n for all slices (and the learned correction), then the
+  // sequential coarse sweep
   PE_TRY(run_propagation(g, N, P->t0, dT, dT, 1, p, P->cG, EG, BG, nullptr, r, fwork, fbytes, st));
-  PE_TRY(sweep(g, N, EG, r, P->d_corr, nullptr, nullptr, cur, nullptr, partials, st));
+  if (learn) {
+    hipEvent_t l0, l1;
+    PE_HIP(hipEventCreate(&l0));
+    PE_HIP(hipEventCreate(&l1));
+    PE_HIP(hipEventRecord(l0, st));
+    pe_status s1 = pe_learned_samples(g, N, P->t0, dT, samples, fwork, fbytes, stream);
+    int32_t fb = 0;
+    pe_status s2 = s1 == PE_OK ? pe_learned_correction(g, P->mlp, N, dT, samples, lcorr, &fb, stream)
+                               : s1;
+    float lms = 0;
+    if (s2 == PE_OK && hipEventRecord(l1, st) == hipSuccess && hipEventSynchronize(l1) == hipSuccess)
+      hipEventElapsedTime(&lms, l0, l1);
+    hipEventDestroy(l0);
+    hipEventDestroy(l1);
+    PE_TRY(s2);
+    rep->ms_learned = lms;
+    rep->fallback = fb;
+    corr = lcorr;
+  }
+  PE_TRY(sweep(g, N, EG, r, corr, nullptr, nullptr, cur, nullptr, partials, st));
   PE_HIP(hipEventRecord(ev[2], st));
   PE_HIP(hipEventSynchronize(ev[2]));
 
@@ -132,7 +160,7 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
                            st));
     PE_HIP(hipEventRecord(ev[4], st));
     PE_HIP(hipMemcpyAsync(nxt, cur, sb * dof, hipMemcpyDeviceToDevice, st));   // U^{0,(k+1)} = U^0
-    PE_TRY(sweep(g, N, EG, r, P->d_corr, cur, Fout, nxt, norms, partials, st));
+    PE_TRY(sweep(g, N, EG, r, corr, cur, Fout, nxt, norms, partials, st));
     double hn[2] = {0, 0};
     PE_HIP(hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, st));
     PE_HIP(hipStreamSynchronize(st));

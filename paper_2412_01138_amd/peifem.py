@@ -35,7 +35,11 @@ EXPORTS = [
     "pe_fine_propagate", "pe_coarse_workspace_bytes", "pe_coarse_sweep",
     "pe_solve_workspace_bytes", "pe_parareal_solve", "pe_grid_dof",
     "pe_grid_precision", "pe_last_error", "pe_set_timing", "pe_get_timing",
+    "pe_mlp_create", "pe_mlp_free", "pe_mlp_get_params", "pe_mlp_set_params", "pe_mlp_forward",
+    "pe_mlp_train_step", "pe_learned_samples_workspace_bytes", "pe_learned_samples",
+    "pe_learned_rows_workspace_bytes", "pe_learned_rows", "pe_learned_correction",
 ]
+PE_MLP_INPUTS, PE_MLP_WIDTH, PE_MLP_PARAMS, PE_MLP_SAMPLES = 12, 64, 9217, 8
 PE_K_DST_LAST, PE_K_DST_MID, PE_K_LOAD, PE_K_UPDATE, PE_K_SWEEP, PE_K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_CLASSES = ("dst_last", "dst_mid", "load", "update", "sweep")
 
@@ -71,14 +75,15 @@ class SolveParams(ctypes.Structure):
                 ("J", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("cG", ctypes.c_double * PE_MAX_STAGES), ("cF", ctypes.c_double * PE_MAX_STAGES),
                 ("K_max", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("d_corr", ctypes.c_void_p)]
+                ("d_corr", ctypes.c_void_p), ("mlp", ctypes.c_void_p)]
 
 
 class SolveReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("jumps", ctypes.c_double * PE_MAX_ITERS), ("ms_tables", ctypes.c_double),
                 ("ms_coarse", ctypes.c_double), ("ms_fine", ctypes.c_double),
-                ("ms_sweep", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_sweep", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_learned", ctypes.c_double), ("fallback", ctypes.c_int32)]
 
 
 _lib = None
@@ -119,11 +124,29 @@ def load_library():
     L.pe_grid_precision.restype = i32
     L.pe_set_timing.argtypes = [vp, i32]
     L.pe_get_timing.argtypes = [vp, ctypes.POINTER(KernelStat)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.pe_mlp_create.argtypes = [ctypes.POINTER(vp), fp, vp]
+    L.pe_mlp_free.argtypes = [vp]
+    L.pe_mlp_free.restype = None
+    L.pe_mlp_get_params.argtypes = [vp, fp, vp]
+    L.pe_mlp_set_params.argtypes = [vp, fp, vp]
+    L.pe_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+    L.pe_mlp_train_step.argtypes = [vp, i64, vp, vp, ctypes.c_float, i32, vp, vp, vp]
+    L.pe_learned_samples_workspace_bytes.argtypes = [vp, i32]
+    L.pe_learned_samples_workspace_bytes.restype = sz
+    L.pe_learned_samples.argtypes = [vp, i32, dbl, dbl, vp, vp, sz, vp]
+    L.pe_learned_rows_workspace_bytes.argtypes = [vp, i32]
+    L.pe_learned_rows_workspace_bytes.restype = sz
+    L.pe_learned_rows.argtypes = [vp, i32, dbl, vp, vp, vp, dbl, vp, vp, i64,
+                                  ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
+    L.pe_learned_correction.argtypes = [vp, vp, i32, dbl, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
     L.pe_last_error.argtypes = []
     L.pe_last_error.restype = ctypes.c_char_p
     for name in ("pe_init_grid", "pe_set_forcing", "pe_phi_tables", "pe_project",
                  "pe_fine_propagate", "pe_coarse_sweep", "pe_parareal_solve", "pe_set_timing",
-                 "pe_get_timing"):
+                 "pe_get_timing", "pe_mlp_create", "pe_mlp_get_params", "pe_mlp_set_params",
+                 "pe_mlp_forward", "pe_mlp_train_step", "pe_learned_samples", "pe_learned_rows",
+                 "pe_learned_correction"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -285,7 +308,44 @@ class Grid:
                                       _ptr(work), work.numel(), _stream(self.stream)))
         return U
 
-    def solve_params(self, t0, T, N, J, cG, cF, K_max, tol, corr=None) -> SolveParams:
+    def learned_samples(self, N: int, t0: float, dT: float, out=None, work=None):
+        """Spectral forcing at T_n + s dT/7, s = 0..7, for every slice: [8N, *grid]."""
+        if out is None:
+            out = self.empty_states(PE_MLP_SAMPLES * N)
+        if work is None:
+            work = self.workspace(self.L.pe_learned_samples_workspace_bytes(self.h, N))
+        _check(self.L.pe_learned_samples(self.h, N, float(t0), float(dT), _ptr(out), _ptr(work),
+                                         work.numel(), _stream(self.stream)))
+        return out
+
+    def learned_rows(self, samples, R, r, dT: float, rel_thresh: float = 1e-9,
+                     max_rows: Optional[int] = None):
+        """Training rows (x [rows, 12], target [rows]) of the modes whose
+        forcing samples do not vanish."""
+        import torch
+        N = R.shape[0]
+        if max_rows is None:
+            max_rows = N * self.dof
+        x = torch.empty((max(max_rows, 1), PE_MLP_INPUTS), dtype=torch.float32, device=self.device)
+        t = torch.empty(max(max_rows, 1), dtype=torch.float32, device=self.device)
+        work = self.workspace(self.L.pe_learned_rows_workspace_bytes(self.h, N))
+        cnt = ctypes.c_int64(0)
+        _check(self.L.pe_learned_rows(self.h, N, float(dT), _ptr(samples), _ptr(R), _ptr(r),
+                                      float(rel_thresh), _ptr(x), _ptr(t), int(max_rows),
+                                      ctypes.byref(cnt), _ptr(work), work.numel(),
+                                      _stream(self.stream)))
+        n = min(int(cnt.value), max_rows)
+        return x[:n], t[:n], int(cnt.value)
+
+    def learned_correction(self, mlp: "Mlp", samples, N: int, dT: float, out=None):
+        if out is None:
+            out = self.empty_states(N)
+        fb = ctypes.c_int32(0)
+        _check(self.L.pe_learned_correction(self.h, mlp.h, N, float(dT), _ptr(samples), _ptr(out),
+                                            ctypes.byref(fb), _stream(self.stream)))
+        return out, bool(fb.value)
+
+    def solve_params(self, t0, T, N, J, cG, cF, K_max, tol, corr=None, mlp=None) -> SolveParams:
         P = SolveParams()
         P.t0, P.T, P.N, P.J = float(t0), float(T), int(N), int(J)
         P.p, P.q = len(cG), len(cF)
@@ -295,6 +355,7 @@ class Grid:
             P.cF[i] = v
         P.K_max, P.tol = int(K_max), float(tol)
         P.d_corr = _ptr(corr)
+        P.mlp = mlp.h if mlp is not None else None
         return P
 
     def solve_workspace_bytes(self, P: SolveParams) -> int:
@@ -311,12 +372,68 @@ class Grid:
         return U, rep
 
 
+class Mlp:
+    """A pe_mlp handle (the learned coarse correction network)."""
+
+    def __init__(self, params, stream=None):
+        import numpy as np
+        self.L = load_library()
+        self.stream = stream
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        if p.size != PE_MLP_PARAMS:
+            raise ValueError(f"expected {PE_MLP_PARAMS} parameters")
+        h = ctypes.c_void_p()
+        _check(self.L.pe_mlp_create(ctypes.byref(h), p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    _stream(stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pe_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(PE_MLP_PARAMS, dtype=np.float32)
+        _check(self.L.pe_mlp_get_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                        _stream(self.stream)))
+        return p
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        _check(self.L.pe_mlp_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                        _stream(self.stream)))
+
+    def forward(self, x):
+        import torch
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(self.L.pe_mlp_forward(self.h, x.shape[0], _ptr(x), _ptr(y), _stream(self.stream)))
+        return y
+
+    def train_step(self, x, t, lr: float, apply: bool = True, want_grad: bool = False):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty(PE_MLP_PARAMS, dtype=torch.float32, device=x.device) if want_grad else None
+        _check(self.L.pe_mlp_train_step(self.h, x.shape[0], _ptr(x), _ptr(t), float(lr),
+                                        1 if apply else 0, _ptr(loss), _ptr(grad),
+                                        _stream(self.stream)))
+        return loss, grad
+
+
 def solve_problem(prob, K_max: Optional[int] = None, tol: Optional[float] = None,
-                  corr=None, device: str = "cuda:0"):
+                  corr=None, device: str = "cuda:0", mlp: Optional[Mlp] = None):
     """Grid + forcing + P_h u0 + Algorithm 1 for a workloads.Problem."""
     g = Grid.from_problem(prob, device=device)
     U0 = g.project(prob.u0) if prob.u0 else None
     P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
-                       prob.K_max if K_max is None else K_max, prob.tol if tol is None else tol, corr)
+                       prob.K_max if K_max is None else K_max, prob.tol if tol is None else tol, corr,
+                       mlp)
     U, rep = g.parareal_solve(P, U0=U0)
     return g, U, rep

@@ -43,7 +43,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(peifem.SpaceFactor) == 5 * 8
     assert ctypes.sizeof(peifem.TimeFactor) == 7 * 8
     assert ctypes.sizeof(peifem.Term) == 8 + 7 * 8 + 3 * 5 * 8
-    assert ctypes.sizeof(peifem.SolveReport) == 8 + 64 * 8 + 5 * 8
+    assert ctypes.sizeof(peifem.SolveReport) == 8 + 64 * 8 + 6 * 8 + 8
     assert peifem.PE_K_COUNT == len(peifem.KERNEL_CLASSES)
 
 

@@ -1,0 +1,199 @@
+"""Learned coarse correction on the GPU vs the FP64 CPU oracle.
+
+The network runs with bf16 weights and bf16 activations into the matrix cores
+(fp32 accumulation), so its outputs and gradients are compared with the FP64
+oracle evaluated on the same bf16-rounded weights, at bf16-level tolerances:
+relative L2 error <= 3e-2 per tensor and cosine similarity >= 0.999 for
+gradients; the network output <= 2e-2 relative to its scale.  Everything
+upstream of the network (forcing samples, training targets) is FP64/FP32 work
+held to the usual path tolerances.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as omlp
+from oracle.eife import Discretization, eife_step
+from oracle.parareal import fine_prop, parareal
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _pe():
+    from paper_2412_01138_amd import peifem
+    return peifem
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def cos(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def bf16_params(seed):
+    return omlp.to_bf16(omlp.init_params(seed))
+
+
+def _rows(seed, n):
+    rng = np.random.default_rng(seed)
+    z = 10.0 ** rng.uniform(-4, 1.5, n)
+    s = rng.normal(size=(n, 8))
+    x, _ = omlp.features(z, s)
+    return x, rng.normal(size=n)
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
+
+
+def test_mlp_forward_matches_oracle():
+    pe = _pe()
+    theta = bf16_params(1)
+    x, _ = _rows(2, 1000)
+    x = omlp.to_bf16(x)                       # inputs enter the matrix cores as bf16
+    m = pe.Mlp(theta)
+    y = m.forward(_dev(x)).cpu().numpy()
+    ref = omlp.forward(theta, x)
+    assert np.max(np.abs(y - ref)) <= 2e-2 * np.max(np.abs(ref))
+    assert rel(y, ref) <= 2e-2
+
+
+@pytest.mark.parametrize("rows", [1, 63, 1000, 70000])
+def test_mlp_gradients_match_oracle(rows):
+    pe = _pe()
+    theta = bf16_params(5)
+    x, t = _rows(6, rows)
+    x = omlp.to_bf16(x)
+    m = pe.Mlp(theta)
+    loss, grad = m.train_step(_dev(x), _dev(t), lr=0.0, apply=False, want_grad=True)
+    L, g_ref = omlp.loss_and_grad(theta, x, t)
+    g = grad.cpu().numpy()
+    assert abs(float(loss.cpu()) - L) <= 2e-2 * L
+    G, R = omlp.unpack(g), omlp.unpack(g_ref)
+    for name, _ in omlp.SHAPES:
+        assert cos(G[name], R[name]) >= 0.999, name
+        assert rel(G[name], R[name]) <= 3e-2, name
+    # fixed reduction order: a second call is bitwise identical; weights untouched
+    loss2, grad2 = m.train_step(_dev(x), _dev(t), lr=0.0, apply=False, want_grad=True)
+    assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
+    np.testing.assert_array_equal(m.get_params(), theta.astype(np.float32))
+
+
+def test_mlp_training_reduces_loss():
+    pe = _pe()
+    teacher = omlp.init_params(11) * 0.5
+    x, _ = _rows(12, 20000)
+    x = omlp.to_bf16(x)
+    t = omlp.forward(teacher, x)
+    m = pe.Mlp(omlp.to_bf16(omlp.init_params(13)))
+    X, T = _dev(x), _dev(t)
+    first = float(m.train_step(X, T, lr=0.0, apply=False)[0].cpu())
+    for step in range(300):
+        lo = (step * 2048) % 20000
+        m.train_step(X[lo:lo + 2048], T[lo:lo + 2048], lr=2e-3)
+    last = float(m.train_step(X, T, lr=0.0, apply=False)[0].cpu())
+    assert last < 0.1 * first, (first, last)
+
+
+def _small_problem(seed=3, dim=2, n=(31, 24), N=6, J=4, s=3):
+    return wl.tiny_problem(dim, n, seed=seed, N=N, J=J, s=s, n_modes=3, T=0.6, u0_modes=1)
+
+
+def test_learned_samples_match_oracle():
+    pe = _pe()
+    prob = _small_problem()
+    g = pe.Grid.from_problem(prob)
+    S = g.learned_samples(prob.N, prob.t0, prob.dT).cpu().numpy()
+    d = Discretization(prob)
+    for n in (0, 3, prob.N - 1):
+        for q in range(8):
+            ref = d.spectral_forcing(prob.t0 + n * prob.dT + q * prob.dT / 7)
+            assert rel(S[8 * n + q], ref) <= 1e-12
+
+
+def test_learned_rows_match_oracle():
+    pe = _pe()
+    prob = _small_problem()
+    g = pe.Grid.from_problem(prob)
+    EF, BF = g.phi_tables(prob.dt, prob.c_fine)
+    EG, BG = g.phi_tables(prob.dT, prob.c_coarse)
+    zero = torch.zeros((prob.N,) + prob.n, dtype=torch.float64, device="cuda:0")
+    R = g.fine_propagate(zero, prob.t0, prob.dT, prob.J, prob.c_fine, EF, BF)
+    U = torch.zeros((prob.N + 1,) + prob.n, dtype=torch.float64, device="cuda:0")
+    r = torch.empty((prob.N,) + prob.n, dtype=torch.float64, device="cuda:0")
+    g.coarse_sweep(U, prob.t0, prob.dT, prob.c_coarse, EG, BG, r)
+    S = g.learned_samples(prob.N, prob.t0, prob.dT)
+    x, t, count = g.learned_rows(S, R, r, prob.dT, rel_thresh=1e-9)
+    # oracle rows in (n, k) order
+    d = Discretization(prob)
+    tF, tG = d.tables(prob.dt, prob.c_fine), d.tables(prob.dT, prob.c_coarse)
+    z = (prob.D * d.lam * prob.dT).ravel()
+    xs, ts = [], []
+    samples_all = []
+    for n in range(prob.N):
+        Tn = prob.t0 + n * prob.dT
+        Rn = fine_prop(d, np.zeros(prob.n), Tn, tF, prob.J).ravel()
+        rn = eife_step(d, np.zeros(prob.n), Tn, tG).ravel()
+        smp = np.stack([d.spectral_forcing(Tn + q * prob.dT / 7).ravel() for q in range(8)], axis=1)
+        samples_all.append(smp)
+        xn, sg = omlp.features(z, smp)
+        xs.append((xn, sg, (Rn - rn)))
+    smax = max(np.max(np.abs(s)) for s in samples_all)
+    X, T = [], []
+    for xn, sg, dlt in xs:
+        keep = sg > 1e-9 * smax
+        X.append(xn[keep])
+        T.append(dlt[keep] / (sg[keep] * prob.dT))
+    X, T = np.concatenate(X), np.concatenate(T)
+    assert count == len(T)
+    np.testing.assert_allclose(x.cpu().numpy(), X, rtol=2e-6, atol=2e-6)
+    assert rel(t.cpu().numpy(), T) <= 1e-5
+
+
+def test_learned_correction_matches_oracle_and_keeps_the_answer():
+    pe = _pe()
+    prob = _small_problem()
+    theta = omlp.to_bf16(bf16_params(21) * 0.05)
+    m = pe.Mlp(theta)
+    g = pe.Grid.from_problem(prob)
+    S = g.learned_samples(prob.N, prob.t0, prob.dT)
+    corr, fb = g.learned_correction(m, S, prob.N, prob.dT)
+    assert not fb
+    d = Discretization(prob)
+    z = (prob.D * d.lam * prob.dT).ravel()
+    Sn = S.cpu().numpy().reshape(prob.N, 8, -1)
+    ref = np.stack([omlp.correction(theta, z, Sn[n].T, prob.dT) for n in range(prob.N)])
+    got = corr.cpu().numpy().reshape(prob.N, -1)
+    assert rel(got, ref) <= 3e-2
+    # the Parareal iterates k >= 1 do not depend on a state-independent correction
+    _, U_plain, rep_plain = pe.solve_problem(prob, K_max=3, tol=0.0)
+    _, U_learn, rep_learn = pe.solve_problem(prob, K_max=3, tol=0.0, mlp=m)
+    assert rep_learn.fallback == 0 and rep_learn.ms_learned > 0
+    assert rel(U_learn.cpu().numpy(), U_plain.cpu().numpy()) <= 1e-13
+    assert abs(rep_learn.jumps[0] - rep_plain.jumps[0]) > 1e-9 * rep_plain.jumps[0]
+    # the oracle Parareal with the same correction has the same first jump
+    r = parareal(d, d.initial(), prob.t0, prob.N, prob.J, d.tables(prob.dt, prob.c_fine),
+                 d.tables(prob.dT, prob.c_coarse), K_max=1,
+                 corrections=[got[n].reshape(prob.n) for n in range(prob.N)])
+    assert abs(rep_learn.jumps[0] - r.jumps[0]) <= 1e-9 * r.jumps[0]
+
+
+def test_learned_correction_falls_back_on_non_finite_network():
+    pe = _pe()
+    prob = _small_problem(seed=4)
+    theta = bf16_params(22)
+    theta[omlp.N_PARAMS - 1] = np.nan          # b4 = NaN
+    m = pe.Mlp(theta)
+    _, U_plain, rep_plain = pe.solve_problem(prob, K_max=2, tol=0.0)
+    _, U_learn, rep_learn = pe.solve_problem(prob, K_max=2, tol=0.0, mlp=m)
+    assert rep_learn.fallback == 1
+    assert rep_learn.jumps[0] == rep_plain.jumps[0]
+    np.testing.assert_array_equal(U_learn.cpu().numpy(), U_plain.cpu().numpy())

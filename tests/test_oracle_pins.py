@@ -411,3 +411,61 @@ def test_parareal_state_independent_correction_changes_only_k0():
     assert np.linalg.norm(r2.iterates[0] - r.iterates[0]) > 1e-3
     for k in (1, 2, 3):
         np.testing.assert_allclose(r2.iterates[k], r.iterates[k], atol=1e-14 * np.linalg.norm(r.iterates[k]))
+
+
+# --------------------------------------------------------------------------
+# P11: the oracle MLP of the learned coarse correction
+# --------------------------------------------------------------------------
+
+def test_mlp_backward_matches_central_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    theta = mlp.init_params(3)
+    x = rng.normal(size=(7, mlp.N_IN))
+    t = rng.normal(size=7)
+    L, grad = mlp.loss_and_grad(theta, x, t)
+    assert abs(L - mlp.loss(theta, x, t)) <= 1e-15 * max(1.0, L)
+    idx = rng.choice(mlp.N_PARAMS, 60, replace=False)
+    idx = np.concatenate([idx, [mlp.N_PARAMS - 1, 0, 12 * 64 + 5]])   # b4, W1[0,0], b1[5]
+    for i in idx:
+        h = 1e-6 * max(1.0, abs(theta[i]))
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (mlp.loss(tp, x, t) - mlp.loss(tm, x, t)) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-7 * max(1.0, abs(fd)), (i, fd, grad[i])
+
+
+def test_mlp_gelu_and_features():
+    from oracle import mlp
+    from scipy.stats import norm
+    xs = np.linspace(-6, 6, 41)
+    np.testing.assert_allclose(mlp.gelu(xs), xs * norm.cdf(xs), rtol=1e-14, atol=1e-300)
+    z = np.array([1e-8, 1e-4, 0.5, 3.0, 400.0])
+    f = mlp.z_features(z)
+    np.testing.assert_allclose(f[:, 1], np.exp(-z), rtol=1e-15)
+    for k, zk in enumerate(z):
+        with mp.workdps(50):
+            zz = mp.mpf(zk)
+            p1 = (1 - mp.exp(-zz)) / zz
+            p2 = (zz - 1 + mp.exp(-zz)) / zz ** 2
+        assert abs(f[k, 2] - float(p1)) <= 1e-14 * float(p1)
+        assert abs(f[k, 3] - 2 * float(p2)) <= 1e-13 * 2 * float(p2)
+    # sigma normalisation: features of a scaled sample row are unchanged
+    s = np.random.default_rng(1).normal(size=(3, 8))
+    x1, sg1 = mlp.features(np.full(3, 0.3), s)
+    x2, sg2 = mlp.features(np.full(3, 0.3), 1e-7 * s)
+    np.testing.assert_allclose(x1, x2, rtol=1e-13)
+    np.testing.assert_allclose(sg2, 1e-7 * sg1, rtol=1e-15)
+    # the correction vanishes with the forcing
+    theta = mlp.init_params(0)
+    assert np.all(mlp.correction(theta, np.full(2, 0.3), np.zeros((2, 8)), 0.1) == 0.0)
+
+
+def test_bf16_rounding_reference():
+    from oracle import mlp
+    v = np.array([1.0, 1.00390625, 1.001953125, 1.005859375, -3.14159265, 1e-30])
+    r = mlp.to_bf16(v)
+    assert r[0] == 1.0 and r[1] == 1.0078125 or r[1] == 1.0       # 1 + 2^-8 is a tie -> even (1.0)
+    assert r[2] == 1.0                                            # below half an ulp
+    assert r[3] == 1.0078125                                      # above half an ulp
+    assert abs(r[4] + 3.140625) < 1e-12
