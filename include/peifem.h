@@ -177,19 +177,29 @@ pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int
  * Learned coarse correction (an addition to the paper's method).
  *
  * G~(v; T_n) = E_G v + r_n + delta_n with, for every mode k,
- *     delta_{n,k} = sigma * dT * NN(x),   sigma = max_s |g_s|,
- *     g_s = ghat_k(T_n + s dT / 7), s = 0..7   (spectral forcing samples),
- *     x = [ln(z)/8, e^{-z}, phi_1(-z), 2 phi_2(-z), g_0/sigma .. g_7/sigma],
+ *     delta_{n,k} = s * dT * NN(x),
+ *     g_j = ghat_k(T_n + j dT / 7), j = 0..7   (spectral forcing samples),
+ *     c = Q^T g,  Q[j][i] = q_i(t_j), t_j = (j - 3.5)/3.5, q_0..q_7 the
+ *         orthonormal polynomials of those points (Gram-Schmidt of the
+ *         monomials 1, t, .., t^7; q_i has degree i, positive leading term),
+ *     s = |(c_4, .., c_7)|   (the part of the samples of degree >= 4),
+ *     x = [ln(z)/8, e^{-z}, phi_1(-z), 2 phi_2(-z), c_0/|g| .. c_3/|g|,
+ *          c_4/s .. c_7/s],
  *     z = D lambda_k dT,  phi_1(-z) = (1 - e^{-z})/z,  phi_2(-z) = (z - 1 + e^{-z})/z^2,
- * (delta = 0 where sigma = 0).  NN: 12 -> 64 -> 64 -> 64 (GELU x Phi(x)) -> 1,
- * bf16 weights, fp32 accumulation, on the matrix cores.  Because delta does
- * not depend on the state, the Parareal iterates k >= 1 are unchanged by it
- * (Algorithm 1 with eq. (2.8) still converges to the fine solution): the
- * correction only moves U^(0) and hence the iteration count.
+ * (delta = 0 where s = 0; zero parts give zero features).  An s-stage
+ * exponential Runge-Kutta step integrates forcing that is a polynomial of
+ * degree < s in time exactly (its weights, eq. (2.7), come from the Lagrange
+ * interpolant), so for s >= 4 the fine-coarse difference depends only on the
+ * part of degree >= 4, which sets the scale s.  NN: 12 -> 64 -> 64 -> 64
+ * (GELU x Phi(x)) -> 1, bf16 weights, fp32 accumulation, on the matrix cores;
+ * the inputs enter the first layer as a bf16 hi + lo pair (no input rounding).
+ * Because delta does not depend on the state, the Parareal iterates k >= 1
+ * are unchanged by it (Algorithm 1 with eq. (2.8) still converges to the fine
+ * solution): the correction only moves U^(0) and hence the iteration count.
  * Parameters: PE_MLP_PARAMS floats, W1[12][64], b1[64], W2[64][64], b2[64],
  * W3[64][64], b3[64], w4[64], b4[1] (W[in][out]).  A pe_mlp holds fp32
  * master weights, their bf16 copies and Adam moments on the device.
- * Training rows: target (R_n - r_n)_k / (sigma dT), R_n = F^J(0), r_n = G(0)
+ * Training rows: target (R_n - r_n)_k / (s dT), R_n = F^J(0), r_n = G(0)
  * on slice n (the state-independent fine/coarse forcing responses). */
 #define PE_MLP_INPUTS 12
 #define PE_MLP_WIDTH 64
@@ -228,16 +238,17 @@ pe_status pe_learned_samples(pe_grid g, int32_t n_slices, double t0, double dT, 
                              void *d_work, size_t work_bytes, void *stream);
 
 /* Training rows from one solve's responses: for every (n, k) with
- * sigma > rel_thresh * max sigma, write x (12 floats) and the target
- * (R - r)_{n,k} / (sigma dT) to d_x / d_t, in (n, k) order, at most max_rows;
+ * s > rel_thresh * max s, write x (12 floats) and the target
+ * (R - r)_{n,k} / (s dT) to d_x / d_t and s to d_s (nullable), in (n, k)
+ * order, at most max_rows;
  * *h_count (host) receives the number of qualifying rows (it can exceed
  * max_rows: only the first max_rows are written).  d_R, d_r: [N][DOF].
  * Needs pe_learned_rows_workspace_bytes(g, N) of d_work.  Synchronises. */
 size_t pe_learned_rows_workspace_bytes(pe_grid g, int32_t n_slices);
 pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double dT, const void *d_samples,
                           const void *d_R, const void *d_r, double rel_thresh, float *d_x,
-                          float *d_t, int64_t max_rows, int64_t *h_count, void *d_work,
-                          size_t work_bytes, void *stream);
+                          float *d_t, float *d_s, int64_t max_rows, int64_t *h_count,
+                          void *d_work, size_t work_bytes, void *stream);
 
 /* delta_n for every slice and mode into d_corr[N][DOF] (state dtype).  If
  * the network produces a non-finite value anywhere, d_corr is zeroed (plain

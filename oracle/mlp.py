@@ -2,17 +2,24 @@
 
 Learned correction of G (an addition to the paper's method): for slice n and
 spectral mode k the coarse step becomes
-    G~(v) = E_G v + r_n + delta_n,  delta_{n,k} = sigma * dT * NN(x),
-where the network input x holds features of z = D lambda_k dT and the eight
-forcing samples g_s = ghat_k(T_n + s dT / 7), s = 0..7, divided by
-sigma = max_s |g_s| (so delta vanishes with the forcing and is homogeneous in
-it).  The training target of a row is (R_n - r_n)_k / (sigma dT) with
-R_n = F^J(0) and r_n = G(0) on slice n: the state-independent fine and coarse
-forcing responses (eq. 4.5 and the Lipschitz identity in the proof of
-Theorem 4.3 make both responses independent of the state).
+    G~(v) = E_G v + r_n + delta_n,  delta_{n,k} = dT * s * NN(x).
+The inputs come from z = D lambda_k dT and the eight forcing samples
+g_s = ghat_k(T_n + s dT / 7), s = 0..7.  The samples are expanded in the
+discrete orthonormal polynomials q_0..q_7 of the points t_s = (s - 3.5)/3.5
+(Gram-Schmidt of 1, t, .., t^7, positive leading coefficients):
+c_j = q_j . g.  Both propagators integrate forcing that is a cubic in time
+exactly (the exponential Runge-Kutta weights reproduce polynomials up to
+degree p - 1 = 3), so the correction depends on the part of degree >= 4; its
+size s = ||(c_4..c_7)|| scales the output, and the inputs are
+    x = [ln(z)/8, e^{-z}, phi_1(-z), 2 phi_2(-z),
+         c_0/|g|, .., c_3/|g|,  c_4/s, .., c_7/s]
+(|g| the Euclidean norm of the samples; zero parts give zero features).
+The training target of a row is (R_n - r_n)_k / (dT s) with R_n = F^J(0) and
+r_n = G(0) on slice n: the state-independent fine and coarse forcing
+responses (eq. 4.5 and the Lipschitz identity in the proof of Theorem 4.3 make
+both responses independent of the state).
 
 Network: 12 inputs -> 64 -> 64 -> 64 (GELU, x Phi(x)) -> 1 (linear).
-Features: [ln(z)/8, e^{-z}, phi_1(-z), 2 phi_2(-z), g_0/sigma .. g_7/sigma].
 Parameters (flat float vector, this order): W1[12][64], b1[64], W2[64][64],
 b2[64], W3[64][64], b3[64], w4[64], b4[1]  (W[in][out], y = x W + b).
 
@@ -75,14 +82,28 @@ def z_features(z: np.ndarray) -> np.ndarray:
     return np.stack([np.log(z) / 8.0, e, phi1, 2.0 * phi2], axis=-1)
 
 
+def sample_basis() -> np.ndarray:
+    """Q[s][j] = q_j(t_s): orthonormal columns from Gram-Schmidt of the
+    monomials in t_s = (s - 3.5)/3.5 (numpy QR, signs fixed so that every
+    diagonal entry of R is positive)."""
+    t = (np.arange(SAMPLES) - 3.5) / 3.5
+    V = np.vander(t, SAMPLES, increasing=True)
+    Q, R = np.linalg.qr(V)
+    return Q * np.sign(np.diag(R))[None, :]
+
+
 def features(z: np.ndarray, samples: np.ndarray):
     """Rows of network inputs from z[rows] and samples[rows, 8]; returns
-    (x[rows, 12], sigma[rows])."""
+    (x[rows, 12], s[rows]) with s the norm of the degree 4..7 coefficients."""
     samples = np.asarray(samples, dtype=np.float64)
-    sigma = np.max(np.abs(samples), axis=-1)
-    safe = np.where(sigma > 0, sigma, 1.0)
-    x = np.concatenate([z_features(z), samples / safe[:, None]], axis=-1)
-    return x, sigma
+    c = samples @ sample_basis()
+    gn = np.linalg.norm(samples, axis=-1)
+    hi = np.linalg.norm(c[:, 4:], axis=-1)
+    gsafe = np.where(gn > 0, gn, 1.0)
+    hsafe = np.where(hi > 0, hi, 1.0)
+    x = np.concatenate([z_features(z), c[:, :4] / gsafe[:, None], c[:, 4:] / hsafe[:, None]],
+                       axis=-1)
+    return x, hi
 
 
 def forward(theta: np.ndarray, x: np.ndarray, keep: bool = False):
@@ -149,7 +170,8 @@ def to_bf16(a: np.ndarray) -> np.ndarray:
 
 
 def correction(theta, z, samples, dT):
-    """delta = sigma * dT * NN(x) per row (zero where the forcing samples vanish)."""
-    x, sigma = features(z, samples)
+    """delta = dT * s * NN(x) per row (zero where the samples have no part of
+    degree >= 4)."""
+    x, s = features(z, samples)
     y = forward(theta, x)
-    return np.where(sigma > 0, sigma * dT * y, 0.0)
+    return np.where(s > 0, s * dT * y, 0.0)

@@ -4,9 +4,10 @@
 // eight times T_n + s dT / 7 (s = 0..7).  They are produced like the stage
 // fields of a fine pass (quadrature of the load vector + per-axis transform)
 // and stored in natural mode order.  Training rows pair those inputs with
-// the target (R_n - r_n)_k / (sigma dT), R_n = F^J(0) and r_n = G(0) of the
-// same slice; rows whose samples vanish carry no information and are skipped
-// (ordered, deterministic compaction).
+// the target (R_n - r_n)_k / (s dT), R_n = F^J(0) and r_n = G(0) of the
+// same slice, s the size of the samples' part of degree >= 4; rows where it
+// vanishes carry no information and are skipped (ordered, deterministic
+// compaction).
 #include <algorithm>
 #include <cmath>
 
@@ -43,6 +44,28 @@ __global__ void k_compact_fields(int d, int n0, int n1, int n2, int np0, int np1
   }
 }
 
+// Gram-Schmidt (modified, applied twice) of the monomials 1, t, .., t^7 at
+// t_j = (j - 3.5)/3.5.  Each q_i gets a positive leading coefficient.
+SampleBasis sample_basis() {
+  constexpr int S = PE_MLP_SAMPLES;
+  SampleBasis B{};
+  for (int i = 0; i < S; ++i) {
+    double v[S];
+    for (int j = 0; j < S; ++j) v[j] = std::pow((j - 3.5) / 3.5, i);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int m = 0; m < i; ++m) {
+        double d = 0.0;
+        for (int j = 0; j < S; ++j) d += B.q[j * S + m] * v[j];
+        for (int j = 0; j < S; ++j) v[j] -= d * B.q[j * S + m];
+      }
+    double nrm = 0.0;
+    for (int j = 0; j < S; ++j) nrm += v[j] * v[j];
+    nrm = std::sqrt(nrm);
+    for (int j = 0; j < S; ++j) B.q[j * S + i] = v[j] / nrm;
+  }
+  return B;
+}
+
 static unsigned nblk(int64_t n) {
   int64_t b = (n + 255) / 256;
   return unsigned(b < 65536 ? (b > 0 ? b : 1) : 65536);
@@ -60,18 +83,17 @@ struct RowsArgs {
   const void *samples, *R, *r;
   int fp64;
   int64_t dof, total;
+  SampleBasis B;
 };
 
-__device__ inline double rows_sigma(const RowsArgs &a, int64_t row, double *g) {
+__device__ inline double rows_scale(const RowsArgs &a, int64_t row, double *g) {
   const int64_t n = row / a.dof, k = row - n * a.dof;
-  double sg = 0.0;
   for (int q = 0; q < PE_MLP_SAMPLES; ++q) {
     const int64_t o = (n * PE_MLP_SAMPLES + q) * a.dof + k;
     g[q] = a.fp64 ? static_cast<const double *>(a.samples)[o]
                   : double(static_cast<const float *>(a.samples)[o]);
-    sg = fmax(sg, fabs(g[q]));
   }
-  return sg;
+  return mode_scale(g, a.B);
 }
 
 __global__ void k_rows_max(RowsArgs a, double *part) {
@@ -80,7 +102,7 @@ __global__ void k_rows_max(RowsArgs a, double *part) {
   for (int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x; row < a.total;
        row += int64_t(gridDim.x) * 256) {
     double g[PE_MLP_SAMPLES];
-    mx = fmax(mx, rows_sigma(a, row, g));
+    mx = fmax(mx, rows_scale(a, row, g));
   }
   sm[threadIdx.x] = mx;
   __syncthreads();
@@ -104,7 +126,7 @@ __global__ void k_rows_count(RowsArgs a, const double *smax, double rel, int *co
   bool q = false;
   if (row < a.total) {
     double g[PE_MLP_SAMPLES];
-    const double sg = rows_sigma(a, row, g);
+    const double sg = rows_scale(a, row, g);
     q = sg > rel * (*smax) && sg > 0.0;
   }
   const unsigned long long bal = __ballot(q);
@@ -124,31 +146,15 @@ __global__ void k_rows_scan(const int *counts, int nb, int64_t *offsets, int64_t
   *total = acc;
 }
 
-__device__ inline void zfeat(double z, float *f) {
-  const double e = exp(-z);
-  double p1, p2;
-  if (z < 1e-3) {
-    p1 = 1.0 - z / 2 + z * z / 6 - z * z * z / 24;
-    p2 = 0.5 - z / 6 + z * z / 24 - z * z * z / 120;
-  } else {
-    p1 = -expm1(-z) / z;
-    p2 = (z - 1.0 + e) / (z * z);
-  }
-  f[0] = float(log(z) / 8.0);
-  f[1] = float(e);
-  f[2] = float(p1);
-  f[3] = float(2.0 * p2);
-}
-
 __global__ void k_rows_write(RowsArgs a, const double *smax, double rel, const int64_t *offsets,
-                             int64_t max_rows, float *x, float *tg) {
+                             int64_t max_rows, float *x, float *tg, float *scale_out) {
   __shared__ int sc[4];
   const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
   bool q = false;
   double g[PE_MLP_SAMPLES];
   double sg = 0.0;
   if (row < a.total) {
-    sg = rows_sigma(a, row, g);
+    sg = rows_scale(a, row, g);
     q = sg > rel * (*smax) && sg > 0.0;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -171,14 +177,14 @@ __global__ void k_rows_write(RowsArgs a, const double *smax, double rel, const i
     lam = a.lam0[rr / a.n1] + a.lam1[rr % a.n1] + a.lam2[k2];
   }
   float f[PE_MLP_INPUTS];
-  zfeat(a.D * lam * a.dT, f);
-  for (int s = 0; s < PE_MLP_SAMPLES; ++s) f[4 + s] = float(g[s] / sg);
+  mode_features(a.D * lam * a.dT, g, a.B, f, sg);
   for (int i = 0; i < PE_MLP_INPUTS; ++i) x[pos * PE_MLP_INPUTS + i] = f[i];
   const double Rv = a.fp64 ? static_cast<const double *>(a.R)[row]
                            : double(static_cast<const float *>(a.R)[row]);
   const double rv = a.fp64 ? static_cast<const double *>(a.r)[row]
                            : double(static_cast<const float *>(a.r)[row]);
   tg[pos] = float((Rv - rv) / (sg * a.dT));
+  if (scale_out) scale_out[pos] = float(sg);
 }
 
 static RowsArgs rows_args(pe_grid g, int N, double dT, const void *S, const void *R, const void *r) {
@@ -198,6 +204,7 @@ static RowsArgs rows_args(pe_grid g, int N, double dT, const void *S, const void
   a.fp64 = g->precision == PE_FP64;
   a.dof = g->dof;
   a.total = int64_t(N) * g->dof;
+  a.B = sample_basis();
   return a;
 }
 
@@ -273,8 +280,8 @@ size_t pe_learned_rows_workspace_bytes(pe_grid g, int32_t n_slices) {
 
 pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double dT, const void *d_samples,
                           const void *d_R, const void *d_r, double rel_thresh, float *d_x,
-                          float *d_t, int64_t max_rows, int64_t *h_count, void *d_work,
-                          size_t work_bytes, void *stream) {
+                          float *d_t, float *d_s, int64_t max_rows, int64_t *h_count,
+                          void *d_work, size_t work_bytes, void *stream) {
   clear_error();
   if (!g || !d_samples || !d_R || !d_r || !d_x || !d_t || !h_count || !d_work)
     return set_error(PE_E_ARG, "null argument");
@@ -299,7 +306,7 @@ pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double dT, const void *d_
   k_rows_max_final<<<1, 1, 0, st>>>(part, int(mb), smax);
   k_rows_count<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, counts);
   k_rows_scan<<<1, 64, 0, st>>>(counts, int(blocks), offsets, total);
-  k_rows_write<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, offsets, max_rows, d_x, d_t);
+  k_rows_write<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, offsets, max_rows, d_x, d_t, d_s);
   PE_HIP(hipGetLastError());
   PE_HIP(hipMemcpyAsync(h_count, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   PE_HIP(hipStreamSynchronize(st));

@@ -108,23 +108,6 @@ __device__ inline void load_weights(WeightsLds &w, const uint16_t *packed, const
   if (threadIdx.x == 0) w.b4 = master[OB4];
 }
 
-// z-features in FP64: [ln z / 8, e^{-z}, phi_1(-z), 2 phi_2(-z)]
-__device__ inline void z_features(double z, float *f) {
-  const double e = exp(-z);
-  double p1, p2;
-  if (z < 1e-3) {
-    p1 = 1.0 - z / 2 + z * z / 6 - z * z * z / 24;
-    p2 = 0.5 - z / 6 + z * z / 24 - z * z * z / 120;
-  } else {
-    p1 = -expm1(-z) / z;
-    p2 = (z - 1.0 + e) / (z * z);
-  }
-  f[0] = float(log(z) / 8.0);
-  f[1] = float(e);
-  f[2] = float(p1);
-  f[3] = float(2.0 * p2);
-}
-
 struct MlpRowSrc {
   // rows from ready-made inputs
   const float *x;          // [rows][12] or null
@@ -135,13 +118,14 @@ struct MlpRowSrc {
   const void *samples;     // [8N][DOF] state dtype
   int fp64;
   int64_t dof;
+  SampleBasis B;
 };
 
-// Feature row -> x[12] (fp32) and sigma; returns false when the row is empty.
-__device__ inline void row_features(const MlpRowSrc &s, int64_t row, float *x, double &sigma) {
+// Feature row -> x[12] (fp32) and the output scale s.
+__device__ inline void row_features(const MlpRowSrc &s, int64_t row, float *x, double &scale) {
   if (s.x) {
     for (int i = 0; i < NIN; ++i) x[i] = s.x[row * NIN + i];
-    sigma = 1.0;
+    scale = 1.0;
     return;
   }
   const int64_t n = row / s.dof, k = row - n * s.dof;
@@ -155,17 +139,25 @@ __device__ inline void row_features(const MlpRowSrc &s, int64_t row, float *x, d
     lam = s.lam0[r / s.n1] + s.lam1[r % s.n1] + s.lam2[k2];
   }
   double g[PE_MLP_SAMPLES];
-  double sg = 0.0;
   for (int q = 0; q < PE_MLP_SAMPLES; ++q) {
     const int64_t o = (n * PE_MLP_SAMPLES + q) * s.dof + k;
     g[q] = s.fp64 ? static_cast<const double *>(s.samples)[o]
                   : double(static_cast<const float *>(s.samples)[o]);
-    sg = fmax(sg, fabs(g[q]));
   }
-  z_features(s.D * lam * s.dT, x);
-  const double inv = sg > 0.0 ? 1.0 / sg : 0.0;
-  for (int q = 0; q < PE_MLP_SAMPLES; ++q) x[4 + q] = float(g[q] * inv);
-  sigma = sg;
+  mode_features(s.D * lam * s.dT, g, s.B, x, scale);
+}
+
+// First-layer input tile: x = hi + lo (both bf16) in columns [0, 12) and
+// [12, 24); the packed W1t repeats its 12 input columns there, so the
+// product sees the fp32 input (to about 2^-16 relative).
+__device__ inline void put_input(uint16_t *X, const float *x, bool ok) {
+  for (int i = 0; i < NIN; ++i) {
+    const float v = ok ? x[i] : 0.f;
+    const uint16_t hi = f2bf(v);
+    X[i] = hi;
+    X[NIN + i] = f2bf(v - bf2f(hi));
+  }
+  for (int i = 2 * NIN; i < KIN; ++i) X[i] = 0;
 }
 
 // --------------------------------------------------------------- inference
@@ -181,7 +173,7 @@ __global__ __launch_bounds__(MNT) void k_mlp_infer(const uint16_t *packed, const
   __shared__ WeightsLds w;
   __shared__ uint16_t X[ROWS][LD1];
   __shared__ uint16_t H1[ROWS][LD2], H2[ROWS][LD2];
-  __shared__ float sig[ROWS];
+  __shared__ double sig[ROWS];
   load_weights(w, packed, master);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
   const int64_t ntiles = (rows + ROWS - 1) / ROWS;
@@ -191,13 +183,10 @@ __global__ __launch_bounds__(MNT) void k_mlp_infer(const uint16_t *packed, const
       const int64_t row = tile * ROWS + t;
       float x[NIN];
       double sg = 0.0;
-      if (row < rows) {
-        row_features(src, row, x, sg);
-      } else {
-        for (int i = 0; i < NIN; ++i) x[i] = 0.f;
-      }
-      for (int i = 0; i < KIN; ++i) X[t][i] = i < NIN ? f2bf(x[i]) : uint16_t(0);
-      sig[t] = float(sg);
+      const bool ok = row < rows;
+      if (ok) row_features(src, row, x, sg);
+      put_input(&X[t][0], x, ok);
+      sig[t] = sg;
     }
     __syncthreads();
     const int r0 = wave * 16;
@@ -285,12 +274,9 @@ __global__ __launch_bounds__(MNT) void k_mlp_train(const uint16_t *packed, const
     if (t < ROWS) {
       const int64_t row = base + t;
       const bool ok = row < end;
-      for (int i = 0; i < KIN; ++i) {
-        const float v = (ok && i < NIN) ? x[row * NIN + i] : 0.f;
-        const uint16_t b = f2bf(v);
-        s.X[t][i] = b;
-        s.XT[i][t] = b;
-      }
+      put_input(&s.X[t][0], ok ? x + row * NIN : nullptr, ok);
+      // the weight gradient of layer 1 uses the hi part of the inputs
+      for (int i = 0; i < KIN; ++i) s.XT[i][t] = i < NIN ? s.X[t][i] : uint16_t(0);
       s.tgt[t] = ok ? tg[row] : 0.f;
     }
     __syncthreads();
@@ -459,7 +445,8 @@ __global__ void k_mlp_pack(const float *w, uint16_t *pk) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < WD * KIN) {
     const int o = e / KIN, i = e % KIN;
-    pk[PW1T + e] = i < NIN ? f2bf(w[OW1 + i * WD + o]) : uint16_t(0);
+    const int ii = i < NIN ? i : i - NIN;   // columns [12, 24) repeat [0, 12)
+    pk[PW1T + e] = i < 2 * NIN ? f2bf(w[OW1 + ii * WD + o]) : uint16_t(0);
   }
   if (e < WD * WD) {
     const int a = e / WD, b = e % WD;
@@ -620,6 +607,7 @@ pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double dT
   src.dT = dT;
   src.samples = d_samples;
   src.fp64 = g->precision == PE_FP64;
+  src.B = sample_basis();
   src.dof = g->dof;
   InferOut out{};
   out.corr = d_corr;

@@ -195,4 +195,55 @@ struct TimedScope {
   }
 };
 
+// ---------------------------------------------------------------- learned G
+// Orthonormal polynomial basis of the eight forcing sample times of a slice
+// (points t_j = (j - 3.5)/3.5): q[j * 8 + i] = q_i(t_j).  Built on the host.
+struct SampleBasis {
+  double q[PE_MLP_SAMPLES * PE_MLP_SAMPLES];
+};
+SampleBasis sample_basis();
+
+// Network inputs of one (slice, mode): x[12] and the output scale s (the
+// norm of the degree >= 4 coefficients of the samples g[8]).
+__device__ inline void mode_features(double z, const double *g, const SampleBasis &B, float *x,
+                                     double &s) {
+  const double e = exp(-z);
+  double p1, p2;
+  if (z < 1e-3) {
+    p1 = 1.0 - z / 2 + z * z / 6 - z * z * z / 24;
+    p2 = 0.5 - z / 6 + z * z / 24 - z * z * z / 120;
+  } else {
+    p1 = -expm1(-z) / z;
+    p2 = (z - 1.0 + e) / (z * z);
+  }
+  x[0] = float(log(z) / 8.0);
+  x[1] = float(e);
+  x[2] = float(p1);
+  x[3] = float(2.0 * p2);
+  double c[PE_MLP_SAMPLES], gn = 0.0, hn = 0.0;
+  for (int i = 0; i < PE_MLP_SAMPLES; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < PE_MLP_SAMPLES; ++j) a += B.q[j * PE_MLP_SAMPLES + i] * g[j];
+    c[i] = a;
+    gn += g[i] * g[i];
+    if (i >= 4) hn += a * a;
+  }
+  gn = sqrt(gn);
+  s = sqrt(hn);
+  const double ig = gn > 0.0 ? 1.0 / gn : 0.0, ih = s > 0.0 ? 1.0 / s : 0.0;
+  for (int i = 0; i < 4; ++i) x[4 + i] = float(c[i] * ig);
+  for (int i = 4; i < PE_MLP_SAMPLES; ++i) x[4 + i] = float(c[i] * ih);
+}
+
+// Output scale alone (row selection).
+__device__ inline double mode_scale(const double *g, const SampleBasis &B) {
+  double hn = 0.0;
+  for (int i = 4; i < PE_MLP_SAMPLES; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < PE_MLP_SAMPLES; ++j) a += B.q[j * PE_MLP_SAMPLES + i] * g[j];
+    hn += a * a;
+  }
+  return sqrt(hn);
+}
+
 }  // namespace pe

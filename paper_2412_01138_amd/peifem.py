@@ -137,7 +137,7 @@ def load_library():
     L.pe_learned_samples.argtypes = [vp, i32, dbl, dbl, vp, vp, sz, vp]
     L.pe_learned_rows_workspace_bytes.argtypes = [vp, i32]
     L.pe_learned_rows_workspace_bytes.restype = sz
-    L.pe_learned_rows.argtypes = [vp, i32, dbl, vp, vp, vp, dbl, vp, vp, i64,
+    L.pe_learned_rows.argtypes = [vp, i32, dbl, vp, vp, vp, dbl, vp, vp, vp, i64,
                                   ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
     L.pe_learned_correction.argtypes = [vp, vp, i32, dbl, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
     L.pe_last_error.argtypes = []
@@ -319,22 +319,28 @@ class Grid:
         return out
 
     def learned_rows(self, samples, R, r, dT: float, rel_thresh: float = 1e-9,
-                     max_rows: Optional[int] = None):
-        """Training rows (x [rows, 12], target [rows]) of the modes whose
-        forcing samples do not vanish."""
+                     max_rows: Optional[int] = None, want_scale: bool = False):
+        """Training rows (x [rows, 12], target [rows], count) of the modes
+        whose forcing samples have a part of degree >= 4; with want_scale the
+        rows' output scales s [rows] come third."""
         import torch
         N = R.shape[0]
         if max_rows is None:
             max_rows = N * self.dof
         x = torch.empty((max(max_rows, 1), PE_MLP_INPUTS), dtype=torch.float32, device=self.device)
         t = torch.empty(max(max_rows, 1), dtype=torch.float32, device=self.device)
+        sc = (torch.empty(max(max_rows, 1), dtype=torch.float32, device=self.device)
+              if want_scale else None)
         work = self.workspace(self.L.pe_learned_rows_workspace_bytes(self.h, N))
         cnt = ctypes.c_int64(0)
         _check(self.L.pe_learned_rows(self.h, N, float(dT), _ptr(samples), _ptr(R), _ptr(r),
-                                      float(rel_thresh), _ptr(x), _ptr(t), int(max_rows),
+                                      float(rel_thresh), _ptr(x), _ptr(t), _ptr(sc),
+                                      int(max_rows),
                                       ctypes.byref(cnt), _ptr(work), work.numel(),
                                       _stream(self.stream)))
         n = min(int(cnt.value), max_rows)
+        if want_scale:
+            return x[:n], t[:n], sc[:n], int(cnt.value)
         return x[:n], t[:n], int(cnt.value)
 
     def learned_correction(self, mlp: "Mlp", samples, N: int, dT: float, out=None):

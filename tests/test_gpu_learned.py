@@ -58,12 +58,30 @@ def test_mlp_forward_matches_oracle():
     pe = _pe()
     theta = bf16_params(1)
     x, _ = _rows(2, 1000)
-    x = omlp.to_bf16(x)                       # inputs enter the matrix cores as bf16
+    x = x.astype(np.float32).astype(np.float64)
     m = pe.Mlp(theta)
     y = m.forward(_dev(x)).cpu().numpy()
     ref = omlp.forward(theta, x)
     assert np.max(np.abs(y - ref)) <= 2e-2 * np.max(np.abs(ref))
     assert rel(y, ref) <= 2e-2
+
+
+def test_mlp_first_layer_sees_fp32_inputs():
+    """Inputs that round to the same bf16 value still give different outputs:
+    z1 = 64 (x_0 - 1) is exact in bf16 for x_0 = 1 and 1 + 2^-12."""
+    pe = _pe()
+    P = omlp.unpack(bf16_params(3).copy())
+    P["W1"][:] = 0.0
+    P["W1"][0, :] = 64.0
+    P["b1"][:] = -64.0
+    theta = omlp.pack(P)
+    x = np.zeros((2, omlp.N_IN))
+    x[:, 0] = [1.0, 1.0 + 2.0 ** -12]
+    assert omlp.to_bf16(x[1, 0]) == 1.0
+    y = pe.Mlp(theta).forward(_dev(x)).cpu().numpy()
+    ref = omlp.forward(theta, x)
+    assert abs(ref[1] - ref[0]) > 1e-3 * max(abs(ref[0]), 1e-30)
+    assert abs((y[1] - y[0]) - (ref[1] - ref[0])) <= 2e-2 * abs(ref[1] - ref[0])
 
 
 @pytest.mark.parametrize("rows", [1, 63, 1000, 70000])
@@ -131,7 +149,7 @@ def test_learned_rows_match_oracle():
     r = torch.empty((prob.N,) + prob.n, dtype=torch.float64, device="cuda:0")
     g.coarse_sweep(U, prob.t0, prob.dT, prob.c_coarse, EG, BG, r)
     S = g.learned_samples(prob.N, prob.t0, prob.dT)
-    x, t, count = g.learned_rows(S, R, r, prob.dT, rel_thresh=1e-9)
+    x, t, sc, count = g.learned_rows(S, R, r, prob.dT, rel_thresh=1e-9, want_scale=True)
     # oracle rows in (n, k) order
     d = Discretization(prob)
     tF, tG = d.tables(prob.dt, prob.c_fine), d.tables(prob.dT, prob.c_coarse)
@@ -146,15 +164,17 @@ def test_learned_rows_match_oracle():
         samples_all.append(smp)
         xn, sg = omlp.features(z, smp)
         xs.append((xn, sg, (Rn - rn)))
-    smax = max(np.max(np.abs(s)) for s in samples_all)
-    X, T = [], []
+    smax = max(np.max(sg) for _, sg, _ in xs)
+    X, T, SC = [], [], []
     for xn, sg, dlt in xs:
-        keep = sg > 1e-9 * smax
+        keep = (sg > 1e-9 * smax) & (sg > 0)
         X.append(xn[keep])
         T.append(dlt[keep] / (sg[keep] * prob.dT))
-    X, T = np.concatenate(X), np.concatenate(T)
+        SC.append(sg[keep])
+    X, T, SC = np.concatenate(X), np.concatenate(T), np.concatenate(SC)
     assert count == len(T)
     np.testing.assert_allclose(x.cpu().numpy(), X, rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(sc.cpu().numpy(), SC, rtol=1e-6)
     assert rel(t.cpu().numpy(), T) <= 1e-5
 
 
@@ -197,3 +217,28 @@ def test_learned_correction_falls_back_on_non_finite_network():
     assert rep_learn.fallback == 1
     assert rep_learn.jumps[0] == rep_plain.jumps[0]
     np.testing.assert_array_equal(U_learn.cpu().numpy(), U_plain.cpu().numpy())
+
+
+def test_trained_network_cuts_the_coarse_error():
+    """Train on seeded forcings of one family with the library's own kernels,
+    then solve an unseen forcing of that family: the learned correction cuts
+    the first jump (the coarse solution's error) at least 20-fold and leaves
+    the converged answer unchanged."""
+    pe = _pe()
+    from paper_2412_01138_amd import learned_g as lg
+    base = wl.tiny_problem(2, (31, 31), seed=8, s=4, N=32, J=8, D=0.01, T=0.5, u0_modes=0)
+    fam = (12, 5.0, 50.0, 16)
+    X, T, S = lg.training_rows(base, range(100, 164), family=fam)
+    assert X.shape[0] > 10000
+    W = lg.row_weights(X, S, base.N, 0.0)
+    m, _ = lg.train(X, T, 4000, batch=4096, lr=2e-3, weights=W)
+    box = list(zip(base.lo, base.hi))
+    prob = base.with_(forcing=wl.random_forcing(999, 2, fam[0], box, fam[1], fam[2], kmax=fam[3]))
+    _, U_plain, rep_plain = pe.solve_problem(prob, K_max=2, tol=0.0)
+    _, U_learn, rep_learn = pe.solve_problem(prob, K_max=2, tol=0.0, mlp=m)
+    assert rep_learn.fallback == 0
+    gain = rep_plain.jumps[0] / rep_learn.jumps[0]
+    print(f"first jump: plain {rep_plain.jumps[0]:.3e}, learned {rep_learn.jumps[0]:.3e}, "
+          f"gain {gain:.1f}")
+    assert gain >= 20.0
+    assert rel(U_learn.cpu().numpy(), U_plain.cpu().numpy()) <= 1e-13

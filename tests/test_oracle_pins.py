@@ -450,14 +450,25 @@ def test_mlp_gelu_and_features():
             p2 = (zz - 1 + mp.exp(-zz)) / zz ** 2
         assert abs(f[k, 2] - float(p1)) <= 1e-14 * float(p1)
         assert abs(f[k, 3] - 2 * float(p2)) <= 1e-13 * 2 * float(p2)
-    # sigma normalisation: features of a scaled sample row are unchanged
-    s = np.random.default_rng(1).normal(size=(3, 8))
-    x1, sg1 = mlp.features(np.full(3, 0.3), s)
-    x2, sg2 = mlp.features(np.full(3, 0.3), 1e-7 * s)
-    np.testing.assert_allclose(x1, x2, rtol=1e-13)
-    np.testing.assert_allclose(sg2, 1e-7 * sg1, rtol=1e-15)
-    # the correction vanishes with the forcing
+    # scaling the samples leaves the inputs unchanged and scales s
+    smp = np.random.default_rng(1).normal(size=(3, 8))
+    x1, s1 = mlp.features(np.full(3, 0.3), smp)
+    x2, s2 = mlp.features(np.full(3, 0.3), 1e-7 * smp)
+    np.testing.assert_allclose(x1, x2, rtol=1e-12)
+    np.testing.assert_allclose(s2, 1e-7 * s1, rtol=1e-13)
+    # the basis is orthonormal and polynomial: q_j has degree j
+    Q = mlp.sample_basis()
+    np.testing.assert_allclose(Q.T @ Q, np.eye(8), atol=1e-14)
+    t = (np.arange(8) - 3.5) / 3.5
+    for deg in range(4):
+        c = (t ** deg) @ Q
+        assert np.max(np.abs(c[deg + 1:])) <= 1e-13 and c[deg] > 0
+    # samples of a cubic in time have no high part: s = 0 and no correction
+    cub = 0.3 - 1.2 * t + 0.7 * t ** 3
+    _, s_cub = mlp.features(np.array([0.5]), cub[None, :])
+    assert s_cub[0] <= 1e-14
     theta = mlp.init_params(0)
+    assert np.all(np.abs(mlp.correction(theta, np.full(1, 0.3), cub[None, :], 0.1)) <= 1e-14)
     assert np.all(mlp.correction(theta, np.full(2, 0.3), np.zeros((2, 8)), 0.1) == 0.0)
 
 
