@@ -237,25 +237,31 @@ size_t pe_learned_samples_workspace_bytes(pe_grid g, int32_t n_slices);
 pe_status pe_learned_samples(pe_grid g, int32_t n_slices, double t0, double dT, void *d_samples,
                              void *d_work, size_t work_bytes, void *stream);
 
-/* Training rows from one solve's responses: for every (n, k) with
+/* Training rows of slices n = 0..N-1 starting at t0: for every (n, k) with
  * s > rel_thresh * max s, write x (12 floats) and the target
  * (R - r)_{n,k} / (s dT) to d_x / d_t and s to d_s (nullable), in (n, k)
- * order, at most max_rows;
- * *h_count (host) receives the number of qualifying rows (it can exceed
- * max_rows: only the first max_rows are written).  d_R, d_r: [N][DOF].
- * Needs pe_learned_rows_workspace_bytes(g, N) of d_work.  Synchronises. */
+ * order, at most max_rows; *h_count (host) receives the number of
+ * qualifying rows (it can exceed max_rows: only the first max_rows are
+ * written).  d_R, d_r: [N][DOF] (state dtype).  The inputs are formed from
+ * the forcing set on the grid (term spectra and time factors; no samples
+ * buffer).  Needs pe_learned_rows_workspace_bytes(g, N) of d_work.
+ * Synchronises. */
 size_t pe_learned_rows_workspace_bytes(pe_grid g, int32_t n_slices);
-pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double dT, const void *d_samples,
-                          const void *d_R, const void *d_r, double rel_thresh, float *d_x,
-                          float *d_t, float *d_s, int64_t max_rows, int64_t *h_count,
-                          void *d_work, size_t work_bytes, void *stream);
+pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double t0, double dT, const void *d_R,
+                          const void *d_r, double rel_thresh, float *d_x, float *d_t, float *d_s,
+                          int64_t max_rows, int64_t *h_count, void *d_work, size_t work_bytes,
+                          void *stream);
 
-/* delta_n for every slice and mode into d_corr[N][DOF] (state dtype).  If
- * the network produces a non-finite value anywhere, d_corr is zeroed (plain
- * coarse step) and *h_fallback (host, nullable) is set to 1.  Synchronises. */
-pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double dT,
-                                const void *d_samples, void *d_corr, int32_t *h_fallback,
-                                void *stream);
+/* delta_n for slices n = 0..N-1 starting at t0 and every mode into
+ * d_corr[N][DOF] (state dtype), from the forcing set on the grid.  If the
+ * network produces a non-finite value anywhere, d_corr is zeroed (plain
+ * coarse step) and *h_fallback (host, nullable) is set to 1.  Needs
+ * pe_learned_correction_workspace_bytes(g, N) of d_work (N * 8 * n_terms
+ * doubles).  Synchronises.  Errors: PE_E_ARG, PE_E_WORKSPACE, PE_E_HIP. */
+size_t pe_learned_correction_workspace_bytes(pe_grid g, int32_t n_slices);
+pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double t0, double dT,
+                                void *d_corr, int32_t *h_fallback, void *d_work,
+                                size_t work_bytes, void *stream);
 
 /* Parareal driver (paper Algorithm 1).  Stopping rule (the paper leaves it
  * open): after iteration k the relative jump

@@ -31,9 +31,7 @@ __global__ void k_time_coefs(FieldBatch b, const DevTerm *terms, int n_terms, do
   int j = b.j0 + rem / b.s;
   int i = rem - (rem / b.s) * b.s;
   double t = ((b.t0 + double(n) * b.dT) + double(j) * b.dt) + b.c[i] * b.dt;
-  DevTerm tm = terms[m];
-  double poly = tm.p[0] + t * (tm.p[1] + t * (tm.p[2] + t * tm.p[3]));
-  coef[idx] = tm.amp * exp(tm.alpha * t) * cos(tm.omega * t + tm.phase) * poly;
+  coef[idx] = term_time(terms[m], t);
   }
 }
 

@@ -82,6 +82,23 @@ __global__ void k_dst_half(int n, int Kh, int H, double *Sh, double *ShT, uint16
   }
 }
 
+// spec[m][k] = sig(k) sum_j S[k][j] C[m][j]: the spectral 1D load of each
+// term on one axis (S the orthonormal sine basis, exact angle reduction).
+__global__ void k_axis_spectra(const double *C, int np, int n, const double *sig, int n_terms,
+                               double *spec) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (k >= n || m >= n_terms) return;
+  const double *c = C + size_t(m) * np;
+  const long long per = 2LL * (n + 1);
+  double acc = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const long long a = (long long)(k + 1) * (j + 1) % per;
+    acc += sinpi(double(a) / double(n + 1)) * c[j];
+  }
+  spec[size_t(m) * n + k] = sig[k] * sqrt(2.0 / (n + 1)) * acc;
+}
+
 // Cf[h][m][p]: the even/odd fold of the last-axis 1D load table C[m][j].
 __global__ void k_fold_table(const double *C, int np, int n, int H, int Kh, int n_terms,
                              double *Cf) {
@@ -253,6 +270,7 @@ static void free_grid_tables(pe_grid g) {
     hipFree(g->ax[a].d_Shi);
     hipFree(g->ax[a].d_Slo);
     hipFree(g->d_C[a]);
+    hipFree(g->d_spec[a]);
   }
   hipFree(g->d_terms);
   hipFree(g->d_Cf);
@@ -430,6 +448,8 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
   for (int a = 0; a < PE_MAX_DIM; ++a) {
     hipFree(g->d_C[a]);
     g->d_C[a] = nullptr;
+    hipFree(g->d_spec[a]);
+    g->d_spec[a] = nullptr;
   }
   hipFree(g->d_terms);
   g->d_terms = nullptr;
@@ -447,6 +467,14 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
   const Axis &last = g->ax[g->dim - 1];
   PE_HIP(hipMalloc(&g->d_Cf, sizeof(double) * 2 * size_t(n_terms) * last.Kh));
   PE_TRY(fold_table(g, g->d_C[g->dim - 1], n_terms, g->d_Cf, st));
+  for (int a = 0; a < g->dim; ++a) {
+    const Axis &ax = g->ax[a];
+    PE_HIP(hipMalloc(&g->d_spec[a], sizeof(double) * size_t(n_terms) * ax.n));
+    k_axis_spectra<<<dim3((ax.n + 127) / 128, n_terms), 128, 0, st>>>(g->d_C[a], ax.np, ax.n,
+                                                                      ax.d_sig, n_terms,
+                                                                      g->d_spec[a]);
+    PE_HIP(hipGetLastError());
+  }
   PE_HIP(hipStreamSynchronize(st));
   return PE_OK;
 }

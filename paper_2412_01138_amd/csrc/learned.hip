@@ -1,13 +1,15 @@
-// Learned coarse correction: forcing samples, training rows, correction.
+// Learned coarse correction: forcing samples, training rows.
 //
 // The network input of slice n and mode k uses the spectral forcing at the
-// eight times T_n + s dT / 7 (s = 0..7).  They are produced like the stage
-// fields of a fine pass (quadrature of the load vector + per-axis transform)
-// and stored in natural mode order.  Training rows pair those inputs with
-// the target (R_n - r_n)_k / (s dT), R_n = F^J(0) and r_n = G(0) of the
-// same slice, s the size of the samples' part of degree >= 4; rows where it
-// vanishes carry no information and are skipped (ordered, deterministic
-// compaction).
+// eight times T_n + j dT / 7 (j = 0..7), expanded in orthonormal polynomials
+// of those times.  The forcing is a sum of separable terms, so these
+// coefficients come from the per-axis term spectra and a small per-slice
+// table (learned_coefs) with no field transform.  pe_learned_samples still
+// produces the samples themselves like the stage fields of a fine pass
+// (quadrature + transform).  Training rows pair the inputs with the target
+// (R_n - r_n)_k / (s dT), R_n = F^J(0) and r_n = G(0) of the same slice, s the
+// size of the samples' part of degree >= 4; rows where it vanishes carry no
+// information and are skipped (ordered, deterministic compaction).
 #include <algorithm>
 #include <cmath>
 
@@ -75,25 +77,78 @@ static size_t sample_field_bytes(pe_grid g) {
   return 2 * field_bytes(g) + sizeof(double) * size_t(std::max(g->n_terms, 1));
 }
 
+// ---------------------------------------------------- sample coefficients
+__global__ void k_learned_coefs(int N, double t0, double dT, const DevTerm *terms, int M,
+                                SampleBasis B, double *Cp) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(N) * PE_MLP_SAMPLES * M) return;
+  const int m = int(idx % M);
+  const int i = int((idx / M) % PE_MLP_SAMPLES);
+  const int n = int(idx / (int64_t(M) * PE_MLP_SAMPLES));
+  const DevTerm tm = terms[m];
+  double acc = 0.0;
+  for (int j = 0; j < PE_MLP_SAMPLES; ++j) {
+    const double t = (t0 + double(n) * dT) + (double(j) / 7.0) * dT;
+    acc += B.q[j * PE_MLP_SAMPLES + i] * term_time(tm, t);
+  }
+  Cp[idx] = acc;
+}
+
+size_t learned_coef_bytes(pe_grid g, int N) {
+  return Arena::need(sizeof(double) * size_t(N) * PE_MLP_SAMPLES * std::max(g->n_terms, 1));
+}
+
+pe_status learned_coefs(pe_grid g, int N, double t0, double dT, double *Cp, hipStream_t st) {
+  const int64_t tot = int64_t(N) * PE_MLP_SAMPLES * g->n_terms;
+  if (tot == 0) return PE_OK;
+  k_learned_coefs<<<unsigned((tot + 255) / 256), 256, 0, st>>>(N, t0, dT, g->d_terms, g->n_terms,
+                                                               sample_basis(), Cp);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
 // ------------------------------------------------------------ training rows
 struct RowsArgs {
-  int d, n0, n1, n2;
+  int d, n0, n1, n2, M;
   const double *lam0, *lam1, *lam2;
+  const double *sp0, *sp1, *sp2;   // per-axis term spectra [M][n_a]
+  const double *Cp;                // [N][8][M]
   double D, dT;
-  const void *samples, *R, *r;
+  const void *R, *r;
   int fp64;
   int64_t dof, total;
-  SampleBasis B;
 };
 
-__device__ inline double rows_scale(const RowsArgs &a, int64_t row, double *g) {
+// Polynomial coefficients c[8] of the forcing samples of row (n, k).
+__device__ inline void row_coeffs(const RowsArgs &a, int64_t row, double *c) {
   const int64_t n = row / a.dof, k = row - n * a.dof;
-  for (int q = 0; q < PE_MLP_SAMPLES; ++q) {
-    const int64_t o = (n * PE_MLP_SAMPLES + q) * a.dof + k;
-    g[q] = a.fp64 ? static_cast<const double *>(a.samples)[o]
-                  : double(static_cast<const float *>(a.samples)[o]);
+  int k0 = 0, k1 = 0, k2 = 0;
+  if (a.d == 1) {
+    k0 = int(k);
+  } else if (a.d == 2) {
+    k0 = int(k / a.n1);
+    k1 = int(k % a.n1);
+  } else {
+    k2 = int(k % a.n2);
+    const int64_t r = k / a.n2;
+    k0 = int(r / a.n1);
+    k1 = int(r % a.n1);
   }
-  return mode_scale(g, a.B);
+  for (int i = 0; i < PE_MLP_SAMPLES; ++i) c[i] = 0.0;
+  const double *cp = a.Cp + n * PE_MLP_SAMPLES * a.M;
+  for (int m = 0; m < a.M; ++m) {
+    double G = a.sp0[int64_t(m) * a.n0 + k0];
+    if (a.d > 1) G *= a.sp1[int64_t(m) * a.n1 + k1];
+    if (a.d > 2) G *= a.sp2[int64_t(m) * a.n2 + k2];
+    for (int i = 0; i < PE_MLP_SAMPLES; ++i) c[i] += cp[i * a.M + m] * G;
+  }
+}
+
+__device__ inline double row_scale(const RowsArgs &a, int64_t row, double *c) {
+  row_coeffs(a, row, c);
+  double hn = 0.0;
+  for (int i = 4; i < PE_MLP_SAMPLES; ++i) hn += c[i] * c[i];
+  return sqrt(hn);
 }
 
 __global__ void k_rows_max(RowsArgs a, double *part) {
@@ -101,8 +156,8 @@ __global__ void k_rows_max(RowsArgs a, double *part) {
   double mx = 0.0;
   for (int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x; row < a.total;
        row += int64_t(gridDim.x) * 256) {
-    double g[PE_MLP_SAMPLES];
-    mx = fmax(mx, rows_scale(a, row, g));
+    double c[PE_MLP_SAMPLES];
+    mx = fmax(mx, row_scale(a, row, c));
   }
   sm[threadIdx.x] = mx;
   __syncthreads();
@@ -125,8 +180,8 @@ __global__ void k_rows_count(RowsArgs a, const double *smax, double rel, int *co
   const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
   bool q = false;
   if (row < a.total) {
-    double g[PE_MLP_SAMPLES];
-    const double sg = rows_scale(a, row, g);
+    double c[PE_MLP_SAMPLES];
+    const double sg = row_scale(a, row, c);
     q = sg > rel * (*smax) && sg > 0.0;
   }
   const unsigned long long bal = __ballot(q);
@@ -151,10 +206,10 @@ __global__ void k_rows_write(RowsArgs a, const double *smax, double rel, const i
   __shared__ int sc[4];
   const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
   bool q = false;
-  double g[PE_MLP_SAMPLES];
+  double c[PE_MLP_SAMPLES];
   double sg = 0.0;
   if (row < a.total) {
-    sg = rows_scale(a, row, g);
+    sg = row_scale(a, row, c);
     q = sg > rel * (*smax) && sg > 0.0;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -166,18 +221,11 @@ __global__ void k_rows_write(RowsArgs a, const double *smax, double rel, const i
   const int local = before + __popcll(bal & ((1ull << lane) - 1ull));
   const int64_t pos = offsets[blockIdx.x] + local;
   if (!q || pos >= max_rows) return;
-  const int64_t n = row / a.dof, k = row - n * a.dof;
-  double lam;
-  if (a.d == 1) {
-    lam = a.lam0[k];
-  } else if (a.d == 2) {
-    lam = a.lam0[k / a.n1] + a.lam1[k % a.n1];
-  } else {
-    const int64_t k2 = k % a.n2, rr = k / a.n2;
-    lam = a.lam0[rr / a.n1] + a.lam1[rr % a.n1] + a.lam2[k2];
-  }
+  const int64_t k = row % a.dof;
+  const double lam = mode_lambda(a.d, a.n1, a.n2, a.lam0, a.lam1, a.lam2, k);
   float f[PE_MLP_INPUTS];
-  mode_features(a.D * lam * a.dT, g, a.B, f, sg);
+  z_features(a.D * lam * a.dT, f);
+  coeff_features(c, f, sg);
   for (int i = 0; i < PE_MLP_INPUTS; ++i) x[pos * PE_MLP_INPUTS + i] = f[i];
   const double Rv = a.fp64 ? static_cast<const double *>(a.R)[row]
                            : double(static_cast<const float *>(a.R)[row]);
@@ -187,24 +235,28 @@ __global__ void k_rows_write(RowsArgs a, const double *smax, double rel, const i
   if (scale_out) scale_out[pos] = float(sg);
 }
 
-static RowsArgs rows_args(pe_grid g, int N, double dT, const void *S, const void *R, const void *r) {
+static RowsArgs rows_args(pe_grid g, int N, double dT, const double *Cp, const void *R,
+                          const void *r) {
   RowsArgs a{};
   a.d = g->dim;
+  a.M = g->n_terms;
   a.n0 = g->ax[0].n;
   a.n1 = g->dim > 1 ? g->ax[1].n : 1;
   a.n2 = g->dim > 2 ? g->ax[2].n : 1;
   a.lam0 = g->ax[0].d_lam;
   a.lam1 = g->ax[1].d_lam;
   a.lam2 = g->ax[2].d_lam;
+  a.sp0 = g->d_spec[0];
+  a.sp1 = g->d_spec[1];
+  a.sp2 = g->d_spec[2];
+  a.Cp = Cp;
   a.D = g->D;
   a.dT = dT;
-  a.samples = S;
   a.R = R;
   a.r = r;
   a.fp64 = g->precision == PE_FP64;
   a.dof = g->dof;
   a.total = int64_t(N) * g->dof;
-  a.B = sample_basis();
   return a;
 }
 
@@ -275,38 +327,45 @@ size_t pe_learned_rows_workspace_bytes(pe_grid g, int32_t n_slices) {
   if (!g || n_slices < 1) return 0;
   const int64_t blocks = (int64_t(n_slices) * g->dof + 255) / 256;
   return 8 * 256 + size_t(blocks) * (sizeof(int) + sizeof(int64_t)) + sizeof(double) * 65538 +
-         sizeof(int64_t);
+         sizeof(int64_t) + learned_coef_bytes(g, n_slices);
 }
 
-pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double dT, const void *d_samples,
-                          const void *d_R, const void *d_r, double rel_thresh, float *d_x,
-                          float *d_t, float *d_s, int64_t max_rows, int64_t *h_count,
-                          void *d_work, size_t work_bytes, void *stream) {
+pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double t0, double dT, const void *d_R,
+                          const void *d_r, double rel_thresh, float *d_x, float *d_t, float *d_s,
+                          int64_t max_rows, int64_t *h_count, void *d_work, size_t work_bytes,
+                          void *stream) {
   clear_error();
-  if (!g || !d_samples || !d_R || !d_r || !d_x || !d_t || !h_count || !d_work)
+  if (!g || !d_R || !d_r || !d_x || !d_t || !h_count || !d_work)
     return set_error(PE_E_ARG, "null argument");
-  if (n_slices < 1 || !(dT > 0) || max_rows < 0 || !(rel_thresh >= 0))
+  if (n_slices < 1 || !(dT > 0) || max_rows < 0 || !(rel_thresh >= 0) || !std::isfinite(t0))
     return set_error(PE_E_ARG, "bad arguments");
   if (work_bytes < pe_learned_rows_workspace_bytes(g, n_slices))
     return set_error(PE_E_WORKSPACE, "workspace too small");
   hipStream_t st = as_stream(stream);
-  RowsArgs a = rows_args(g, n_slices, dT, d_samples, d_R, d_r);
+  if (g->n_terms == 0) {
+    *h_count = 0;
+    return PE_OK;
+  }
+  Arena ar(d_work, work_bytes);
+  double *Cp = ar.take<double>(size_t(n_slices) * PE_MLP_SAMPLES * g->n_terms);
+  RowsArgs a = rows_args(g, n_slices, dT, Cp, d_R, d_r);
   const int64_t blocks = (a.total + 255) / 256;
   if (blocks > (int64_t(1) << 24)) return set_error(PE_E_ARG, "too many rows");
-  Arena ar(d_work, work_bytes);
   int *counts = ar.take<int>(blocks);
   int64_t *offsets = ar.take<int64_t>(blocks);
   const unsigned mb = nblk(a.total);
   double *part = ar.take<double>(mb);
   double *smax = ar.take<double>(1);
   int64_t *total = ar.take<int64_t>(1);
-  if (!counts || !offsets || !part || !smax || !total)
+  if (!Cp || !counts || !offsets || !part || !smax || !total)
     return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  PE_TRY(learned_coefs(g, n_slices, t0, dT, Cp, st));
   k_rows_max<<<mb, 256, 0, st>>>(a, part);
   k_rows_max_final<<<1, 1, 0, st>>>(part, int(mb), smax);
   k_rows_count<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, counts);
   k_rows_scan<<<1, 64, 0, st>>>(counts, int(blocks), offsets, total);
-  k_rows_write<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, offsets, max_rows, d_x, d_t, d_s);
+  k_rows_write<<<unsigned(blocks), 256, 0, st>>>(a, smax, rel_thresh, offsets, max_rows, d_x, d_t,
+                                                 d_s);
   PE_HIP(hipGetLastError());
   PE_HIP(hipMemcpyAsync(h_count, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   PE_HIP(hipStreamSynchronize(st));

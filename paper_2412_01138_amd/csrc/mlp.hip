@@ -4,15 +4,22 @@
 // NN: x[12] -> 64 -> 64 -> 64 (GELU: x Phi(x)) -> 1 (linear), parameters
 // W1[12][64] b1 W2[64][64] b2 W3[64][64] b3 w4[64] b4 (W[in][out]).
 //
-// Kernels work on tiles of 64 rows; each of the 4 waves owns 16 rows, so the
-// forward layers need no cross-wave exchange.  Layer l is C = A W: the MFMA
-// A operand is the activation tile (row-major, k contiguous), the B operand
-// the transposed weights Wt[out][in] (k contiguous).  Backward:
+// Layer l is C = A W on 16-row groups: the MFMA A operand is the activation
+// tile (row-major, k contiguous), the B operand the transposed weights
+// Wt[out][in] (k contiguous).  The inputs enter as bf16 hi + lo halves in the
+// 32-wide first-layer tile (W1t repeats its 12 columns), so layer 1 sees the
+// fp32 features.  Backward:
 //   dA_{l-1} = dZ_l W_l^T  (B operand = W_l[in][out] row-major),
 //   dW_l    += A_{l-1}^T dZ_l (A operand = A^T[in][row], B = dZ^T[out][row]),
 // with the row sums of the weight gradients taken on the matrix cores; every
 // block writes its partial gradient, a second kernel adds the partials in a
 // fixed order (bitwise-repeatable gradients).
+//
+// The learned correction (k_mlp_correct) gives each block 64 consecutive
+// modes and walks the slices, one slice per wave at a time: per-mode inputs
+// (z-features, term spectra) are formed once per block, the per-slice ones
+// from the slice's sample-coefficient table.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -30,6 +37,7 @@ constexpr int NP = PE_MLP_PARAMS;    // 9217
 constexpr int OW1 = 0, OB1 = OW1 + NIN * WD, OW2 = OB1 + WD, OB2 = OW2 + WD * WD, OW3 = OB2 + WD,
               OB3 = OW3 + WD * WD, OW4 = OB3 + WD, OB4 = OW4 + WD;
 static_assert(OB4 + 1 == NP, "parameter layout");
+static_assert(2 * NIN <= KIN, "hi/lo inputs fit the first-layer tile");
 
 // packed bf16 weights (global): W1t[64][32], W2t[64][64], W3t[64][64],
 // W2n[64][64], W3n[64][64], w4[64]
@@ -57,14 +65,38 @@ struct pe_mlp_s {
 
 namespace pe {
 
-__device__ inline uint16_t f2bf(float x) {
-  uint32_t u = __float_as_uint(x);
-  return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+// round to nearest even (hardware conversion)
+__device__ inline uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x)); }
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
-__device__ inline float gelu(float x) { return 0.5f * x * erfcf(-x * 0.70710678118654752f); }
+
+// Phi(-|x|) = erfc(|x|/sqrt 2)/2 by the rational approximation of
+// Abramowitz & Stegun 7.1.26 (absolute error of erf below 1.5e-7), and
+// e = exp(-x^2/2), shared with the normal density.
+__device__ inline float normal_tail(float x, float &e) {
+  const float u = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
+                                                                         t * 1.061405429f))));
+  e = __expf(-u * u);
+  return 0.5f * poly * e;
+}
+__device__ inline float gelu(float x) {
+  float e;
+  const float tail = normal_tail(x, e);
+  return x * (x >= 0.f ? 1.0f - tail : tail);
+}
 __device__ inline float gelu_d(float x) {
-  return 0.5f * erfcf(-x * 0.70710678118654752f) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+  float e;
+  const float tail = normal_tail(x, e);
+  return (x >= 0.f ? 1.0f - tail : tail) + x * 0.39894228040143268f * e;
+}
+
+// LDS ordering between lanes of one wave (no cross-wave exchange)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One wave: C[16][64] += A[16][K] * Bt[64][K]^T.  Lane (lr, lk) receives
@@ -83,21 +115,26 @@ __device__ inline void mm16x64(const uint16_t *A, int lda, const uint16_t *Bt, i
   }
 }
 
-struct WeightsLds {
+// forward weights in LDS
+struct alignas(16) FwdWeights {
   uint16_t W1t[WD][LD1];
   uint16_t W2t[WD][LD2], W3t[WD][LD2];
-  uint16_t W2n[WD][LD2], W3n[WD][LD2];
   float w4[WD], b1[WD], b2[WD], b3[WD], b4;
 };
 
-__device__ inline void load_weights(WeightsLds &w, const uint16_t *packed, const float *master) {
+// forward + the transposed products of the backward pass
+struct alignas(16) WeightsLds {
+  FwdWeights f;
+  uint16_t W2n[WD][LD2], W3n[WD][LD2];
+};
+
+__device__ inline void load_fwd_weights(FwdWeights &w, const uint16_t *packed,
+                                        const float *master) {
   for (int e = threadIdx.x; e < WD * KIN; e += MNT) w.W1t[e / KIN][e % KIN] = packed[PW1T + e];
   for (int e = threadIdx.x; e < WD * WD; e += MNT) {
     const int r = e / WD, c = e % WD;
     w.W2t[r][c] = packed[PW2T + e];
     w.W3t[r][c] = packed[PW3T + e];
-    w.W2n[r][c] = packed[PW2N + e];
-    w.W3n[r][c] = packed[PW3N + e];
   }
   for (int e = threadIdx.x; e < WD; e += MNT) {
     w.w4[e] = bf2f(packed[PW4 + e]);
@@ -108,137 +145,199 @@ __device__ inline void load_weights(WeightsLds &w, const uint16_t *packed, const
   if (threadIdx.x == 0) w.b4 = master[OB4];
 }
 
-struct MlpRowSrc {
-  // rows from ready-made inputs
-  const float *x;          // [rows][12] or null
-  // rows from forcing samples (learned correction)
-  int dim, n0, n1, n2;
-  const double *lam0, *lam1, *lam2;
-  double D, dT;
-  const void *samples;     // [8N][DOF] state dtype
-  int fp64;
-  int64_t dof;
-  SampleBasis B;
-};
-
-// Feature row -> x[12] (fp32) and the output scale s.
-__device__ inline void row_features(const MlpRowSrc &s, int64_t row, float *x, double &scale) {
-  if (s.x) {
-    for (int i = 0; i < NIN; ++i) x[i] = s.x[row * NIN + i];
-    scale = 1.0;
-    return;
+__device__ inline void load_weights(WeightsLds &w, const uint16_t *packed, const float *master) {
+  load_fwd_weights(w.f, packed, master);
+  for (int e = threadIdx.x; e < WD * WD; e += MNT) {
+    const int r = e / WD, c = e % WD;
+    w.W2n[r][c] = packed[PW2N + e];
+    w.W3n[r][c] = packed[PW3N + e];
   }
-  const int64_t n = row / s.dof, k = row - n * s.dof;
-  double lam;
-  if (s.dim == 1) {
-    lam = s.lam0[k];
-  } else if (s.dim == 2) {
-    lam = s.lam0[k / s.n1] + s.lam1[k % s.n1];
-  } else {
-    const int64_t k2 = k % s.n2, r = k / s.n2;
-    lam = s.lam0[r / s.n1] + s.lam1[r % s.n1] + s.lam2[k2];
-  }
-  double g[PE_MLP_SAMPLES];
-  for (int q = 0; q < PE_MLP_SAMPLES; ++q) {
-    const int64_t o = (n * PE_MLP_SAMPLES + q) * s.dof + k;
-    g[q] = s.fp64 ? static_cast<const double *>(s.samples)[o]
-                  : double(static_cast<const float *>(s.samples)[o]);
-  }
-  mode_features(s.D * lam * s.dT, g, s.B, x, scale);
 }
 
-// First-layer input tile: x = hi + lo (both bf16) in columns [0, 12) and
-// [12, 24); the packed W1t repeats its 12 input columns there, so the
-// product sees the fp32 input (to about 2^-16 relative).
+// First-layer input row: x = hi + lo (both bf16) in columns [0, 12) and
+// [12, 24), zeros after (x may be null when !ok: a zero row).
 __device__ inline void put_input(uint16_t *X, const float *x, bool ok) {
+  uint32_t v[KIN / 2];
+  uint16_t hi[NIN], lo[NIN];
   for (int i = 0; i < NIN; ++i) {
-    const float v = ok ? x[i] : 0.f;
-    const uint16_t hi = f2bf(v);
-    X[i] = hi;
-    X[NIN + i] = f2bf(v - bf2f(hi));
+    const float f = ok ? x[i] : 0.f;
+    hi[i] = f2bf(f);
+    lo[i] = f2bf(f - bf2f(hi[i]));
   }
-  for (int i = 2 * NIN; i < KIN; ++i) X[i] = 0;
+  for (int i = 0; i < KIN / 2; ++i) {
+    const int e0 = 2 * i, e1 = 2 * i + 1;
+    const uint16_t a = e0 < NIN ? hi[e0] : e0 < 2 * NIN ? lo[e0 - NIN] : uint16_t(0);
+    const uint16_t b = e1 < NIN ? hi[e1] : e1 < 2 * NIN ? lo[e1 - NIN] : uint16_t(0);
+    v[i] = uint32_t(a) | (uint32_t(b) << 16);
+  }
+  uint4 *dst = reinterpret_cast<uint4 *>(X);
+  for (int q = 0; q < KIN / 8; ++q) dst[q] = uint4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
 }
 
-// --------------------------------------------------------------- inference
-struct InferOut {
-  float *y;          // [rows] network output (pe_mlp_forward) or null
-  void *corr;        // [rows] delta (learned correction) or null
-  int fp64;
-  int *bad;          // set to 1 on a non-finite output
+// Rows X[0..15] through the network (one wave; H1, H2: 16-row scratch).
+// On return every lane of row group lk holds y - b4 of rows 4*lk + r in ys[r].
+__device__ inline void forward16(const FwdWeights &w, const uint16_t *X, uint16_t (*H1)[LD2],
+                                 uint16_t (*H2)[LD2], int lr, int lk, float (&ys)[4]) {
+  f4 acc[4];
+  for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+  mm16x64<KIN>(X, LD1, &w.W1t[0][0], LD1, acc, lr, lk);
+  for (int j = 0; j < 4; ++j)
+    for (int r = 0; r < 4; ++r) H1[4 * lk + r][j * 16 + lr] = f2bf(gelu(acc[j][r] + w.b1[j * 16 + lr]));
+  wave_sync();
+  for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+  mm16x64<WD>(&H1[0][0], LD2, &w.W2t[0][0], LD2, acc, lr, lk);
+  for (int j = 0; j < 4; ++j)
+    for (int r = 0; r < 4; ++r) H2[4 * lk + r][j * 16 + lr] = f2bf(gelu(acc[j][r] + w.b2[j * 16 + lr]));
+  wave_sync();
+  for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+  mm16x64<WD>(&H2[0][0], LD2, &w.W3t[0][0], LD2, acc, lr, lk);
+  for (int r = 0; r < 4; ++r) ys[r] = 0.f;
+  for (int j = 0; j < 4; ++j)
+    for (int r = 0; r < 4; ++r) ys[r] += gelu(acc[j][r] + w.b3[j * 16 + lr]) * w.w4[j * 16 + lr];
+  for (int r = 0; r < 4; ++r)
+    for (int off = 8; off >= 1; off >>= 1) ys[r] += __shfl_xor(ys[r], off, 16);
+}
+
+// ------------------------------------------------- inference on given rows
+struct alignas(16) InferWave {
+  uint16_t X[16][LD1];
+  uint16_t H1[16][LD2], H2[16][LD2];
 };
 
+// y[r] = NN(x[r]); each wave takes 16-row groups in turn.
 __global__ __launch_bounds__(MNT) void k_mlp_infer(const uint16_t *packed, const float *master,
-                                                   MlpRowSrc src, int64_t rows, InferOut out) {
-  __shared__ WeightsLds w;
-  __shared__ uint16_t X[ROWS][LD1];
-  __shared__ uint16_t H1[ROWS][LD2], H2[ROWS][LD2];
-  __shared__ double sig[ROWS];
-  load_weights(w, packed, master);
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
-  const int64_t ntiles = (rows + ROWS - 1) / ROWS;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    __syncthreads();
-    if (t < ROWS) {
-      const int64_t row = tile * ROWS + t;
-      float x[NIN];
-      double sg = 0.0;
+                                                   const float *x, int64_t rows, float *y) {
+  __shared__ FwdWeights w;
+  __shared__ InferWave iw[MNT / 64];
+  load_fwd_weights(w, packed, master);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  InferWave &W = iw[wave];
+  const int64_t groups = (rows + 15) / 16;
+  for (int64_t gi = int64_t(blockIdx.x) * (MNT / 64) + wave; gi < groups;
+       gi += int64_t(gridDim.x) * (MNT / 64)) {
+    if (lane < 16) {
+      const int64_t row = gi * 16 + lane;
       const bool ok = row < rows;
-      if (ok) row_features(src, row, x, sg);
-      put_input(&X[t][0], x, ok);
-      sig[t] = sg;
+      put_input(&W.X[lane][0], ok ? x + row * NIN : nullptr, ok);
     }
-    __syncthreads();
-    const int r0 = wave * 16;
-    f4 acc[4];
-    // layer 1
-    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-    mm16x64<KIN>(&X[r0][0], LD1, &w.W1t[0][0], LD1, acc, lr, lk);
-    for (int j = 0; j < 4; ++j)
-      for (int r = 0; r < 4; ++r)
-        H1[r0 + 4 * lk + r][j * 16 + lr] = f2bf(gelu(acc[j][r] + w.b1[j * 16 + lr]));
-    __syncthreads();
-    // layer 2
-    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-    mm16x64<WD>(&H1[r0][0], LD2, &w.W2t[0][0], LD2, acc, lr, lk);
-    for (int j = 0; j < 4; ++j)
-      for (int r = 0; r < 4; ++r)
-        H2[r0 + 4 * lk + r][j * 16 + lr] = f2bf(gelu(acc[j][r] + w.b2[j * 16 + lr]));
-    __syncthreads();
-    // layer 3 + linear output
-    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-    mm16x64<WD>(&H2[r0][0], LD2, &w.W3t[0][0], LD2, acc, lr, lk);
-    float ys[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int j = 0; j < 4; ++j)
-      for (int r = 0; r < 4; ++r) ys[r] += gelu(acc[j][r] + w.b3[j * 16 + lr]) * w.w4[j * 16 + lr];
-    for (int r = 0; r < 4; ++r)
-      for (int off = 8; off >= 1; off >>= 1) ys[r] += __shfl_xor(ys[r], off, 16);
-    if (lr == 0) {
+    wave_sync();
+    float ys[4];
+    forward16(w, &W.X[0][0], W.H1, W.H2, lr, lk, ys);
+    if (lr == 0)
       for (int r = 0; r < 4; ++r) {
-        const int lrow = r0 + 4 * lk + r;
-        const int64_t row = tile * ROWS + lrow;
-        if (row >= rows) continue;
-        const float y = ys[r] + w.b4;
-        if (out.y) out.y[row] = y;
-        if (out.corr) {
-          const double sg = sig[lrow];
-          double dlt = sg > 0.0 ? sg * src.dT * double(y) : 0.0;
-          if (!isfinite(dlt)) {
-            *out.bad = 1;
-            dlt = 0.0;
-          }
-          if (out.fp64)
-            static_cast<double *>(out.corr)[row] = dlt;
-          else
-            static_cast<float *>(out.corr)[row] = float(dlt);
-        }
+        const int64_t row = gi * 16 + 4 * lk + r;
+        if (row < rows) y[row] = ys[r] + w.b4;
       }
+    wave_sync();
+  }
+}
+
+// --------------------------------------------------- learned correction
+struct CorrArgs {
+  int d, n0, n1, n2, M, N;
+  const double *lam0, *lam1, *lam2;
+  const double *sp0, *sp1, *sp2;   // per-axis term spectra [M][n_a]
+  const double *Cp;                // [N][8][M] sample-coefficient tables
+  double D, dT;
+  int64_t dof;
+  int ktiles, nsplit;              // grid = ktiles x nsplit blocks
+  void *corr;                      // [N][DOF] state dtype
+  int fp64;
+  int *bad;                        // set to 1 on a non-finite output
+};
+
+struct alignas(16) CorrWave {
+  uint16_t X[ROWS][LD1];
+  uint16_t H1[16][LD2], H2[16][LD2];
+  float y[ROWS];
+};
+
+constexpr size_t lds_align(size_t b) { return (b + 15) & ~size_t(15); }
+constexpr size_t CORR_LDS_FIXED = lds_align(sizeof(FwdWeights)) + (MNT / 64) * sizeof(CorrWave);
+
+// Block (kt, sg): modes kt*64 .. kt*64+63; wave w takes slices
+// n = 4 sg + w, 4 sg + w + 4 nsplit, ...  (no block-wide barrier in the loop:
+// waves may run different slice counts).
+__global__ __launch_bounds__(MNT) void k_mlp_correct(const uint16_t *packed, const float *master,
+                                                     CorrArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  FwdWeights &w = *reinterpret_cast<FwdWeights *>(lds);
+  CorrWave *cw = reinterpret_cast<CorrWave *>(lds + lds_align(sizeof(FwdWeights)));
+  double *Gs = reinterpret_cast<double *>(lds + CORR_LDS_FIXED);   // [M][64]
+  load_fwd_weights(w, packed, master);
+  const int t = threadIdx.x, lane = t & 63, lr = lane & 15, lk = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int kt = int(blockIdx.x % unsigned(a.ktiles));
+  const int sg = int(blockIdx.x / unsigned(a.ktiles));
+  for (int e = t; e < a.M * 64; e += MNT) {
+    const int m = e >> 6;
+    const int64_t kk = int64_t(kt) * 64 + (e & 63);
+    double G = 0.0;
+    if (kk < a.dof) {
+      int k0 = 0, k1 = 0, k2 = 0;
+      if (a.d == 1) {
+        k0 = int(kk);
+      } else if (a.d == 2) {
+        k0 = int(kk / a.n1);
+        k1 = int(kk % a.n1);
+      } else {
+        k2 = int(kk % a.n2);
+        const int64_t r = kk / a.n2;
+        k0 = int(r / a.n1);
+        k1 = int(r % a.n1);
+      }
+      G = a.sp0[int64_t(m) * a.n0 + k0];
+      if (a.d > 1) G *= a.sp1[int64_t(m) * a.n1 + k1];
+      if (a.d > 2) G *= a.sp2[int64_t(m) * a.n2 + k2];
     }
+    Gs[e] = G;
+  }
+  const int64_t k = int64_t(kt) * 64 + lane;
+  const bool kv = k < a.dof;
+  float zf[4] = {0.f, 0.f, 0.f, 0.f};
+  if (kv) z_features(a.D * mode_lambda(a.d, a.n1, a.n2, a.lam0, a.lam1, a.lam2, k) * a.dT, zf);
+  __syncthreads();
+  CorrWave &W = cw[wave];
+  for (int n = 4 * sg + wave; n < a.N; n += 4 * a.nsplit) {
+    const double *cp = a.Cp + int64_t(n) * PE_MLP_SAMPLES * a.M;
+    double c[PE_MLP_SAMPLES];
+    for (int i = 0; i < PE_MLP_SAMPLES; ++i) c[i] = 0.0;
+    for (int m = 0; m < a.M; ++m) {
+      const double G = Gs[m * 64 + lane];
+      for (int i = 0; i < PE_MLP_SAMPLES; ++i) c[i] += cp[i * a.M + m] * G;
+    }
+    float x[NIN];
+    for (int i = 0; i < 4; ++i) x[i] = zf[i];
+    double s;
+    coeff_features(c, x, s);
+    put_input(&W.X[lane][0], x, kv);
+    wave_sync();
+    for (int g = 0; g < ROWS / 16; ++g) {
+      float ys[4];
+      forward16(w, &W.X[16 * g][0], W.H1, W.H2, lr, lk, ys);
+      if (lr == 0)
+        for (int r = 0; r < 4; ++r) W.y[16 * g + 4 * lk + r] = ys[r] + w.b4;
+      wave_sync();
+    }
+    if (kv) {
+      double dlt = s > 0.0 ? s * a.dT * double(W.y[lane]) : 0.0;
+      if (!isfinite(dlt)) {
+        *a.bad = 1;
+        dlt = 0.0;
+      }
+      const int64_t o = int64_t(n) * a.dof + k;
+      if (a.fp64)
+        static_cast<double *>(a.corr)[o] = dlt;
+      else
+        static_cast<float *>(a.corr)[o] = float(dlt);
+    }
+    wave_sync();
   }
 }
 
 // ---------------------------------------------------------------- training
-struct TrainLds {
+struct alignas(16) TrainLds {
   WeightsLds w;
   uint16_t X[ROWS][LD1];
   uint16_t XT[KIN][LD2];
@@ -255,7 +354,7 @@ __global__ __launch_bounds__(MNT) void k_mlp_train(const uint16_t *packed, const
                                                    const float *x, const float *tg, int64_t rows,
                                                    int64_t rows_per_block, float *partials,
                                                    float *loss_part) {
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   TrainLds &s = *reinterpret_cast<TrainLds *>(smem_raw);
   load_weights(s.w, packed, master);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
@@ -282,32 +381,32 @@ __global__ __launch_bounds__(MNT) void k_mlp_train(const uint16_t *packed, const
     __syncthreads();
     f4 z1[4], z2[4], z3[4];
     for (int j = 0; j < 4; ++j) z1[j] = z2[j] = z3[j] = f4{0.f, 0.f, 0.f, 0.f};
-    mm16x64<KIN>(&s.X[r0][0], LD1, &s.w.W1t[0][0], LD1, z1, lr, lk);
+    mm16x64<KIN>(&s.X[r0][0], LD1, &s.w.f.W1t[0][0], LD1, z1, lr, lk);
     for (int j = 0; j < 4; ++j)
       for (int r = 0; r < 4; ++r) {
-        z1[j][r] += s.w.b1[j * 16 + lr];
+        z1[j][r] += s.w.f.b1[j * 16 + lr];
         const uint16_t h = f2bf(gelu(z1[j][r]));
         s.H1[r0 + 4 * lk + r][j * 16 + lr] = h;
         s.H1T[j * 16 + lr][r0 + 4 * lk + r] = h;
       }
     __syncthreads();
-    mm16x64<WD>(&s.H1[r0][0], LD2, &s.w.W2t[0][0], LD2, z2, lr, lk);
+    mm16x64<WD>(&s.H1[r0][0], LD2, &s.w.f.W2t[0][0], LD2, z2, lr, lk);
     for (int j = 0; j < 4; ++j)
       for (int r = 0; r < 4; ++r) {
-        z2[j][r] += s.w.b2[j * 16 + lr];
+        z2[j][r] += s.w.f.b2[j * 16 + lr];
         const uint16_t h = f2bf(gelu(z2[j][r]));
         s.H2[r0 + 4 * lk + r][j * 16 + lr] = h;
         s.H2T[j * 16 + lr][r0 + 4 * lk + r] = h;
       }
     __syncthreads();
-    mm16x64<WD>(&s.H2[r0][0], LD2, &s.w.W3t[0][0], LD2, z3, lr, lk);
+    mm16x64<WD>(&s.H2[r0][0], LD2, &s.w.f.W3t[0][0], LD2, z3, lr, lk);
     float h3[4][4];
     float ys[4] = {0.f, 0.f, 0.f, 0.f};
     for (int j = 0; j < 4; ++j)
       for (int r = 0; r < 4; ++r) {
-        z3[j][r] += s.w.b3[j * 16 + lr];
+        z3[j][r] += s.w.f.b3[j * 16 + lr];
         h3[j][r] = gelu(z3[j][r]);
-        ys[r] += h3[j][r] * s.w.w4[j * 16 + lr];
+        ys[r] += h3[j][r] * s.w.f.w4[j * 16 + lr];
       }
     for (int r = 0; r < 4; ++r)
       for (int off = 8; off >= 1; off >>= 1) ys[r] += __shfl_xor(ys[r], off, 16);
@@ -316,7 +415,7 @@ __global__ __launch_bounds__(MNT) void k_mlp_train(const uint16_t *packed, const
     for (int r = 0; r < 4; ++r) {
       const int lrow = r0 + 4 * lk + r;
       const bool ok = base + lrow < end;
-      const float res = ok ? (ys[r] + s.w.b4 - s.tgt[lrow]) : 0.f;
+      const float res = ok ? (ys[r] + s.w.f.b4 - s.tgt[lrow]) : 0.f;
       dy[r] = res * inv_b;
       if (lr == 0) lsum += res * res;
     }
@@ -324,7 +423,7 @@ __global__ __launch_bounds__(MNT) void k_mlp_train(const uint16_t *packed, const
     for (int j = 0; j < 4; ++j)
       for (int r = 0; r < 4; ++r) {
         gw4[j] += h3[j][r] * dy[r];
-        const float d = dy[r] * s.w.w4[j * 16 + lr] * gelu_d(z3[j][r]);
+        const float d = dy[r] * s.w.f.w4[j * 16 + lr] * gelu_d(z3[j][r]);
         gb3[j] += d;
         const uint16_t b = f2bf(d);
         s.dZ3[r0 + 4 * lk + r][j * 16 + lr] = b;
@@ -464,13 +563,10 @@ static pe_status repack(pe_mlp m, hipStream_t st) {
   return PE_OK;
 }
 
-pe_status mlp_infer(pe_mlp m, const MlpRowSrc &src, int64_t rows, const InferOut &out,
-                    hipStream_t st) {
-  int64_t tiles = (rows + ROWS - 1) / ROWS;
-  unsigned blocks = unsigned(tiles < 4096 ? (tiles > 0 ? tiles : 1) : 4096);
-  k_mlp_infer<<<blocks, MNT, 0, st>>>(m->packed, m->master, src, rows, out);
-  PE_HIP(hipGetLastError());
-  return PE_OK;
+static unsigned infer_blocks(int64_t rows) {
+  const int64_t groups = (rows + 15) / 16;
+  const int64_t b = (groups + MNT / 64 - 1) / (MNT / 64);
+  return unsigned(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
 }  // namespace pe
@@ -546,11 +642,10 @@ pe_status pe_mlp_forward(pe_mlp m, int64_t rows, const float *d_x, float *d_y, v
   clear_error();
   if (!m || !d_x || !d_y) return set_error(PE_E_ARG, "null argument");
   if (rows < 1) return set_error(PE_E_ARG, "rows must be >= 1");
-  MlpRowSrc src{};
-  src.x = d_x;
-  InferOut out{};
-  out.y = d_y;
-  return mlp_infer(m, src, rows, out, as_stream(stream));
+  hipStream_t st = as_stream(stream);
+  k_mlp_infer<<<infer_blocks(rows), MNT, 0, st>>>(m->packed, m->master, d_x, rows, d_y);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
 }
 
 pe_status pe_mlp_train_step(pe_mlp m, int64_t rows, const float *d_x, const float *d_t, float lr,
@@ -587,39 +682,73 @@ pe_status pe_mlp_train_step(pe_mlp m, int64_t rows, const float *d_x, const floa
   return PE_OK;
 }
 
-pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double dT,
-                                const void *d_samples, void *d_corr, int32_t *h_fallback,
-                                void *stream) {
+size_t pe_learned_correction_workspace_bytes(pe_grid g, int32_t n_slices) {
+  if (!g || n_slices < 1) return 0;
+  return learned_coef_bytes(g, n_slices);
+}
+
+pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double t0, double dT,
+                                void *d_corr, int32_t *h_fallback, void *d_work,
+                                size_t work_bytes, void *stream) {
   clear_error();
-  if (!g || !m || !d_samples || !d_corr) return set_error(PE_E_ARG, "null argument");
-  if (n_slices < 1 || !(dT > 0)) return set_error(PE_E_ARG, "bad n_slices / dT");
+  if (!g || !m || !d_corr) return set_error(PE_E_ARG, "null argument");
+  if (n_slices < 1 || !(dT > 0) || !std::isfinite(t0))
+    return set_error(PE_E_ARG, "bad n_slices / t0 / dT");
   hipStream_t st = as_stream(stream);
-  MlpRowSrc src{};
-  src.x = nullptr;
-  src.dim = g->dim;
-  src.n0 = g->ax[0].n;
-  src.n1 = g->dim > 1 ? g->ax[1].n : 1;
-  src.n2 = g->dim > 2 ? g->ax[2].n : 1;
-  src.lam0 = g->ax[0].d_lam;
-  src.lam1 = g->ax[1].d_lam;
-  src.lam2 = g->ax[2].d_lam;
-  src.D = g->D;
-  src.dT = dT;
-  src.samples = d_samples;
-  src.fp64 = g->precision == PE_FP64;
-  src.B = sample_basis();
-  src.dof = g->dof;
-  InferOut out{};
-  out.corr = d_corr;
-  out.fp64 = src.fp64;
-  out.bad = m->flag;
+  const bool fp64 = g->precision == PE_FP64;
+  const size_t sb = fp64 ? sizeof(double) : sizeof(float);
+  if (h_fallback) *h_fallback = 0;
+  if (g->n_terms == 0) {
+    PE_HIP(hipMemsetAsync(d_corr, 0, sb * size_t(n_slices) * g->dof, st));
+    return PE_OK;
+  }
+  if (!d_work || work_bytes < pe_learned_correction_workspace_bytes(g, n_slices))
+    return set_error(PE_E_WORKSPACE, "workspace %zu B below %zu B", work_bytes,
+                     pe_learned_correction_workspace_bytes(g, n_slices));
+  double *Cp = static_cast<double *>(d_work);
+  PE_TRY(learned_coefs(g, n_slices, t0, dT, Cp, st));
+  CorrArgs a{};
+  a.d = g->dim;
+  a.M = g->n_terms;
+  a.N = n_slices;
+  a.n0 = g->ax[0].n;
+  a.n1 = g->dim > 1 ? g->ax[1].n : 1;
+  a.n2 = g->dim > 2 ? g->ax[2].n : 1;
+  a.lam0 = g->ax[0].d_lam;
+  a.lam1 = g->ax[1].d_lam;
+  a.lam2 = g->ax[2].d_lam;
+  a.sp0 = g->d_spec[0];
+  a.sp1 = g->d_spec[1];
+  a.sp2 = g->d_spec[2];
+  a.Cp = Cp;
+  a.D = g->D;
+  a.dT = dT;
+  a.dof = g->dof;
+  a.corr = d_corr;
+  a.fp64 = fp64;
+  a.bad = m->flag;
+  const int64_t ktiles = (g->dof + 63) / 64;
+  const int64_t slice_groups = (int64_t(n_slices) + 3) / 4;
+  const int64_t want = (2048 + ktiles - 1) / ktiles;
+  const int64_t nsplit = std::max<int64_t>(1, std::min(slice_groups, want));
+  if (ktiles * nsplit > (int64_t(1) << 24)) return set_error(PE_E_ARG, "grid too large");
+  a.ktiles = int(ktiles);
+  a.nsplit = int(nsplit);
+  const size_t lds = CORR_LDS_FIXED + sizeof(double) * 64 * size_t(a.M);
+  static bool attr_set = false;
+  if (!attr_set) {
+    PE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mlp_correct),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(CORR_LDS_FIXED + sizeof(double) * 64 * PE_MAX_TERMS)));
+    attr_set = true;
+  }
   PE_HIP(hipMemsetAsync(m->flag, 0, sizeof(int), st));
-  PE_TRY(mlp_infer(m, src, int64_t(n_slices) * g->dof, out, st));
+  k_mlp_correct<<<unsigned(ktiles * nsplit), MNT, lds, st>>>(m->packed, m->master, a);
+  PE_HIP(hipGetLastError());
   int bad = 0;
   PE_HIP(hipMemcpyAsync(&bad, m->flag, sizeof(int), hipMemcpyDeviceToHost, st));
   PE_HIP(hipStreamSynchronize(st));
   if (bad) {
-    const size_t sb = src.fp64 ? sizeof(double) : sizeof(float);
     PE_HIP(hipMemsetAsync(d_corr, 0, sb * size_t(n_slices) * g->dof, st));
     PE_HIP(hipStreamSynchronize(st));
   }

@@ -67,6 +67,8 @@ struct pe_grid_s {
   pe::DevTerm *d_terms = nullptr;        // [n_terms]
   double *d_C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][np_a] 1D loads
   double *d_Cf = nullptr;        // [2][n_terms][Kh_last] folded last-axis loads
+  // spec_a[m][k] = sig_a(k) (S_a^T C_a[m])_k: spectral 1D loads of each term
+  double *d_spec[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][n_a]
   // kernel timing (benchmark instrumentation)
   bool timing = false;
   std::vector<pe::PendingTiming> pending;
@@ -196,6 +198,12 @@ struct TimedScope {
 };
 
 // ---------------------------------------------------------------- learned G
+// amp_m tau_m(t): the time factor of a forcing term with its amplitude.
+__device__ inline double term_time(const DevTerm &tm, double t) {
+  const double poly = tm.p[0] + t * (tm.p[1] + t * (tm.p[2] + t * tm.p[3]));
+  return tm.amp * exp(tm.alpha * t) * cos(tm.omega * t + tm.phase) * poly;
+}
+
 // Orthonormal polynomial basis of the eight forcing sample times of a slice
 // (points t_j = (j - 3.5)/3.5): q[j * 8 + i] = q_i(t_j).  Built on the host.
 struct SampleBasis {
@@ -203,10 +211,16 @@ struct SampleBasis {
 };
 SampleBasis sample_basis();
 
-// Network inputs of one (slice, mode): x[12] and the output scale s (the
-// norm of the degree >= 4 coefficients of the samples g[8]).
-__device__ inline void mode_features(double z, const double *g, const SampleBasis &B, float *x,
-                                     double &s) {
+// Cp[n][i][m] = sum_j q_i(t_j) amp_m tau_m(t0 + n dT + j dT / 7): the
+// polynomial coefficients of the forcing samples of slice n are
+// c_i = sum_m Cp[n][i][m] prod_a spec_a[m][k_a] (the forcing is a sum of
+// separable terms, so its spectral samples are too).
+size_t learned_coef_bytes(pe_grid g, int N);
+pe_status learned_coefs(pe_grid g, int N, double t0, double dT, double *Cp, hipStream_t st);
+
+// z-features [ln z / 8, e^{-z}, phi_1(-z), 2 phi_2(-z)] in FP64 (series
+// below z = 1e-3, where the closed forms cancel).
+__device__ inline void z_features(double z, float *x) {
   const double e = exp(-z);
   double p1, p2;
   if (z < 1e-3) {
@@ -220,14 +234,14 @@ __device__ inline void mode_features(double z, const double *g, const SampleBasi
   x[1] = float(e);
   x[2] = float(p1);
   x[3] = float(2.0 * p2);
-  double c[PE_MLP_SAMPLES], gn = 0.0, hn = 0.0;
-  for (int i = 0; i < PE_MLP_SAMPLES; ++i) {
-    double a = 0.0;
-    for (int j = 0; j < PE_MLP_SAMPLES; ++j) a += B.q[j * PE_MLP_SAMPLES + i] * g[j];
-    c[i] = a;
-    gn += g[i] * g[i];
-    if (i >= 4) hn += a * a;
-  }
+}
+
+// Sample features x[4..11] and the output scale s from the polynomial
+// coefficients c[8] of the samples (|g| = |c|: the basis is orthonormal).
+__device__ inline void coeff_features(const double *c, float *x, double &s) {
+  double gn = 0.0, hn = 0.0;
+  for (int i = 0; i < PE_MLP_SAMPLES; ++i) gn += c[i] * c[i];
+  for (int i = 4; i < PE_MLP_SAMPLES; ++i) hn += c[i] * c[i];
   gn = sqrt(gn);
   s = sqrt(hn);
   const double ig = gn > 0.0 ? 1.0 / gn : 0.0, ih = s > 0.0 ? 1.0 / s : 0.0;
@@ -235,15 +249,13 @@ __device__ inline void mode_features(double z, const double *g, const SampleBasi
   for (int i = 4; i < PE_MLP_SAMPLES; ++i) x[4 + i] = float(c[i] * ih);
 }
 
-// Output scale alone (row selection).
-__device__ inline double mode_scale(const double *g, const SampleBasis &B) {
-  double hn = 0.0;
-  for (int i = 4; i < PE_MLP_SAMPLES; ++i) {
-    double a = 0.0;
-    for (int j = 0; j < PE_MLP_SAMPLES; ++j) a += B.q[j * PE_MLP_SAMPLES + i] * g[j];
-    hn += a * a;
-  }
-  return sqrt(hn);
+// Eigenvalue sum lambda_k of natural mode index k (last axis fastest).
+__device__ inline double mode_lambda(int d, int n1, int n2, const double *l0, const double *l1,
+                                     const double *l2, int64_t k) {
+  if (d == 1) return l0[k];
+  if (d == 2) return l0[k / n1] + l1[k % n1];
+  const int64_t k2 = k % n2, r = k / n2;
+  return l0[r / n1] + l1[r % n1] + l2[k2];
 }
 
 }  // namespace pe

@@ -33,7 +33,7 @@ static size_t fixed_bytes(pe_grid g, const pe_solve_params *P) {
   b += Arena::need(sizeof(double) * 2);                     // norms
   b += coarse_partials_bytes(g);
   if (P->mlp && !P->d_corr) {
-    b += Arena::need(sb * dof * P->N * PE_MLP_SAMPLES);     // forcing samples
+    b += learned_coef_bytes(g, P->N);                       // sample-coefficient tables
     b += Arena::need(sb * dof * P->N);                      // learned correction
   }
   return b + 6 * 256;
@@ -93,9 +93,10 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
   double *norms = ar.take<double>(2);
   double *partials = ar.take<double>(coarse_partials_bytes(g) / sizeof(double));
   const bool learn = P->mlp && !P->d_corr;
-  char *samples = learn ? ar.take<char>(sb * dof * N * PE_MLP_SAMPLES) : nullptr;
+  const size_t coef_bytes = learn ? learned_coef_bytes(g, N) : 0;
+  char *coefs = learn ? ar.take<char>(coef_bytes) : nullptr;
   char *lcorr = learn ? ar.take<char>(sb * dof * N) : nullptr;
-  if (!EF || !EG || !Ubuf || !Fout || !r || !norms || !partials || (learn && (!samples || !lcorr)))
+  if (!EF || !EG || !Ubuf || !Fout || !r || !norms || !partials || (learn && (!coefs || !lcorr)))
     return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
   const void *corr = P->d_corr;
   double *BF = EF + dof, *BG = EG + dof;
@@ -134,10 +135,9 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
     PE_HIP(hipEventCreate(&l0));
     PE_HIP(hipEventCreate(&l1));
     PE_HIP(hipEventRecord(l0, st));
-    pe_status s1 = pe_learned_samples(g, N, P->t0, dT, samples, fwork, fbytes, stream);
     int32_t fb = 0;
-    pe_status s2 = s1 == PE_OK ? pe_learned_correction(g, P->mlp, N, dT, samples, lcorr, &fb, stream)
-                               : s1;
+    pe_status s2 = pe_learned_correction(g, P->mlp, N, P->t0, dT, lcorr, &fb, coefs, coef_bytes,
+                                         stream);
     float lms = 0;
     if (s2 == PE_OK && hipEventRecord(l1, st) == hipSuccess && hipEventSynchronize(l1) == hipSuccess)
       hipEventElapsedTime(&lms, l0, l1);

@@ -1,8 +1,9 @@
 """Training and evaluation driver of the learned coarse correction.
 
 Everything numerical runs in the library (libpeifem): the fine and coarse
-forcing responses F^J(0), G(0), the forcing samples, the training rows, the
-BF16-MFMA training steps and the corrected Parareal solve.  This module only
+forcing responses F^J(0), G(0), the training rows (network inputs from the
+forcing's term spectra and time factors), the BF16-MFMA training steps and
+the corrected Parareal solve.  This module only
 sequences those calls.
 
 Training data: for each seeded forcing of the workload's family, on a grid of
@@ -72,7 +73,6 @@ def training_rows(template, seeds: Sequence[int], grid_n: Optional[Sequence[int]
     r = g.empty_states(prob.N)
     U = g.empty_states(prob.N + 1).zero_()
     cwork = g.workspace(g.L.pe_coarse_workspace_bytes(g.h, prob.N, prob.p))
-    S = g.empty_states(8 * prob.N)
     xs, ts, ss = [], [], []
     t0 = time.perf_counter()
     for i, seed in enumerate(seeds):
@@ -81,8 +81,7 @@ def training_rows(template, seeds: Sequence[int], grid_n: Optional[Sequence[int]
         g.set_forcing(terms)
         g.fine_propagate(zero, prob.t0, prob.dT, prob.J, prob.c_fine, EF, BF, Uout=R, work=fwork)
         g.coarse_sweep(U, prob.t0, prob.dT, prob.c_coarse, EG, BG, r, work=cwork)
-        g.learned_samples(prob.N, prob.t0, prob.dT, out=S)
-        x, t, sc, _ = g.learned_rows(S, R, r, prob.dT, rel_thresh=rel_thresh,
+        x, t, sc, _ = g.learned_rows(R, r, prob.t0, prob.dT, rel_thresh=rel_thresh,
                                      max_rows=prob.N * modes * 2, want_scale=True)
         xs.append(x.clone())
         ts.append(t.clone())

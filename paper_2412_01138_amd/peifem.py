@@ -37,7 +37,8 @@ EXPORTS = [
     "pe_grid_precision", "pe_last_error", "pe_set_timing", "pe_get_timing",
     "pe_mlp_create", "pe_mlp_free", "pe_mlp_get_params", "pe_mlp_set_params", "pe_mlp_forward",
     "pe_mlp_train_step", "pe_learned_samples_workspace_bytes", "pe_learned_samples",
-    "pe_learned_rows_workspace_bytes", "pe_learned_rows", "pe_learned_correction",
+    "pe_learned_rows_workspace_bytes", "pe_learned_rows",
+    "pe_learned_correction_workspace_bytes", "pe_learned_correction",
 ]
 PE_MLP_INPUTS, PE_MLP_WIDTH, PE_MLP_PARAMS, PE_MLP_SAMPLES = 12, 64, 9217, 8
 PE_K_DST_LAST, PE_K_DST_MID, PE_K_LOAD, PE_K_UPDATE, PE_K_SWEEP, PE_K_COUNT = 0, 1, 2, 3, 4, 5
@@ -137,9 +138,12 @@ def load_library():
     L.pe_learned_samples.argtypes = [vp, i32, dbl, dbl, vp, vp, sz, vp]
     L.pe_learned_rows_workspace_bytes.argtypes = [vp, i32]
     L.pe_learned_rows_workspace_bytes.restype = sz
-    L.pe_learned_rows.argtypes = [vp, i32, dbl, vp, vp, vp, dbl, vp, vp, vp, i64,
+    L.pe_learned_rows.argtypes = [vp, i32, dbl, dbl, vp, vp, dbl, vp, vp, vp, i64,
                                   ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
-    L.pe_learned_correction.argtypes = [vp, vp, i32, dbl, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    L.pe_learned_correction_workspace_bytes.argtypes = [vp, i32]
+    L.pe_learned_correction_workspace_bytes.restype = sz
+    L.pe_learned_correction.argtypes = [vp, vp, i32, dbl, dbl, vp, ctypes.POINTER(ctypes.c_int32),
+                                        vp, sz, vp]
     L.pe_last_error.argtypes = []
     L.pe_last_error.restype = ctypes.c_char_p
     for name in ("pe_init_grid", "pe_set_forcing", "pe_phi_tables", "pe_project",
@@ -318,11 +322,12 @@ class Grid:
                                          work.numel(), _stream(self.stream)))
         return out
 
-    def learned_rows(self, samples, R, r, dT: float, rel_thresh: float = 1e-9,
+    def learned_rows(self, R, r, t0: float, dT: float, rel_thresh: float = 1e-9,
                      max_rows: Optional[int] = None, want_scale: bool = False):
-        """Training rows (x [rows, 12], target [rows], count) of the modes
-        whose forcing samples have a part of degree >= 4; with want_scale the
-        rows' output scales s [rows] come third."""
+        """Training rows (x [rows, 12], target [rows], count) of the slices
+        starting at t0 + n dT whose forcing samples have a part of degree >= 4
+        (R = F^J(0), r = G(0) per slice); with want_scale the rows' output
+        scales s [rows] come third."""
         import torch
         N = R.shape[0]
         if max_rows is None:
@@ -333,22 +338,25 @@ class Grid:
               if want_scale else None)
         work = self.workspace(self.L.pe_learned_rows_workspace_bytes(self.h, N))
         cnt = ctypes.c_int64(0)
-        _check(self.L.pe_learned_rows(self.h, N, float(dT), _ptr(samples), _ptr(R), _ptr(r),
+        _check(self.L.pe_learned_rows(self.h, N, float(t0), float(dT), _ptr(R), _ptr(r),
                                       float(rel_thresh), _ptr(x), _ptr(t), _ptr(sc),
-                                      int(max_rows),
-                                      ctypes.byref(cnt), _ptr(work), work.numel(),
+                                      int(max_rows), ctypes.byref(cnt), _ptr(work), work.numel(),
                                       _stream(self.stream)))
         n = min(int(cnt.value), max_rows)
         if want_scale:
             return x[:n], t[:n], sc[:n], int(cnt.value)
         return x[:n], t[:n], int(cnt.value)
 
-    def learned_correction(self, mlp: "Mlp", samples, N: int, dT: float, out=None):
+    def learned_correction(self, mlp: "Mlp", N: int, t0: float, dT: float, out=None, work=None):
+        """delta_n for slices starting at t0 + n dT: ([N, *grid], fallback)."""
         if out is None:
             out = self.empty_states(N)
+        if work is None:
+            work = self.workspace(self.L.pe_learned_correction_workspace_bytes(self.h, N))
         fb = ctypes.c_int32(0)
-        _check(self.L.pe_learned_correction(self.h, mlp.h, N, float(dT), _ptr(samples), _ptr(out),
-                                            ctypes.byref(fb), _stream(self.stream)))
+        _check(self.L.pe_learned_correction(self.h, mlp.h, N, float(t0), float(dT), _ptr(out),
+                                            ctypes.byref(fb), _ptr(work), work.numel(),
+                                            _stream(self.stream)))
         return out, bool(fb.value)
 
     def solve_params(self, t0, T, N, J, cG, cF, K_max, tol, corr=None, mlp=None) -> SolveParams:
