@@ -263,17 +263,17 @@ static pe_status lagrange_A(int s, const double *c, double A[PE_MAX_STAGES][PE_M
 
 static void free_grid_tables(pe_grid g) {
   for (int a = 0; a < PE_MAX_DIM; ++a) {
-    hipFree(g->ax[a].d_lam);
-    hipFree(g->ax[a].d_sig);
-    hipFree(g->ax[a].d_Sh);
-    hipFree(g->ax[a].d_ShT);
-    hipFree(g->ax[a].d_Shi);
-    hipFree(g->ax[a].d_Slo);
-    hipFree(g->d_C[a]);
-    hipFree(g->d_spec[a]);
+    dev_free(g->ax[a].d_lam);
+    dev_free(g->ax[a].d_sig);
+    dev_free(g->ax[a].d_Sh);
+    dev_free(g->ax[a].d_ShT);
+    dev_free(g->ax[a].d_Shi);
+    dev_free(g->ax[a].d_Slo);
+    dev_free(g->d_C[a]);
+    dev_free(g->d_spec[a]);
   }
-  hipFree(g->d_terms);
-  hipFree(g->d_Cf);
+  dev_free(g->d_terms);
+  dev_free(g->d_Cf);
 }
 
 pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst, hipStream_t st) {
@@ -288,15 +288,15 @@ pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst
     }
     hipError_t e = hipMemcpyAsync(d_sp, sp.data(), sizeof(SpaceParams) * n_terms,
                                   hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) { hipFree(d_sp); PE_HIP(e); }
+    if (e != hipSuccess) { dev_free(d_sp); PE_HIP(e); }
     const Axis &ax = g->ax[a];
     dim3 grid((ax.np + 127) / 128, n_terms);
     if (n_terms > 0)
       k_load_1d<<<grid, 128, 0, st>>>(ax.n, ax.np, ax.lo, ax.h, rule, d_sp, n_terms, dst[a]);
     e = hipStreamSynchronize(st);
-    if (e != hipSuccess) { hipFree(d_sp); PE_HIP(e); }
+    if (e != hipSuccess) { dev_free(d_sp); PE_HIP(e); }
   }
-  hipFree(d_sp);
+  dev_free(d_sp);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }
@@ -332,8 +332,8 @@ int64_t pe_grid_dof(pe_grid g) { return g ? g->dof : -1; }
 
 static void drop_pending(pe_grid g) {
   for (auto &p : g->pending) {
-    hipEventDestroy(p.start);
-    hipEventDestroy(p.stop);
+    event_free(p.start);
+    event_free(p.stop);
   }
   g->pending.clear();
 }
@@ -446,14 +446,14 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
   if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");
   hipStream_t st = as_stream(stream);
   for (int a = 0; a < PE_MAX_DIM; ++a) {
-    hipFree(g->d_C[a]);
+    dev_free(g->d_C[a]);
     g->d_C[a] = nullptr;
-    hipFree(g->d_spec[a]);
+    dev_free(g->d_spec[a]);
     g->d_spec[a] = nullptr;
   }
-  hipFree(g->d_terms);
+  dev_free(g->d_terms);
   g->d_terms = nullptr;
-  hipFree(g->d_Cf);
+  dev_free(g->d_Cf);
   g->d_Cf = nullptr;
   g->n_terms = n_terms;
   if (n_terms == 0) return PE_OK;

@@ -13,7 +13,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "pe_internal.h"
+#include "learned_feat.h"
 
 namespace pe {
 

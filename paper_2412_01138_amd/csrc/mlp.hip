@@ -23,7 +23,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "pe_internal.h"
+#include "learned_feat.h"
 
 namespace pe {
 
@@ -608,14 +608,14 @@ pe_status pe_mlp_create(pe_mlp *out, const float *h_params, void *stream) {
 
 void pe_mlp_free(pe_mlp m) {
   if (!m) return;
-  hipFree(m->master);
-  hipFree(m->m);
-  hipFree(m->v);
-  hipFree(m->packed);
-  hipFree(m->partials);
-  hipFree(m->loss_part);
-  hipFree(m->grad);
-  hipFree(m->flag);
+  dev_free(m->master);
+  dev_free(m->m);
+  dev_free(m->v);
+  dev_free(m->packed);
+  dev_free(m->partials);
+  dev_free(m->loss_part);
+  dev_free(m->grad);
+  dev_free(m->flag);
   delete m;
 }
 

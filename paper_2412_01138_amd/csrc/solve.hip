@@ -9,7 +9,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "pe_internal.h"
+#include "learned_feat.h"
 
 namespace pe {
 
@@ -110,7 +110,7 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
   struct EvGuard {
     hipEvent_t *e;
     ~EvGuard() {
-      for (int i = 0; i < 5; ++i) hipEventDestroy(e[i]);
+      for (int i = 0; i < 5; ++i) event_free(e[i]);
     }
   } guard{ev};
   float ms = 0;
@@ -140,9 +140,9 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
                                          stream);
     float lms = 0;
     if (s2 == PE_OK && hipEventRecord(l1, st) == hipSuccess && hipEventSynchronize(l1) == hipSuccess)
-      hipEventElapsedTime(&lms, l0, l1);
-    hipEventDestroy(l0);
-    hipEventDestroy(l1);
+      (void)hipEventElapsedTime(&lms, l0, l1);
+    event_free(l0);
+    event_free(l1);
     PE_TRY(s2);
     rep->ms_learned = lms;
     rep->fallback = fb;
