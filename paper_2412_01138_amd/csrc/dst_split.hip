@@ -38,11 +38,16 @@ constexpr int SNT = 256;
 constexpr int SGEN_MAX_TERMS = 32;
 constexpr int SGEN_MAX_CF = 8192;   // floats of one folded half table kept in LDS
 
-__device__ inline uint16_t bf16_rn(float x) {
-  uint32_t u = __float_as_uint(x);
-  return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+typedef float f8 __attribute__((ext_vector_type(8)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));   // dword-aligned loads
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// hi = bf16(v) (round to nearest even), lo = bf16(v - hi), 8 at a time
+__device__ inline void split8(const f8 &v, bf16x8 &hi, bf16x8 &lo) {
+  hi = __builtin_convertvector(v, bf16x8);
+  const f8 hv = __builtin_convertvector(hi, f8);
+  lo = __builtin_convertvector(v - hv, bf16x8);
 }
-__device__ inline float bf16_val(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
 struct SplitArgs {
   const float *X;          // [F][R][np]  (contracted axis contiguous)
@@ -58,7 +63,7 @@ struct SplitArgs {
 };
 
 template <int BM>
-struct SSmem {
+struct alignas(16) SSmem {
   uint16_t Ahi[BM][SLD], Alo[BM][SLD];
   uint16_t Bhi[SBN][SLD], Blo[SBN][SLD];
 };
@@ -68,9 +73,9 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
   constexpr bool GEN = GM > 0;
   constexpr int TM = BM / 32;                 // MFMA tiles per wave along the modes
   constexpr int TN = 4;                       // ... along r (64 per wave)
-  constexpr int TPR_A = SNT / BM;             // threads per A row
-  constexpr int EA = SKB / TPR_A;             // bf16 of one A row per thread (4, 8, 16)
+  constexpr int ACH = BM * (SKB / 8) / SNT;   // 16-byte A chunks per thread per array (2, 1, ..)
   constexpr int EB = 16;                      // p values of one B row per thread
+  static_assert(ACH >= 1 || BM == 32, "A chunk mapping");
   __shared__ SSmem<BM> sm;
   extern __shared__ float cf_lds[];           // GEN: [M][Kh] folded table of this half
 
@@ -79,21 +84,22 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
     const int64_t nb = gridDim.x;
     if (nb % 8 == 0) bid = (bid % 8) * (nb / 8) + bid / 8;   // one field's tiles on one XCD
   }
+  // the two halves of a tile read the same rows: run them back to back
+  const int h = int(bid % 2);
+  bid /= 2;
   const int tn = int(bid % a.tiles_n);
   bid /= a.tiles_n;
   const int tm = int(bid % a.tiles_m);
-  bid /= a.tiles_m;
-  const int h = int(bid % 2);
-  const int64_t f = bid / 2;
+  const int64_t f = bid / a.tiles_m;
   const int m0 = tm * BM;
   const int64_t n0 = int64_t(tn) * SBN;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
 
-  // A-tile role: row ia, bf16 columns ka0 .. ka0 + EA
-  const int ia = t / TPR_A, ka0 = (t % TPR_A) * EA;
-  const bool arow_ok = m0 + ia < a.Kh;
-  const int64_t arow = int64_t(h) * a.Kh + (arow_ok ? m0 + ia : a.Kh - 1);
+  // A-tile role: 16-byte chunks c = t + SNT u of the BM x 32 tile
+  // (row c / 4, bf16 columns 8 (c % 4) ..); BM = 32 uses half the threads
+  constexpr int AU = ACH > 0 ? ACH : 1;
+  const bool a_active = ACH > 0 || t < BM * (SKB / 8);
   // B-tile role: row rb (an r index), p values pb0 .. pb0 + 16
   const int rb = t / 2, pb0 = (t % 2) * EB;
   const int64_t grow = n0 + rb;
@@ -126,50 +132,87 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
   }
 
   const float *xrow = GEN ? nullptr : a.X + (f * a.R + grc) * a.np;
-  uint16_t pah[EA], pal[EA];
+  u16x8 pah[AU], pal[AU];
   float pxa[GEN ? 1 : EB], pxb[GEN ? 1 : EB];
   auto load = [&](int k0) {
+    if (a_active) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      pah[e] = a.Shi[arow * a.Kh + k0 + ka0 + e];
-      pal[e] = a.Slo[arow * a.Kh + k0 + ka0 + e];
+      for (int u = 0; u < AU; ++u) {
+        const int c = t + SNT * u;
+        const int row = m0 + c / 4;
+        const int64_t arow = int64_t(h) * a.Kh + (row < a.Kh ? row : a.Kh - 1);
+        const int64_t o = arow * a.Kh + k0 + 8 * (c % 4);
+        pah[u] = *reinterpret_cast<const u16x8 *>(a.Shi + o);
+        pal[u] = *reinterpret_cast<const u16x8 *>(a.Slo + o);
+      }
     }
     if constexpr (!GEN) {
+      const int p = k0 + pb0;
+      // forward x[p .. p+15]: p + 15 < Kh <= np, inside the row
 #pragma unroll
-      for (int e = 0; e < EB; ++e) {
-        const int p = k0 + pb0 + e;
-        const int pa = p < a.n ? p : a.n - 1;
-        const int pm = a.n - 1 - p > 0 ? a.n - 1 - p : 0;
-        pxa[e] = xrow[pa];
-        pxb[e] = xrow[pm];
+      for (int q = 0; q < EB / 4; ++q) {
+        const f4u v = *reinterpret_cast<const f4u *>(xrow + p + 4 * q);
+        pxa[4 * q] = v.x;
+        pxa[4 * q + 1] = v.y;
+        pxa[4 * q + 2] = v.z;
+        pxa[4 * q + 3] = v.w;
+      }
+      // mirror x[n-1-p-e], e = 0..15: one ascending run from n-16-p
+      const int mb = a.n - EB - p;
+      if (mb >= 0) {
+#pragma unroll
+        for (int q = 0; q < EB / 4; ++q) {
+          const f4u v = *reinterpret_cast<const f4u *>(xrow + mb + 4 * q);
+          pxb[EB - 1 - 4 * q] = v.x;
+          pxb[EB - 2 - 4 * q] = v.y;
+          pxb[EB - 3 - 4 * q] = v.z;
+          pxb[EB - 4 - 4 * q] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+          const int i = a.n - 1 - p - e;
+          pxb[e] = xrow[i > 0 ? i : 0];
+        }
       }
     }
   };
   auto store = [&](int k0) {
+    if (a_active) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      sm.Ahi[ia][ka0 + e] = arow_ok ? pah[e] : uint16_t(0);
-      sm.Alo[ia][ka0 + e] = arow_ok ? pal[e] : uint16_t(0);
+      for (int u = 0; u < AU; ++u) {
+        const int c = t + SNT * u;
+        const bool ok = m0 + c / 4 < a.Kh;
+        const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+        *reinterpret_cast<u16x8 *>(&sm.Ahi[c / 4][8 * (c % 4)]) = ok ? pah[u] : z;
+        *reinterpret_cast<u16x8 *>(&sm.Alo[c / 4][8 * (c % 4)]) = ok ? pal[u] : z;
+      }
     }
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int p = k0 + pb0 + e;
-      float v;
-      if constexpr (GEN) {
-        const int Mm1 = a.gen.M - 1;
-        v = 0.0f;
+    for (int g8 = 0; g8 < EB / 8; ++g8) {
+      f8 v;
 #pragma unroll
-        for (int m = 0; m < GM; ++m) v += rf[m] * cf_lds[(m < Mm1 ? m : Mm1) * a.Kh + p];
-      } else {
-        const bool has_a = p < a.H || (h == 0 && p == a.H && (a.n & 1));
-        const bool has_b = p < a.H;
-        v = (has_a ? pxa[e] : 0.0f) + (has_b ? (h == 0 ? pxb[e] : -pxb[e]) : 0.0f);
-        v = brow_ok ? v : 0.0f;
+      for (int e8 = 0; e8 < 8; ++e8) {
+        const int e = 8 * g8 + e8;
+        const int p = k0 + pb0 + e;
+        float x;
+        if constexpr (GEN) {
+          const int Mm1 = a.gen.M - 1;
+          x = 0.0f;
+#pragma unroll
+          for (int m = 0; m < GM; ++m) x += rf[m] * cf_lds[(m < Mm1 ? m : Mm1) * a.Kh + p];
+        } else {
+          const bool has_b = p < a.H;
+          const bool has_a = has_b || (h == 0 && p == a.H && (a.n & 1));
+          x = (has_a ? pxa[e] : 0.0f) + (has_b ? (h == 0 ? pxb[e] : -pxb[e]) : 0.0f);
+          x = brow_ok ? x : 0.0f;
+        }
+        v[e8] = x;
       }
-      const uint16_t hi = bf16_rn(v);
-      const uint16_t lo = bf16_rn(v - bf16_val(hi));
-      sm.Bhi[rb][pb0 + e] = hi;
-      sm.Blo[rb][pb0 + e] = lo;
+      bf16x8 hi, lo;
+      split8(v, hi, lo);
+      *reinterpret_cast<bf16x8 *>(&sm.Bhi[rb][pb0 + 8 * g8]) = hi;
+      *reinterpret_cast<bf16x8 *>(&sm.Blo[rb][pb0 + 8 * g8]) = lo;
     }
   };
 

@@ -97,35 +97,50 @@ template <typename TS, typename TG>
 __global__ void k_update(Dims D, const double *__restrict__ sig0, const double *__restrict__ sig1,
                          const double *__restrict__ sig2, const double *__restrict__ E,
                          const double *__restrict__ B, int s, const TS *Uin, TS *Uout,
-                         const TG *__restrict__ G, int nslices, int jc, int64_t dof,
+                         const TG *__restrict__ G, int nslices, int chunk, int jc, int64_t dof,
                          int64_t dofp) {
-  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < int64_t(nslices) * dof;
+  // thread = (slice chunk, coefficient): the tables of coefficient k are read
+  // once and applied to `chunk` consecutive slices
+  const int nchunks = (nslices + chunk - 1) / chunk;
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < int64_t(nchunks) * dof;
        idx += int64_t(gridDim.x) * blockDim.x) {
-  int64_t n = idx / dof;
-  int64_t k = idx - n * dof;
-  int kk[3] = {0, 0, 0};
-  int64_t r = k;
-  for (int a = D.d - 1; a >= 0; --a) {
-    kk[a] = int(r % D.n[a]);
-    r /= D.n[a];
+    const int64_t c = idx / dof;
+    const int64_t k = idx - c * dof;
+    int kk[3] = {0, 0, 0};
+    int64_t r = k;
+    for (int a = D.d - 1; a >= 0; --a) {
+      kk[a] = int(r % D.n[a]);
+      r /= D.n[a];
+    }
+    int64_t p = 0;   // position of mode k in the folded mode order of every axis
+    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + fold_pos(kk[a], D.Kh[a]);
+    double sig = sig0[kk[0]];
+    if (D.d > 1) sig *= sig1[kk[1]];
+    if (D.d > 2) sig *= sig2[kk[2]];
+    const double e = E[k];
+    double bs[PE_MAX_STAGES];
+    for (int i = 0; i < s; ++i) bs[i] = B[int64_t(i) * dof + k] * sig;
+    const int n1 = int(c * chunk) + chunk < nslices ? int(c * chunk) + chunk : nslices;
+    for (int n = int(c * chunk); n < n1; ++n) {
+      const int64_t o = int64_t(n) * dof + k;
+      double V = Uin ? double(Uin[o]) : 0.0;
+      const TG *Gn = G + (int64_t(n) * jc) * int64_t(s) * dofp + p;
+      for (int j = 0; j < jc; ++j) {
+        double v = e * V;
+        for (int i = 0; i < s; ++i) v += bs[i] * double(Gn[(int64_t(j) * s + i) * dofp]);
+        V = v;
+      }
+      Uout[o] = TS(V);
+    }
   }
-  int64_t p = 0;   // position of mode k in the folded mode order of every axis
-  for (int a = 0; a < D.d; ++a) p = p * D.np[a] + fold_pos(kk[a], D.Kh[a]);
-  double sig = sig0[kk[0]];
-  if (D.d > 1) sig *= sig1[kk[1]];
-  if (D.d > 2) sig *= sig2[kk[2]];
-  double e = E[k];
-  double bs[PE_MAX_STAGES];
-  for (int i = 0; i < s; ++i) bs[i] = B[int64_t(i) * dof + k] * sig;
-  double V = Uin ? double(Uin[idx]) : 0.0;
-  const TG *Gn = G + (n * jc) * int64_t(s) * dofp + p;
-  for (int j = 0; j < jc; ++j) {
-    double v = e * V;
-    for (int i = 0; i < s; ++i) v += bs[i] * double(Gn[(int64_t(j) * s + i) * dofp]);
-    V = v;
-  }
-  Uout[idx] = TS(V);
-  }
+}
+
+// Slices per update thread: enough threads to fill the chip (about 2^21),
+// the rest of the batch's slices walked by each thread.
+static int update_chunk(int nslices, int64_t dof) {
+  const int64_t want = int64_t(1) << 21;
+  int64_t c = (int64_t(nslices) * dof + want - 1) / want;
+  return int(std::max<int64_t>(1, std::min<int64_t>(c, nslices)));
 }
 
 template <typename TS>
@@ -301,20 +316,23 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
                                   : static_cast<const char *>(d_Uout);
       if (uin) uin += size_t(n0) * dof * sbytes;
       char *uout = static_cast<char *>(d_Uout) + size_t(n0) * dof * sbytes;
-      int64_t tot = int64_t(nb) * dof;
-      // state read + write, jc*s stage fields read, tables read once
+      const int chunk = update_chunk(nb, dof);
+      const int64_t tot = int64_t((nb + chunk - 1) / chunk) * dof;
+      // state read + write, jc*s stage fields read, tables read once per chunk
       TimedScope ts(g, PE_K_UPDATE, 0.0,
-                    double(tot) * sbytes * (2.0 + double(jc) * s) + double(1 + s) * dof * 8.0, st);
+                    double(nb) * dof * sbytes * (2.0 + double(jc) * s) +
+                        double(1 + s) * dof * 8.0 * double((nb + chunk - 1) / chunk),
+                    st);
       if (fp64)
         k_update<double, double><<<blocks_for(tot), 256, 0, st>>>(
             D, g->ax[0].d_sig, g->ax[1].d_sig, g->ax[2].d_sig, d_E, d_B, s,
             reinterpret_cast<const double *>(uin), reinterpret_cast<double *>(uout),
-            static_cast<const double *>(res), nb, jc, dof, g->dofp);
+            static_cast<const double *>(res), nb, chunk, jc, dof, g->dofp);
       else
         k_update<float, float><<<blocks_for(tot), 256, 0, st>>>(
             D, g->ax[0].d_sig, g->ax[1].d_sig, g->ax[2].d_sig, d_E, d_B, s,
             reinterpret_cast<const float *>(uin), reinterpret_cast<float *>(uout),
-            static_cast<const float *>(res), nb, jc, dof, g->dofp);
+            static_cast<const float *>(res), nb, chunk, jc, dof, g->dofp);
       PE_HIP(hipGetLastError());
     }
   }

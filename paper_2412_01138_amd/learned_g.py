@@ -54,16 +54,20 @@ def init_params(seed: int) -> np.ndarray:
 
 
 def training_rows(template, seeds: Sequence[int], grid_n: Optional[Sequence[int]] = None,
-                  rel_thresh: float = 1e-9, log=None, family=None):
+                  rel_thresh: float = 1e-9, log=None, family=None, precision: str = "fp64"):
     """Rows (x, target, s) on `template`'s box/slicing for each forcing seed;
     family = (modes, omega_lo, omega_hi, largest wavenumber) of the seeded
-    sine-mode forcings (default: the workload's own)."""
+    sine-mode forcings (default: the workload's own).  The responses are
+    computed at `precision` (FP64 by default: the targets are differences of
+    two responses, which an FP32 state would resolve only coarsely)."""
     import torch
     import workloads as wl
     if family is None:
         family = WORKLOAD_FAMILY.get(_workload_id(template), (12, 5.0, 50.0, 32))
     modes, wlo, whi, kmax = family
-    prob = template if grid_n is None else template.with_(n=tuple(grid_n))
+    prob = template.with_(precision=precision)
+    if grid_n is not None:
+        prob = prob.with_(n=tuple(grid_n))
     g = peifem.Grid(prob.n, prob.lo, prob.hi, prob.D, prob.precision)
     EF, BF = g.phi_tables(prob.dt, prob.c_fine)
     EG, BG = g.phi_tables(prob.dT, prob.c_coarse)
@@ -86,7 +90,7 @@ def training_rows(template, seeds: Sequence[int], grid_n: Optional[Sequence[int]
         xs.append(x.clone())
         ts.append(t.clone())
         ss.append(sc.clone())
-        if log and (i + 1) % max(1, len(seeds) // 8) == 0:
+        if log and (i + 1) % max(1, len(seeds) // 16) == 0:
             log(f"  rows: {i + 1}/{len(seeds)} forcings, {sum(len(q) for q in ts)} rows, "
                 f"{time.perf_counter() - t0:.1f} s")
     return torch.cat(xs), torch.cat(ts), torch.cat(ss)
