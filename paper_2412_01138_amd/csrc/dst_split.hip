@@ -16,7 +16,11 @@
 // The first pass can generate its input from the quadrature tables, as in the
 // FP64 path: the folded load row of field f, row r is
 //     sum_m rf[r][m] Cf[h][m][p],  rf = coef[f][m] prod_{a<d-1} C_a[m][j_a],
-// evaluated in fp32 from the FP64 tables.
+// a product with k = the (at most 32) forcing terms, done on the same bf16
+// MFMA as the transform with hi/lo splits of both factors (three products,
+// fp32 accumulation): A = Cf^T of this half (bf16 hi/lo, [p][m] in LDS),
+// B = the wave's row factors (registers), C = the tile transposed, so a lane
+// holds four consecutive p of one row.
 //
 // Block: 256 threads = 4 waves (2 x 2), tile BM (modes) x 128 (rows r),
 // k-step 32, single LDS buffer with register prefetch.
@@ -35,8 +39,8 @@ constexpr int SKB = 32;          // k-step
 constexpr int SBN = 128;         // block tile along r
 constexpr int SLD = SKB + 8;     // LDS row length in bf16 (16-byte pad: conflict-free b128 reads)
 constexpr int SNT = 256;
-constexpr int SGEN_MAX_TERMS = 32;
-constexpr int SGEN_MAX_CF = 8192;   // floats of one folded half table kept in LDS
+constexpr int SGEN_MAX_TERMS = 32;   // one 32-deep MFMA k-step over the terms
+constexpr int SGEN_LD = 40;          // LDS row length (bf16) of the transposed table
 
 typedef float f8 __attribute__((ext_vector_type(8)));
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));   // dword-aligned loads
@@ -68,16 +72,16 @@ struct alignas(16) SSmem {
   uint16_t Bhi[SBN][SLD], Blo[SBN][SLD];
 };
 
-template <int BM, int GM>
+template <int BM, bool GEN>
 __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
-  constexpr bool GEN = GM > 0;
   constexpr int TM = BM / 32;                 // MFMA tiles per wave along the modes
   constexpr int TN = 4;                       // ... along r (64 per wave)
   constexpr int ACH = BM * (SKB / 8) / SNT;   // 16-byte A chunks per thread per array (2, 1, ..)
   constexpr int EB = 16;                      // p values of one B row per thread
   static_assert(ACH >= 1 || BM == 32, "A chunk mapping");
   __shared__ SSmem<BM> sm;
-  extern __shared__ float cf_lds[];           // GEN: [M][Kh] folded table of this half
+  // GEN: Cf^T of this half as bf16 hi / lo, [Kh][SGEN_LD] each
+  extern __shared__ __align__(16) uint16_t cft[];
 
   int64_t bid = blockIdx.x;
   {
@@ -106,27 +110,45 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
   const bool brow_ok = grow < a.R;
   const int64_t grc = brow_ok ? grow : a.R - 1;
 
-  float rf[GEN ? GM : 1];
+  // GEN: the wave's 32 rows of row factors as MFMA B fragments (two 16-row
+  // tiles): lane supplies rf[row = 32 wave + 16 rt + lr][m = 8 lk + e]
+  bf16x8 rfh[GEN ? 2 : 1], rfl[GEN ? 2 : 1];
   if constexpr (GEN) {
     const int M = a.gen.M;
-    const int ncf = M * a.Kh;
-    const double *cf_src = a.gen.Cf + int64_t(h) * ncf;
-    for (int e = t; e < ncf; e += SNT) cf_lds[e] = float(cf_src[e]);
-    int j0 = 0, j1 = 0;
-    if (a.d == 2) j0 = int(grc);
-    if (a.d == 3) {
-      j0 = int(grc / a.np1);
-      j1 = int(grc - int64_t(j0) * a.np1);
+    const double *cf_src = a.gen.Cf + int64_t(h) * M * a.Kh;
+    uint16_t *cth = cft, *ctl = cft + a.Kh * SGEN_LD;
+    for (int e = t; e < a.Kh * SGEN_MAX_TERMS; e += SNT) {
+      const int p = e / SGEN_MAX_TERMS, m = e % SGEN_MAX_TERMS;
+      const float v = m < M ? float(cf_src[int64_t(m) * a.Kh + p]) : 0.0f;
+      const __bf16 hv = static_cast<__bf16>(v);
+      const __bf16 lv = static_cast<__bf16>(v - static_cast<float>(hv));
+      cth[p * SGEN_LD + m] = __builtin_bit_cast(uint16_t, hv);
+      ctl[p * SGEN_LD + m] = __builtin_bit_cast(uint16_t, lv);
     }
     const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
     const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
 #pragma unroll
-    for (int m = 0; m < GM; ++m) {
-      const int mm = m < M ? m : M - 1;
-      double v = a.gen.coef[f * M + mm];
-      if (C0) v *= C0[int64_t(mm) * a.np0 + j0];
-      if (C1) v *= C1[int64_t(mm) * a.np1 + j1];
-      rf[m] = (m < M && brow_ok) ? float(v) : 0.0f;
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t gr0 = n0 + 32 * wave + 16 * rt + lr;
+      const bool ok = gr0 < a.R;
+      const int64_t gr = ok ? gr0 : a.R - 1;
+      int j0 = 0, j1 = 0;
+      if (a.d == 2) j0 = int(gr);
+      if (a.d == 3) {
+        j0 = int(gr / a.np1);
+        j1 = int(gr - int64_t(j0) * a.np1);
+      }
+      f8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int m = 8 * lk + e;
+        const int mm = m < M ? m : M - 1;
+        double x = a.gen.coef[f * M + mm];
+        if (C0) x *= C0[int64_t(mm) * a.np0 + j0];
+        if (C1) x *= C1[int64_t(mm) * a.np1 + j1];
+        v[e] = (m < M && ok) ? float(x) : 0.0f;
+      }
+      split8(v, rfh[rt], rfl[rt]);
     }
     __syncthreads();
   }
@@ -188,31 +210,53 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
         *reinterpret_cast<u16x8 *>(&sm.Alo[c / 4][8 * (c % 4)]) = ok ? pal[u] : z;
       }
     }
+    if constexpr (GEN) {
+      // B tile rows 32 wave .. + 32, p = k0 .. k0 + 32: C^T = Cf^T rf^T
+      const uint16_t *cth = cft, *ctl = cft + a.Kh * SGEN_LD;
 #pragma unroll
-    for (int g8 = 0; g8 < EB / 8; ++g8) {
-      f8 v;
+      for (int pt = 0; pt < 2; ++pt) {
+        const int pr = (k0 + 16 * pt + lr) * SGEN_LD + 8 * lk;
+        const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(cth + pr);
+        const bf16x8 al = *reinterpret_cast<const bf16x8 *>(ctl + pr);
 #pragma unroll
-      for (int e8 = 0; e8 < 8; ++e8) {
-        const int e = 8 * g8 + e8;
-        const int p = k0 + pb0 + e;
-        float x;
-        if constexpr (GEN) {
-          const int Mm1 = a.gen.M - 1;
-          x = 0.0f;
+        for (int rt = 0; rt < 2; ++rt) {
+          f4 c = f4{0.f, 0.f, 0.f, 0.f};
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, rfh[rt], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, rfl[rt], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, rfh[rt], c, 0, 0, 0);
+          // lane holds p = 16 pt + 4 lk + r (r = 0..3) of row 32 wave + 16 rt + lr
+          uint16_t hb[4], lb[4];
 #pragma unroll
-          for (int m = 0; m < GM; ++m) x += rf[m] * cf_lds[(m < Mm1 ? m : Mm1) * a.Kh + p];
-        } else {
+          for (int r = 0; r < 4; ++r) {
+            const __bf16 hv = static_cast<__bf16>(c[r]);
+            hb[r] = __builtin_bit_cast(uint16_t, hv);
+            lb[r] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(c[r] - static_cast<float>(hv)));
+          }
+          const int row = 32 * wave + 16 * rt + lr, col = 16 * pt + 4 * lk;
+          *reinterpret_cast<uint2 *>(&sm.Bhi[row][col]) =
+              uint2{uint32_t(hb[0]) | (uint32_t(hb[1]) << 16), uint32_t(hb[2]) | (uint32_t(hb[3]) << 16)};
+          *reinterpret_cast<uint2 *>(&sm.Blo[row][col]) =
+              uint2{uint32_t(lb[0]) | (uint32_t(lb[1]) << 16), uint32_t(lb[2]) | (uint32_t(lb[3]) << 16)};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int g8 = 0; g8 < EB / 8; ++g8) {
+        f8 v;
+#pragma unroll
+        for (int e8 = 0; e8 < 8; ++e8) {
+          const int e = 8 * g8 + e8;
+          const int p = k0 + pb0 + e;
           const bool has_b = p < a.H;
           const bool has_a = has_b || (h == 0 && p == a.H && (a.n & 1));
-          x = (has_a ? pxa[e] : 0.0f) + (has_b ? (h == 0 ? pxb[e] : -pxb[e]) : 0.0f);
-          x = brow_ok ? x : 0.0f;
+          float x = (has_a ? pxa[e] : 0.0f) + (has_b ? (h == 0 ? pxb[e] : -pxb[e]) : 0.0f);
+          v[e8] = brow_ok ? x : 0.0f;
         }
-        v[e8] = x;
+        bf16x8 hi, lo;
+        split8(v, hi, lo);
+        *reinterpret_cast<bf16x8 *>(&sm.Bhi[rb][pb0 + 8 * g8]) = hi;
+        *reinterpret_cast<bf16x8 *>(&sm.Blo[rb][pb0 + 8 * g8]) = lo;
       }
-      bf16x8 hi, lo;
-      split8(v, hi, lo);
-      *reinterpret_cast<bf16x8 *>(&sm.Bhi[rb][pb0 + 8 * g8]) = hi;
-      *reinterpret_cast<bf16x8 *>(&sm.Blo[rb][pb0 + 8 * g8]) = lo;
     }
   };
 
@@ -268,37 +312,38 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
 // ------------------------------------------------------------------ dispatch
 constexpr int64_t SMAX_BLOCKS = (int64_t(1) << 24) - 1;
 
-template <int BM, int GM>
+template <int BM, bool GEN>
 static pe_status launch_split_t(SplitArgs a, int64_t count, hipStream_t st) {
   const int64_t per_f = int64_t(a.tiles_m) * a.tiles_n * 2;
   if (per_f > SMAX_BLOCKS) return set_error(PE_E_ARG, "internal: split grid too large");
   const int64_t max_f = std::max<int64_t>(1, SMAX_BLOCKS / per_f);
-  size_t dyn = GM > 0 ? sizeof(float) * size_t(a.gen.M) * a.Kh : 0;
+  size_t dyn = GEN ? 2 * sizeof(uint16_t) * size_t(a.Kh) * SGEN_LD : 0;
   for (int64_t f0 = 0; f0 < count; f0 += max_f) {
     const int64_t nf = std::min(max_f, count - f0);
     SplitArgs b = a;
-    if (GM == 0) b.X = a.X + f0 * a.R * a.np;
+    if (!GEN) b.X = a.X + f0 * a.R * a.np;
     b.Y = a.Y + f0 * a.R * a.np;
-    if (GM > 0) b.gen.coef = a.gen.coef + f0 * a.gen.M;
-    k_split_pass<BM, GM><<<dim3(unsigned(nf * per_f)), SNT, dyn, st>>>(b);
+    if (GEN) b.gen.coef = a.gen.coef + f0 * a.gen.M;
+    k_split_pass<BM, GEN><<<dim3(unsigned(nf * per_f)), SNT, dyn, st>>>(b);
     PE_HIP(hipGetLastError());
   }
   return PE_OK;
 }
 
-template <int GM>
+template <bool GEN>
 static pe_status launch_split(SplitArgs a, int64_t count, hipStream_t st) {
   const int bm = a.Kh >= 128 ? 128 : (a.Kh >= 64 ? 64 : 32);
   a.tiles_m = (a.Kh + bm - 1) / bm;
   a.tiles_n = int((a.R + SBN - 1) / SBN);
-  if (bm == 128) return launch_split_t<128, GM>(a, count, st);
-  if (bm == 64) return launch_split_t<64, GM>(a, count, st);
-  return launch_split_t<32, GM>(a, count, st);
+  if (bm == 128) return launch_split_t<128, GEN>(a, count, st);
+  if (bm == 64) return launch_split_t<64, GEN>(a, count, st);
+  return launch_split_t<32, GEN>(a, count, st);
 }
 
 bool gen_supported_split(pe_grid g, int n_terms) {
   const Axis &last = g->ax[g->dim - 1];
-  return n_terms >= 1 && n_terms <= SGEN_MAX_TERMS && int64_t(n_terms) * last.Kh <= SGEN_MAX_CF;
+  // the transposed hi/lo table of one half must fit in LDS next to the tiles
+  return n_terms >= 1 && n_terms <= SGEN_MAX_TERMS && last.Kh <= 256;
 }
 
 pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,
@@ -331,16 +376,9 @@ pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *
     a.np1 = d >= 2 ? g->ax[1].np : 1;
     if (q == 0 && gen) {
       a.gen = *gen;
-      if (gen->M <= 8)
-        PE_TRY(launch_split<8>(a, count, st));
-      else if (gen->M <= 16)
-        PE_TRY(launch_split<16>(a, count, st));
-      else if (gen->M <= 24)
-        PE_TRY(launch_split<24>(a, count, st));
-      else
-        PE_TRY(launch_split<32>(a, count, st));
+      PE_TRY(launch_split<true>(a, count, st));
     } else {
-      PE_TRY(launch_split<0>(a, count, st));
+      PE_TRY(launch_split<false>(a, count, st));
     }
     std::swap(in, out);
   }
