@@ -159,6 +159,47 @@ def learned_vs_plain(forcings: int, steps: int, repeats: int = 3):
     }
 
 
+def split_workloads(repeats: int = 2):
+    """Plain-G Parareal solves of the two 3D split-bf16 workloads (FP32 state,
+    split-bf16 transforms, tol 1e-5): wall time, iterations, fine DOF*stage
+    updates/s (whole solve), and the per-kernel HIP-event time."""
+    import torch
+    import workloads as wl
+    from paper_2412_01138_amd import peifem
+
+    out = {}
+    for cfg in (3, 5):
+        prob = wl.config(cfg)
+        g = peifem.Grid.from_problem(prob)
+        P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
+                           prob.K_max, prob.tol)
+        work = g.workspace(g.solve_workspace_bytes(P))
+        U = g.empty_states(prob.N + 1)
+        g.parareal_solve(P, U=U, work=work)
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            _, rep = g.parareal_solve(P, U=U, work=work)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / repeats
+        stats = g.get_timing()
+        g.set_timing(False)
+        upd = rep.iterations * prob.dof * prob.N * prob.J * prob.q
+        out[prob.name] = {
+            "grid": list(prob.n), "N": prob.N, "J": prob.J, "q": prob.q, "tol": prob.tol,
+            "iterations": rep.iterations, "jumps": [rep.jumps[i] for i in range(rep.iterations)],
+            "ms_per_solve": ms, "fine_updates_per_s": upd / (ms / 1e3),
+            "kernels_ms_per_launch": {k: v["ms"] / v["launches"] for k, v in stats.items()
+                                      if v["launches"]},
+            "kernels_GB_s": {k: v["bytes"] / v["ms"] / 1e6 for k, v in stats.items()
+                             if v["launches"] and v["ms"] > 0},
+        }
+        del work, U, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +209,8 @@ def main():
     ap.add_argument("--cpu-slices", type=int, default=8)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain G comparison")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the 3D split-bf16 workloads")
     ap.add_argument("--learned-forcings", type=int, default=4096)
     ap.add_argument("--learned-steps", type=int, default=60000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -284,6 +327,8 @@ def main():
         torch.cuda.synchronize()
     if not args.no_learned:
         out["learned_vs_plain_G"] = learned_vs_plain(args.learned_forcings, args.learned_steps)
+    if not args.no_3d:
+        out["split_bf16_workloads"] = split_workloads()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_slices)
     print(json.dumps(out))
