@@ -46,6 +46,13 @@ typedef float f8 __attribute__((ext_vector_type(8)));
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));   // dword-aligned loads
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
+// LDS ordering between lanes of one wave (no cross-wave exchange)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // hi = bf16(v) (round to nearest even), lo = bf16(v - hi), 8 at a time
 __device__ inline void split8(const f8 &v, bf16x8 &hi, bf16x8 &lo) {
   hi = __builtin_convertvector(v, bf16x8);
@@ -294,19 +301,40 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
     __syncthreads();
   }
 
+  // Output through a per-wave LDS scratch (the tile buffers are free after
+  // the last barrier): each 16-row group of the wave's 64 columns is written
+  // in MFMA layout, read back as rows and stored as float4 runs (256 B of
+  // one output row per 16 lanes instead of 64 B pieces of four rows).
   float *Y = a.Y + f * int64_t(a.np) * a.R;
+  constexpr int SCR = 68;   // scratch row stride (floats)
+  static_assert(sizeof(SSmem<BM>) >= 4 * 16 * SCR * sizeof(float), "scratch fits");
+  float *scr = reinterpret_cast<float *>(&sm) + wave * (16 * SCR);
+  const bool vec_ok = (a.R & 3) == 0;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int64_t col = n0 + wn * 64 + j * 16 + lr;
-      if (col >= a.R) continue;
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * (BM / 2) + i * 16 + 4 * lk + r;
-        if (row < a.Kh) Y[int64_t(h * a.Kh + row) * a.R + col] = acc[i][j][r];
+      for (int r = 0; r < 4; ++r) scr[(4 * lk + r) * SCR + j * 16 + lr] = acc[i][j][r];
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = (lane >> 4) + 4 * q, c4 = (lane & 15) * 4;
+      const int row = m0 + wm * (BM / 2) + i * 16 + rr;
+      const int64_t col = n0 + wn * 64 + c4;
+      if (row >= a.Kh || col >= a.R) continue;
+      const f4 v = *reinterpret_cast<const f4 *>(&scr[rr * SCR + c4]);
+      float *dst = Y + int64_t(h * a.Kh + row) * a.R + col;
+      if (vec_ok) {
+        *reinterpret_cast<f4 *>(dst) = v;   // R % 4 == 0: col + 3 < R
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e < a.R) dst[e] = v[e];
       }
     }
+    wave_sync();
+  }
 }
 
 // ------------------------------------------------------------------ dispatch
