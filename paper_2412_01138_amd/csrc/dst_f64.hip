@@ -374,6 +374,345 @@ __global__ __launch_bounds__(NT) void k_pass_mid(MidArgs a) {
     }
 }
 
+// ------------------------------------------------- MID pass, second level
+// For n = 2 Kh - 1 (M = Kh, Q = M / 2) each half of the fold splits again:
+// with u = fold_h(x), the output pair (i, i') of half h relates by
+//     S[k(i')][j] = (-1)^{j+1} S[k(i)][j],   i' = M-1-i (h = 0), M-2-i (h = 1),
+// so A_i = sum_{j odd} S[k(i)][j] u_j and B_i = sum_{j even} S[k(i)][j] u_j
+// give y_i = A_i + B_i and y_i' = A_i - B_i: two Q x Q products per half
+// instead of one M x M, half the multiply-adds.  Row i = Q-1 of half 1 is
+// its own partner (its B vanishes); position M-1 of half 1 is a pad (zero).
+struct Mid2Args {
+  const double *X;     // [O][np][I]
+  double *Y;           // [O][np][I]
+  int64_t O, I;
+  int np, n, H, Kh, Q;
+  const double *Sq;    // [2][2][Q][Q]
+  int tiles_m, tiles_n;
+};
+
+template <int BM, int BN>
+struct Smem2 {
+  double A[2][2][KB][BM + 1];   // [buffer][parity g][k][row]
+  double B[2][2][KB][BN + 1];
+};
+
+template <int BM, int BN>
+__global__ __launch_bounds__(NT) void k_pass_mid2(Mid2Args a) {
+  using C = Cfg<BM, BN>;
+  __shared__ Smem2<BM, BN> sm;
+
+  int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = int(bid % a.tiles_n);
+  bid /= a.tiles_n;
+  const int tm = int(bid % a.tiles_m);
+  bid /= a.tiles_m;
+  const int h = int(bid % 2);
+  const int64_t o = bid / 2;
+  const int m0 = tm * BM;
+  const int64_t n0 = int64_t(tn) * BN;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+  const double *X = a.X + o * a.np * a.I;
+
+  const int ra = t / C::TPR;
+  const int ca0 = (t % C::TPR) * C::CPT;
+  const bool arow_ok = m0 + ra < a.Q;
+  const int arow = arow_ok ? m0 + ra : a.Q - 1;
+  const double *S0 = a.Sq + (int64_t(2 * h) * a.Q + arow) * a.Q;
+  const double *S1 = a.Sq + (int64_t(2 * h + 1) * a.Q + arow) * a.Q;
+
+  // raw prefetch (input rows p = 2 jj + g and their mirrors n-1-p; p <= H)
+  double pa0[C::CPT], pa1[C::CPT], xa[2][C::B_PER], xb[2][C::B_PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < C::CPT; ++c) {
+      pa0[c] = S0[k0 + ca0 + c];
+      pa1[c] = S1[k0 + ca0 + c];
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int q = 0; q < C::B_PER; ++q) {
+        const int e = t + q * NT;
+        const int k = e / BN, nl = e % BN;
+        const int64_t col = n0 + nl;
+        const double *x = X + (col < a.I ? col : a.I - 1);
+        const int p = 2 * (k0 + k) + g;
+        xa[g][q] = x[int64_t(p) * a.I];
+        xb[g][q] = x[int64_t(a.n - 1 - p) * a.I];
+      }
+  };
+  auto store = [&](int buf, int k0) {
+#pragma unroll
+    for (int c = 0; c < C::CPT; ++c) {
+      sm.A[buf][0][ca0 + c][ra] = arow_ok ? pa0[c] : 0.0;
+      sm.A[buf][1][ca0 + c][ra] = arow_ok ? pa1[c] : 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int q = 0; q < C::B_PER; ++q) {
+        const int e = t + q * NT;
+        const int k = e / BN, nl = e % BN;
+        const int p = 2 * (k0 + k) + g;
+        double v;
+        if (p < a.H)
+          v = h == 0 ? xa[g][q] + xb[g][q] : xa[g][q] - xb[g][q];
+        else   // p == H: the middle node counts once in half 0, not at all in half 1
+          v = h == 0 ? xa[g][q] : 0.0;
+        sm.B[buf][g][k][nl] = (n0 + nl < a.I) ? v : 0.0;
+      }
+  };
+
+  d4 acc0[C::TM][C::TN], acc1[C::TM][C::TN];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) acc0[i][j] = acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = a.Q / KB;
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load((kt + 1) * KB);
+    mma_stage<BM, BN>(sm.A[buf][0], sm.B[buf][0], acc0, wm, wn, lr, lk);
+    mma_stage<BM, BN>(sm.A[buf][1], sm.B[buf][1], acc1, wm, wn, lr, lk);
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * KB);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  double *Y = a.Y + o * a.np * a.I;
+  const int M = a.Kh;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      const int64_t col = n0 + wn * (BN / 2) + j * 16 + lr;
+      if (col >= a.I) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * (BM / 2) + i * 16 + lk + 4 * r;
+        if (row >= a.Q) continue;
+        const double A = acc0[i][j][r], B = acc1[i][j][r];
+        Y[int64_t(h * a.Kh + row) * a.I + col] = A + B;
+        int pos2;
+        double v2;
+        if (h == 0) {
+          pos2 = M - 1 - row;
+          v2 = A - B;
+        } else if (row < a.Q - 1) {
+          pos2 = M - 2 - row;
+          v2 = A - B;
+        } else {
+          pos2 = M - 1;   // pad position of half 1
+          v2 = 0.0;
+        }
+        Y[int64_t(h * a.Kh + pos2) * a.I + col] = v2;
+      }
+    }
+}
+
+// ------------------------------------------------ LAST pass, second level
+// Same split as the MID pass above, on the contiguous axis: for half h and
+// parity g the folded input row is sampled at p = 2 jj + g (A operand,
+// rows r x jj, or generated from the quadrature tables at those p), the B
+// operand is SqT[h][g] (jj x i); the row of outputs gets y_i = C_0 + C_1
+// and y_i' = C_0 - C_1.
+template <int BM, int BN, int GM>
+__global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
+  constexpr bool GEN = GM > 0;
+  using C = Cfg<BM, BN>;
+  __shared__ Smem2<BM, BN> sm;
+  extern __shared__ double cf_lds[];   // GEN: folded last-axis table of this half, [M][Kh]
+
+  const int Q = a.Kh / 2;
+  int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = int(bid % a.tiles_n);
+  bid /= a.tiles_n;
+  const int h = int(bid % 2);
+  const int64_t tm = bid / 2;
+  const int64_t m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+
+  const int ra = t / C::TPR;
+  const int ca0 = (t % C::TPR) * C::CPT;
+  const int64_t grow = m0 + ra;
+  const bool row_ok = grow < a.R;
+
+  constexpr int RW = BM / 4;                 // rows generated per wave
+  constexpr int RT = RW / 16 > 0 ? RW / 16 : 1;
+  constexpr int GK = GM > 0 ? GM / 4 : 1;    // MFMA k-steps over the terms
+  double rfa[RT][GK];
+  if constexpr (GEN) {
+    const int M = a.gen.M;
+    const int ncf = M * a.Kh;
+    const double *cf_src = a.gen.Cf + int64_t(h) * ncf;
+    double stage[GEN_MAX_CF / NT];
+#pragma unroll
+    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
+      int e = t + q * NT;
+      stage[q] = cf_src[e < ncf ? e : ncf - 1];
+    }
+    const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
+    const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t gr0 = m0 + wave * RW + rt * 16 + lr;
+      const bool ok = gr0 < a.R;
+      const int64_t gr = ok ? gr0 : a.R - 1;
+      const int64_t f = gr / a.rows_per_field;
+      const int64_t rem = gr - f * a.rows_per_field;
+      int j0 = 0, j1 = 0;
+      if (a.d == 2) j0 = int(rem);
+      if (a.d == 3) {
+        j0 = int(rem / a.np1);
+        j1 = int(rem - int64_t(j0) * a.np1);
+      }
+#pragma unroll
+      for (int kk = 0; kk < GK; ++kk) {
+        const int m = lk + 4 * kk;
+        const int mm = m < M ? m : M - 1;
+        double v = a.gen.coef[f * M + mm];
+        if (C0) v *= C0[int64_t(mm) * a.np0 + j0];
+        if (C1) v *= C1[int64_t(mm) * a.np1 + j1];
+        rfa[rt][kk] = (m < M && ok) ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
+      int e = t + q * NT;
+      if (e < ncf) cf_lds[e] = stage[q];
+    }
+    __syncthreads();
+  }
+
+  // raw prefetch: input rows at p = 2 jj + g and their mirrors (p <= H)
+  double ra_a[GEN ? 1 : 2][GEN ? 1 : C::CPT], ra_b[GEN ? 1 : 2][GEN ? 1 : C::CPT];
+  double rb[2][C::B_PER];
+  const double *xrow = GEN ? nullptr : a.X + (row_ok ? grow : a.R - 1) * a.np;
+  const double *SqT = a.ShT;   // [2][2][Q][Q] when set up for this pass
+  auto load = [&](int k0) {
+    if constexpr (!GEN) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int c = 0; c < C::CPT; ++c) {
+          const int p = 2 * (k0 + ca0 + c) + g;
+          ra_a[g][c] = xrow[p];
+          ra_b[g][c] = xrow[a.n - 1 - p];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int q = 0; q < C::B_PER; ++q) {
+        const int e = t + q * NT;
+        const int k = e / BN, nl = e % BN;
+        const int col = n0 + nl;
+        rb[g][q] = SqT[(int64_t(2 * h + g) * Q + k0 + k) * Q + (col < Q ? col : Q - 1)];
+      }
+  };
+  auto store = [&](int buf, int k0) {
+    if constexpr (GEN) {
+      const int Mm1 = a.gen.M - 1;
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        double cfb[GK];
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+          const int term = lk + 4 * kk;
+          cfb[kk] = cf_lds[(term < Mm1 ? term : Mm1) * a.Kh + 2 * (k0 + lr) + g];
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          d4 gacc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kk = 0; kk < GK; ++kk)
+            gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(rfa[rt][kk], cfb[kk], gacc, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sm.A[buf][g][lr][wave * RW + rt * 16 + lk + 4 * r] = gacc[r];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int c = 0; c < C::CPT; ++c) {
+          const int p = 2 * (k0 + ca0 + c) + g;
+          double v;
+          if (p < a.H)
+            v = h == 0 ? ra_a[g][c] + ra_b[g][c] : ra_a[g][c] - ra_b[g][c];
+          else
+            v = h == 0 ? ra_a[g][c] : 0.0;
+          sm.A[buf][g][ca0 + c][ra] = row_ok ? v : 0.0;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int q = 0; q < C::B_PER; ++q) {
+        const int e = t + q * NT;
+        const int col = n0 + e % BN;
+        sm.B[buf][g][e / BN][e % BN] = col < Q ? rb[g][q] : 0.0;
+      }
+  };
+
+  d4 acc0[C::TM][C::TN], acc1[C::TM][C::TN];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) acc0[i][j] = acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = Q / KB;
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load((kt + 1) * KB);
+    mma_stage<BM, BN>(sm.A[buf][0], sm.B[buf][0], acc0, wm, wn, lr, lk);
+    mma_stage<BM, BN>(sm.A[buf][1], sm.B[buf][1], acc1, wm, wn, lr, lk);
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * KB);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  const int M = a.Kh;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      const int col = n0 + wn * (BN / 2) + j * 16 + lr;
+      if (col >= Q) continue;
+      int pos2;
+      bool diff;
+      if (h == 0) {
+        pos2 = M - 1 - col;
+        diff = true;
+      } else if (col < Q - 1) {
+        pos2 = M - 2 - col;
+        diff = true;
+      } else {
+        pos2 = M - 1;   // pad position of half 1
+        diff = false;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * (BM / 2) + i * 16 + lk + 4 * r;
+        if (row >= a.R) continue;
+        const double A = acc0[i][j][r], B = acc1[i][j][r];
+        a.Y[row * a.np + h * a.Kh + col] = A + B;
+        a.Y[row * a.np + h * a.Kh + pos2] = diff ? A - B : 0.0;
+      }
+    }
+}
+
 // ------------------------------------------------------------------ dispatch
 static int pick(int64_t extent) { return extent >= 128 ? 128 : (extent >= 64 ? 64 : 32); }
 
@@ -453,6 +792,62 @@ static pe_status launch_mid(MidArgs a, hipStream_t st) {
   return set_error(PE_E_ARG, "internal: no MID tile for %d x %d", bm, bn);
 }
 
+template <int BM, int BN, int GM>
+static pe_status launch_last2_t(LastArgs a, size_t dyn, hipStream_t st) {
+  constexpr bool GEN = GM > 0;
+  const int64_t per_row_tile = int64_t(a.tiles_n) * 2;
+  int64_t max_tm = MAX_BLOCKS / per_row_tile;
+  if (GEN) {
+    int64_t fields_per_chunk = std::max<int64_t>(1, max_tm * BM / a.rows_per_field);
+    max_tm = fields_per_chunk * a.rows_per_field / BM;
+    if (max_tm < 1 || (fields_per_chunk * a.rows_per_field) % BM != 0)
+      max_tm = (a.R + BM - 1) / BM;   // single launch (small batches)
+  }
+  const int64_t total_tm = a.tiles_m;
+  for (int64_t tm0 = 0; tm0 < total_tm; tm0 += max_tm) {
+    int64_t ntm = std::min(max_tm, total_tm - tm0);
+    if (ntm * per_row_tile > MAX_BLOCKS) return set_error(PE_E_ARG, "internal: LAST2 grid too large");
+    LastArgs b = a;
+    int64_t r0 = tm0 * BM;
+    b.R = std::min<int64_t>(a.R - r0, ntm * BM);
+    b.tiles_m = int(ntm);
+    if (!GEN) b.X = a.X + r0 * a.np;
+    b.Y = a.Y + r0 * a.np;
+    if (GEN) b.gen.coef = a.gen.coef + (r0 / a.rows_per_field) * a.gen.M;
+    k_pass_last2<BM, BN, GM><<<dim3(unsigned(ntm * per_row_tile)), NT, dyn, st>>>(b);
+    PE_HIP(hipGetLastError());
+  }
+  return PE_OK;
+}
+
+// a.ShT must point at the axis' SqT blocks
+template <int GM>
+static pe_status launch_last2(LastArgs a, hipStream_t st) {
+  constexpr int BM = 64, BN = 64;
+  a.tiles_m = int((a.R + BM - 1) / BM);
+  a.tiles_n = (a.Kh / 2 + BN - 1) / BN;
+  size_t dyn = GM > 0 ? sizeof(double) * size_t(a.gen.M) * a.Kh : 0;
+  return launch_last2_t<BM, BN, GM>(a, dyn, st);
+}
+
+static pe_status launch_mid2(Mid2Args a, hipStream_t st) {
+  constexpr int BM = 64, BN = 64;
+  a.tiles_m = (a.Q + BM - 1) / BM;
+  a.tiles_n = int((a.I + BN - 1) / BN);
+  const int64_t per_o = int64_t(a.tiles_m) * a.tiles_n * 2;
+  if (per_o > MAX_BLOCKS) return set_error(PE_E_ARG, "internal: MID2 grid too large");
+  const int64_t max_o = std::max<int64_t>(1, MAX_BLOCKS / per_o);
+  for (int64_t o0 = 0; o0 < a.O; o0 += max_o) {
+    Mid2Args b = a;
+    b.O = std::min(max_o, a.O - o0);
+    b.X = a.X + o0 * a.np * a.I;
+    b.Y = a.Y + o0 * a.np * a.I;
+    k_pass_mid2<BM, BN><<<dim3(unsigned(b.O * per_o)), NT, 0, st>>>(b);
+    PE_HIP(hipGetLastError());
+  }
+  return PE_OK;
+}
+
 bool gen_supported(pe_grid g, int n_terms) {
   const Axis &last = g->ax[g->dim - 1];
   return n_terms >= 1 && n_terms <= GEN_MAX_TERMS && int64_t(n_terms) * last.Kh <= GEN_MAX_CF;
@@ -467,10 +862,11 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
     int64_t inner = 1, outer = count;
     for (int b = ax_i + 1; b < d; ++b) inner *= g->ax[b].np;
     for (int b = 0; b < ax_i; ++b) outer *= g->ax[b].np;
-    // algorithmic work of the folded pass per line of n nodes:
-    // ceil(n/2)^2 + floor(n/2)^2 multiply-adds; every field read and written once
+    // algorithmic work per line of n nodes: one fold level,
+    // ceil(n/2)^2 + floor(n/2)^2 multiply-adds; two levels, 4 (Kh/2)^2
     double lines = double(count) * double(g->dof) / ax.n;
-    double fl = 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
+    double fl = ax.l2 ? 2.0 * lines * double(ax.Kh) * ax.Kh
+                      : 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
     TimedScope ts(g, ax_i == d - 1 ? PE_K_DST_LAST : PE_K_DST_MID, fl,
                   2.0 * double(count) * double(g->dof) * sizeof(double), st);
     if (ax_i == d - 1) {
@@ -487,7 +883,22 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
       a.rows_per_field = outer / count;
       a.np0 = g->ax[0].np;
       a.np1 = d >= 2 ? g->ax[1].np : 1;
-      if (gen) {
+      if (ax.l2) {
+        a.ShT = ax.d_SqT;
+        if (gen) {
+          a.gen = *gen;
+          if (gen->M <= 4)
+            PE_TRY(launch_last2<4>(a, st));
+          else if (gen->M <= 8)
+            PE_TRY(launch_last2<8>(a, st));
+          else if (gen->M <= 12)
+            PE_TRY(launch_last2<12>(a, st));
+          else
+            PE_TRY(launch_last2<16>(a, st));
+        } else {
+          PE_TRY(launch_last2<0>(a, st));
+        }
+      } else if (gen) {
         a.gen = *gen;
         if (gen->M <= 4)
           PE_TRY(launch_last<4>(a, st));
@@ -500,6 +911,19 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
       } else {
         PE_TRY(launch_last<0>(a, st));
       }
+    } else if (ax.l2) {
+      Mid2Args a{};
+      a.X = in;
+      a.Y = out;
+      a.O = outer;
+      a.I = inner;
+      a.np = ax.np;
+      a.n = ax.n;
+      a.H = ax.H;
+      a.Kh = ax.Kh;
+      a.Q = ax.Kh / 2;
+      a.Sq = ax.d_Sq;
+      PE_TRY(launch_mid2(a, st));
     } else {
       MidArgs a{};
       a.X = in;

@@ -99,6 +99,22 @@ __global__ void k_axis_spectra(const double *C, int np, int n, const double *sig
   spec[size_t(m) * n + k] = sig[k] * sqrt(2.0 / (n + 1)) * acc;
 }
 
+// Quarter blocks of the second even/odd level (n = 2 Kh - 1, Q = Kh / 2):
+// Sq[h][g][i][jj] = S[k][j], k = 2i + 1 + h, j = 2jj + 1 + g (1-based),
+// exact angle reduction as above; SqT is the transpose of each block.
+__global__ void k_dst_quarter(int n, int Q, double *Sq, double *SqT) {
+  const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const int hg = blockIdx.z;   // 2 h + g
+  if (jj >= Q) return;
+  const int h = hg >> 1, g = hg & 1;
+  const long long k = 2 * i + 1 + h, j = 2 * jj + 1 + g;
+  const long long m = k * j % (2LL * (n + 1));
+  const double v = sqrt(2.0 / (n + 1)) * sinpi(double(m) / double(n + 1));
+  Sq[(size_t(hg) * Q + i) * Q + jj] = v;
+  SqT[(size_t(hg) * Q + jj) * Q + i] = v;
+}
+
 // Cf[h][m][p]: the even/odd fold of the last-axis 1D load table C[m][j].
 __global__ void k_fold_table(const double *C, int np, int n, int H, int Kh, int n_terms,
                              double *Cf) {
@@ -269,6 +285,8 @@ static void free_grid_tables(pe_grid g) {
     dev_free(g->ax[a].d_ShT);
     dev_free(g->ax[a].d_Shi);
     dev_free(g->ax[a].d_Slo);
+    dev_free(g->ax[a].d_Sq);
+    dev_free(g->ax[a].d_SqT);
     dev_free(g->d_C[a]);
     dev_free(g->d_spec[a]);
   }
@@ -417,11 +435,21 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
       e = hipMalloc(&ax.d_Shi, sizeof(uint16_t) * s2);
       if (e == hipSuccess) e = hipMalloc(&ax.d_Slo, sizeof(uint16_t) * s2);
     }
+    // second fold level: FP64 grids whose axis has n = 2 Kh - 1
+    ax.l2 = precision == PE_FP64 && ax.n == 2 * ax.Kh - 1;
+    if (e == hipSuccess && ax.l2) {
+      const size_t q2 = size_t(ax.Kh / 2) * (ax.Kh / 2) * 4;
+      e = hipMalloc(&ax.d_Sq, sizeof(double) * q2);
+      if (e == hipSuccess) e = hipMalloc(&ax.d_SqT, sizeof(double) * q2);
+    }
     if (e != hipSuccess)
       return fail(set_error(PE_E_HIP, "grid table allocation failed: %s", hipGetErrorString(e)));
     k_axis_eig<<<(ax.n + 127) / 128, 128, 0, st>>>(ax.n, ax.h, ax.d_lam, ax.d_sig);
     k_dst_half<<<dim3((ax.Kh + 127) / 128, ax.Kh, 2), 128, 0, st>>>(ax.n, ax.Kh, ax.H, ax.d_Sh,
                                                                      ax.d_ShT, ax.d_Shi, ax.d_Slo);
+    if (ax.l2)
+      k_dst_quarter<<<dim3((ax.Kh / 2 + 127) / 128, ax.Kh / 2, 4), 128, 0, st>>>(
+          ax.n, ax.Kh / 2, ax.d_Sq, ax.d_SqT);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -38,6 +38,11 @@ struct Axis {
   double *d_ShT = nullptr;       // [2][Kh][Kh]  transposed halves, ShT[h][p][i]
   uint16_t *d_Shi = nullptr;     // [2][Kh][Kh] bf16 high part of Sh
   uint16_t *d_Slo = nullptr;     // [2][Kh][Kh] bf16 low part of Sh (Sh - hi)
+  // second even/odd level (n = 2 Kh - 1): Q = Kh / 2 and, for mode half h and
+  // input parity g, Sq[h][g][i][jj] = S[2i+1+h][2jj+1+g] (1-based S indices)
+  bool l2 = false;
+  double *d_Sq = nullptr;        // [2][2][Q][Q]
+  double *d_SqT = nullptr;       // [2][2][Q][Q], SqT[h][g][jj][i]
 };
 
 struct PendingTiming {

@@ -95,6 +95,12 @@ def _fine_case(dim, n, N, J, s, seed=0, n_modes=4):
     (2, (64, 64), 2, 3, 4),
     (3, (9, 33, 7), 2, 3, 4),
     (3, (20, 5, 40), 2, 2, 2),
+    # axes with n = 2^m - 1 take the second even/odd level
+    (2, (63, 63), 2, 3, 3),
+    (2, (127, 40), 2, 2, 4),
+    (2, (255, 63), 1, 2, 3),
+    (3, (63, 127, 31), 1, 2, 3),
+    (3, (127, 63, 63), 1, 2, 2),
 ])
 def test_fine_propagate(dim, n, N, J, s):
     pe = _peifem()
