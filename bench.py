@@ -278,7 +278,11 @@ def main():
                          "bytes_per_launch": st["bytes"] / st["launches"],
                          "TFLOP/s": st["flops"] / st["launches"] / (a_ms / 1e3) / 1e12,
                          "GB/s": st["bytes"] / st["launches"] / (a_ms / 1e3) / 1e9}
-    if tr["flops"] > 0:
+    # the binding roof: matrix cores when the kernel's algorithmic intensity is
+    # above the FP64 ridge (peak flops / peak bandwidth), HBM below it
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    intensity = flops_per_launch / bytes_per_launch if bytes_per_launch > 0 else float("inf")
+    if tr["flops"] > 0 and intensity >= ridge:
         achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS}
@@ -286,6 +290,9 @@ def main():
         achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS}
+    roof["intensity_flop_per_byte"] = intensity
+    roof["ridge_flop_per_byte"] = ridge
+    roof["achieved_TFLOP/s"] = flops_per_launch / (avg_ms / 1e3) / 1e12
     roof["traffic"] = measured_traffic(dom)
     roof.update({"kernel": KERNEL_NAMES[dom], "avg_launch_ms": avg_ms,
                  "flops_per_launch": flops_per_launch, "bytes_per_launch": bytes_per_launch,
