@@ -211,6 +211,8 @@ def main():
                     help="skip the learned-vs-plain G comparison")
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3D split-bf16 workloads")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="run only the 3D split-bf16 workloads (profiling)")
     ap.add_argument("--learned-forcings", type=int, default=4096)
     ap.add_argument("--learned-steps", type=int, default=60000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -228,6 +230,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.only_3d:
+        print(json.dumps({"split_bf16_workloads": split_workloads()}))
+        return
     prob = wl.config(2)
     g = peifem.Grid.from_problem(prob)
     P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
