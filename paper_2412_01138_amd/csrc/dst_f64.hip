@@ -498,7 +498,8 @@ __global__ __launch_bounds__(NT) void k_pass_mid2(Mid2Args a) {
         const int row = m0 + wm * (BM / 2) + i * 16 + lk + 4 * r;
         if (row >= a.Q) continue;
         const double A = acc0[i][j][r], B = acc1[i][j][r];
-        Y[int64_t(h * a.Kh + row) * a.I + col] = A + B;
+        // streaming stores: the next pass reads every field once
+        __builtin_nontemporal_store(A + B, &Y[int64_t(h * a.Kh + row) * a.I + col]);
         int pos2;
         double v2;
         if (h == 0) {
@@ -511,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_pass_mid2(Mid2Args a) {
           pos2 = M - 1;   // pad position of half 1
           v2 = 0.0;
         }
-        Y[int64_t(h * a.Kh + pos2) * a.I + col] = v2;
+        __builtin_nontemporal_store(v2, &Y[int64_t(h * a.Kh + pos2) * a.I + col]);
       }
     }
 }
@@ -707,8 +708,8 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
         const int64_t row = m0 + wm * (BM / 2) + i * 16 + lk + 4 * r;
         if (row >= a.R) continue;
         const double A = acc0[i][j][r], B = acc1[i][j][r];
-        a.Y[row * a.np + h * a.Kh + col] = A + B;
-        a.Y[row * a.np + h * a.Kh + pos2] = diff ? A - B : 0.0;
+        __builtin_nontemporal_store(A + B, &a.Y[row * a.np + h * a.Kh + col]);
+        __builtin_nontemporal_store(diff ? A - B : 0.0, &a.Y[row * a.np + h * a.Kh + pos2]);
       }
     }
 }

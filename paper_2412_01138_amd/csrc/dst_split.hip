@@ -326,7 +326,8 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
       const f4 v = *reinterpret_cast<const f4 *>(&scr[rr * SCR + c4]);
       float *dst = Y + int64_t(h * a.Kh + row) * a.R + col;
       if (vec_ok) {
-        *reinterpret_cast<f4 *>(dst) = v;   // R % 4 == 0: col + 3 < R
+        // R % 4 == 0: col + 3 < R; streaming store (read once by the next pass)
+        __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(dst));
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
