@@ -52,6 +52,7 @@ KERNEL_SOURCES = {
     "load": ("fine.hip", "pe_internal.h"),
     "update": ("fine.hip", "pe_internal.h"),
     "sweep": ("coarse.hip", "pe_internal.h"),
+    "mid_update": ("fused_update.hip", "pe_internal.h"),
 }
 
 
@@ -265,8 +266,11 @@ def main():
     fine_ms = sum(r.ms_fine for r in reports) / len(reports)
 
     # dominant kernel: the class with the largest total event time
-    KERNEL_NAMES = {"dst_last": "k_pass_last (last-axis folded DST-I pass + fused quadrature)",
-                    "dst_mid": "k_pass_mid (axis-0 folded DST-I pass)",
+    KERNEL_NAMES = {"dst_last": "k_pass_last2 (last-axis DST-I pass, two fold levels, "
+                                "fused load quadrature)",
+                    "dst_mid": "k_pass_mid2 (axis-0 DST-I pass, two fold levels)",
+                    "mid_update": "k_final_update (axis-0 DST-I pass fused with the diagonal "
+                                  "update)",
                     "load": "k_load_fields", "update": "k_update", "sweep": "k_sweep"}
     dom = max((k for k in stats if stats[k]["launches"]), key=lambda k: stats[k]["ms"])
     tr = stats[dom]

@@ -310,9 +310,11 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
 /* Kernel timing, for benchmarks.  While enabled, the library brackets every
  * launch of its main kernels with HIP events recorded on the launch stream
  * and accumulates, per kernel class, the launch count, the summed event time
- * and the algorithmic work of those launches: flops of the dense transform
- * (2 * DOF * n_a per field and axis pass, unpadded sizes) and HBM bytes
- * (each array read or written once, unpadded).  pe_set_timing(g, 1) enables
+ * and the algorithmic work of those launches: matrix-core flops of the
+ * folded transform (per field and axis pass, 2 (DOF/n_a) Kh_a^2 with two
+ * fold levels, 2 (DOF/n_a) (ceil(n_a/2)^2 + floor(n_a/2)^2) with one; split
+ * passes count their three bf16 products) and HBM bytes (each array read or
+ * written once, unpadded).  pe_set_timing(g, 1) enables
  * and resets the counters, pe_set_timing(g, 0) disables.  pe_get_timing
  * waits for the recorded events and fills out[0..PE_K_COUNT-1].  Errors:
  * PE_E_ARG, PE_E_HIP. */
@@ -322,7 +324,8 @@ typedef enum {
   PE_K_LOAD = 2,      /* separate stage load-vector quadrature */
   PE_K_UPDATE = 3,    /* fused diagonal update */
   PE_K_SWEEP = 4,     /* coarse / correction sweep with norms */
-  PE_K_COUNT = 5
+  PE_K_MID_UPDATE = 5,  /* axis-0 DST pass fused with the diagonal update */
+  PE_K_COUNT = 6
 } pe_kernel_class;
 
 typedef struct {

@@ -91,14 +91,6 @@ __device__ inline double fold_val(double a, double b, int h, bool has_a, bool ha
   return av + bv;
 }
 
-// Blocks are handed to the 8 XCDs round-robin by block index; remapping the
-// index gives every XCD a contiguous range of logical tiles, so the tiles of
-// one field (both halves, all column tiles) share that XCD's L2.
-__device__ inline int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  if (nblocks % 8 != 0) return bid;
-  return (bid % 8) * (nblocks / 8) + bid / 8;
-}
-
 struct LastArgs {
   const double *X;     // [R][np] nodal input (unused when generating)
   double *Y;           // [R][np] output
@@ -855,10 +847,10 @@ bool gen_supported(pe_grid g, int n_terms) {
 }
 
 pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
-                         double **result, hipStream_t st) {
+                         double **result, hipStream_t st, int stop_axis) {
   double *in = buf0, *out = buf1;
   const int d = g->dim;
-  for (int ax_i = d - 1; ax_i >= 0; --ax_i) {
+  for (int ax_i = d - 1; ax_i >= stop_axis; --ax_i) {
     const Axis &ax = g->ax[ax_i];
     int64_t inner = 1, outer = count;
     for (int b = ax_i + 1; b < d; ++b) inner *= g->ax[b].np;
@@ -868,8 +860,12 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
     double lines = double(count) * double(g->dof) / ax.n;
     double fl = ax.l2 ? 2.0 * lines * double(ax.Kh) * ax.Kh
                       : 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
-    TimedScope ts(g, ax_i == d - 1 ? PE_K_DST_LAST : PE_K_DST_MID, fl,
-                  2.0 * double(count) * double(g->dof) * sizeof(double), st);
+    // a generating pass writes its field and reads only the per-field
+    // coefficients; the others read and write the field
+    const bool gen_pass = gen && ax_i == d - 1;
+    const double bytes = (gen_pass ? 1.0 : 2.0) * double(count) * double(g->dof) * sizeof(double) +
+                         (gen_pass ? double(count) * gen->M * sizeof(double) : 0.0);
+    TimedScope ts(g, ax_i == d - 1 ? PE_K_DST_LAST : PE_K_DST_MID, fl, bytes, st);
     if (ax_i == d - 1) {
       LastArgs a{};
       a.X = in;

@@ -388,8 +388,10 @@ pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *
     double lines = double(count) * double(g->dof) / ax.n;
     // three bf16 products of the folded pass
     double fl = 3.0 * 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
-    TimedScope ts(g, q == 0 ? PE_K_DST_LAST : PE_K_DST_MID, fl,
-                  2.0 * double(count) * double(g->dof) * sizeof(float), st);
+    const bool gen_pass = gen && q == 0;   // writes only (plus per-field coefficients)
+    const double bytes = (gen_pass ? 1.0 : 2.0) * double(count) * double(g->dof) * sizeof(float) +
+                         (gen_pass ? double(count) * gen->M * sizeof(double) : 0.0);
+    TimedScope ts(g, q == 0 ? PE_K_DST_LAST : PE_K_DST_MID, fl, bytes, st);
     SplitArgs a{};
     a.X = in;
     a.Y = out;

@@ -201,11 +201,11 @@ static pe_status launch_load(pe_grid g, double *const *C, int n_terms, const dou
 }
 
 static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *work0, void *work1,
-                           void **result, hipStream_t st) {
+                           void **result, hipStream_t st, int stop_axis = 0) {
   if (g->precision == PE_FP64) {
     double *r = nullptr;
     PE_TRY(dst_fields_f64(g, count, gen, static_cast<double *>(work0), static_cast<double *>(work1),
-                          &r, st));
+                          &r, st, stop_axis));
     *result = r;
   } else {
     float *r = nullptr;
@@ -225,7 +225,7 @@ static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *wo
 }
 
 pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
-                             double *coef, void **result, hipStream_t st) {
+                             double *coef, void **result, hipStream_t st, int stop_axis) {
   int64_t count = b.count();
   int64_t nc = count * g->n_terms;
   k_time_coefs<<<blocks_for(nc), 256, 0, st>>>(b, g->d_terms, g->n_terms, coef, count);
@@ -240,10 +240,10 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
     gs.coef = coef;
     gs.Cf = g->d_Cf;
     gs.M = g->n_terms;
-    return transform(g, count, &gs, work0, work1, result, st);
+    return transform(g, count, &gs, work0, work1, result, st, stop_axis);
   }
   PE_TRY(launch_load(g, g->d_C, g->n_terms, coef, work0, count, st));
-  return transform(g, count, nullptr, work0, work1, result, st);
+  return transform(g, count, nullptr, work0, work1, result, st, stop_axis);
 }
 
 static size_t per_field_bytes(pe_grid g) {
@@ -271,8 +271,13 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
     PE_HIP(hipGetLastError());
     return PE_OK;
   }
+  // the axis-0 pass fused with the update needs its tables at folded
+  // positions; without room for them the separate pass + update run
+  const size_t tbytes = fused_update_table_bytes(g);
   size_t pf = per_field_bytes(g);
   size_t overhead = 3 * 256;
+  const bool fused = tbytes > 0 && work_bytes >= overhead + tbytes + pf * size_t(s);
+  if (fused) overhead += tbytes;
   if (work_bytes < overhead + pf * size_t(s))
     return set_error(PE_E_WORKSPACE, "workspace %zu B below the minimum %zu B", work_bytes,
                      overhead + pf * size_t(s));
@@ -294,7 +299,11 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
   double *coef = ar.take<double>(size_t(maxf) * std::max(g->n_terms, 1));
   char *w0 = ar.take<char>(size_t(maxf) * field_bytes(g));
   char *w1 = ar.take<char>(size_t(maxf) * field_bytes(g));
-  if (!coef || !w0 || !w1) return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  double *Ef = fused ? ar.take<double>(size_t(g->dofp)) : nullptr;
+  double *Bf = fused ? ar.take<double>(size_t(g->dofp) * s) : nullptr;
+  if (!coef || !w0 || !w1 || (fused && (!Ef || !Bf)))
+    return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
+  if (fused) PE_TRY(fused_update_tables(g, s, d_E, d_B, Ef, Bf, st));
 
   for (int n0 = 0; n0 < N; n0 += Nb) {
     int nb = std::min(Nb, N - n0);
@@ -311,11 +320,17 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
       b.dt = dt;
       for (int i = 0; i < s; ++i) b.c[i] = c[i];
       void *res = nullptr;
-      PE_TRY(load_and_transform(g, b, w0, w1, coef, &res, st));
+      PE_TRY(load_and_transform(g, b, w0, w1, coef, &res, st, fused ? 1 : 0));
       const char *uin = (j0 == 0) ? static_cast<const char *>(d_Uin)
                                   : static_cast<const char *>(d_Uout);
       if (uin) uin += size_t(n0) * dof * sbytes;
       char *uout = static_cast<char *>(d_Uout) + size_t(n0) * dof * sbytes;
+      if (fused) {
+        PE_TRY(final_pass_update(g, b, static_cast<const double *>(res), Ef, Bf,
+                                 reinterpret_cast<const double *>(uin),
+                                 reinterpret_cast<double *>(uout), st));
+        continue;
+      }
       const int chunk = update_chunk(nb, dof);
       const int64_t tot = int64_t((nb + chunk - 1) / chunk) * dof;
       // state read + write, jc*s stage fields read, tables read once per chunk
@@ -350,7 +365,7 @@ extern "C" {
 
 size_t pe_fine_workspace_bytes(pe_grid g, int64_t fields) {
   if (!g || fields < 1) return 0;
-  return 3 * 256 + size_t(fields) * per_field_bytes(g) + 3 * 256;
+  return 3 * 256 + size_t(fields) * per_field_bytes(g) + 3 * 256 + fused_update_table_bytes(g);
 }
 
 pe_status pe_fine_propagate(pe_grid g, int32_t n_slices, double t0, double dT, int32_t J,

@@ -1,0 +1,328 @@
+// Axis-0 transform pass fused with the diagonal update of eq. (2.6) (FP64,
+// axes with two even/odd fold levels, d >= 2).
+//
+// After the passes over axes d-1..1 a batch holds, for every stage field f =
+// (slice n, step j, stage i), the partial transform X_f[p][t]: p the nodes of
+// axis 0, t the folded positions of the other axes.  The rest of one fine
+// step is the axis-0 product and, per coefficient k of slice n,
+//     W_k <- E_k W_k + sum_i (b_i sigma)_k ghat_{n,j,i}(k),   j in order
+// (eq. 2.6 in the M-orthonormal basis; sigma_k turns DST coefficients into
+// M-orthonormal ones).  The update of mode k needs the transformed value of
+// mode k only, so a block owns one slice and a 16-wide strip of t and walks
+// the slice's stage fields in order: each field's strip is folded into LDS
+// (both halves), multiplied by the axis-0 quarter blocks Sq (kept in
+// registers for the whole block), and the products go straight into the
+// states, which stay in registers too.  The transformed stage fields never
+// travel through HBM: one read of the partial transform per field replaces
+// the write + read + read of the separate pass and update.
+//
+// Second fold level (axis 0, n = 2 Kh - 1, Q = Kh / 2): for half h and input
+// parity g, C_g[i][t] = sum_jj Sq[h][g][i][jj] u_h[2 jj + g][t] with u_0 =
+// x_p + x_{n-1-p}, u_1 = x_p - x_{n-1-p} (the middle node p = H counts once in
+// half 0 only); folded position h Kh + i gets C_0 + C_1 and its partner i'
+// (M-1-i for h = 0, M-2-i for h = 1; the last row of half 1 pairs with the pad
+// position M-1) gets C_0 - C_1.
+//
+// Waves: HB halves per block x Q/16 row tiles.  Wave (h, rt) owns rows
+// [16 rt, 16 rt + 16) of half h; with v_mfma_f64_16x16x4f64 (lane l supplies
+// A[l%16][l/16], B[l/16][l%16], receives C[l/16 + 4r][l%16]) each lane holds
+// the 4 rows l/16 + 4r of column l%16 for both parities, i.e. the states of
+// 8 modes.  The rounding sequence of every state is the one of the separate
+// update kernel (W = E W, then W += (b_i sigma) y per stage).
+#include <algorithm>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct FuArgs {
+  const double *X;     // [count][np0][I]: partial transforms of the batch
+  const double *Sq;    // [2][2][Q][Q] quarter blocks of axis 0
+  const double *Ef;    // [np0 * I] decay e^{-z} at folded positions (0 at pads)
+  const double *Bf;    // [s][np0 * I] b_i(z) sigma at folded positions (0 at pads)
+  const double *Uin;   // [nslices][dof] states in, or null (zero)
+  double *Uout;        // [nslices][dof] states out
+  int64_t I;           // padded inner size prod_{a>0} np_a
+  int64_t dofp;        // np0 * I
+  int64_t dof;         // prod_a n_a
+  int n0, Kh0;         // axis 0
+  int n1, Kh1, n2, Kh2, np2;   // inner axes (2D: n2 = np2 = Kh2 = 1)
+  int jc, s, strips;
+};
+
+// compact index of the mode at folded position (P0, t), -1 at pads
+__device__ inline int64_t mode_index(const FuArgs &a, int P0, int64_t t) {
+  const int k0 = unfold_pos(P0, a.Kh0);
+  const int p1 = int(t / a.np2), p2 = int(t - int64_t(p1) * a.np2);
+  const int k1 = unfold_pos(p1, a.Kh1), k2 = unfold_pos(p2, a.Kh2);
+  if (k0 >= a.n0 || k1 >= a.n1 || k2 >= a.n2) return -1;
+  return (int64_t(k0) * a.n1 + k1) * a.n2 + k2;
+}
+
+template <int Q, int HB>
+__global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
+  constexpr int RT = Q / 16;            // row tiles per half
+  constexpr int NTH = HB * RT * 64;     // threads
+  constexpr int KS = Q / 4;             // k-steps per parity
+  constexpr int KH = 2 * Q;             // folded rows per half
+  constexpr int ITEMS = KH * 8 / NTH;   // (row, column pair) loader items per thread
+  static_assert(ITEMS * NTH == KH * 8, "loader items must tile the strip");
+  constexpr bool LATE_TABLES = Q > 64;
+  __shared__ __attribute__((aligned(16))) double F[2][HB][2][Q][16];
+
+  int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  int hb = 0;
+  if (HB == 1) {
+    hb = int(bid % 2);
+    bid /= 2;
+  }
+  const int strip = int(bid % a.strips);
+  const int nl = int(bid / a.strips);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int hl = HB == 2 ? wave / RT : 0;
+  const int h = HB == 2 ? hl : hb;
+  const int rt = wave % RT;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int M = a.Kh0;
+
+  // quarter blocks of this wave's rows, both parities, as MFMA A fragments
+  double s0[KS], s1[KS];
+  {
+    const double *S0 = a.Sq + (int64_t(2 * h) * Q + rt * 16 + lr) * Q + lk;
+    const double *S1 = S0 + int64_t(Q) * Q;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      s0[ks] = S0[4 * ks];
+      s1[ks] = S1[4 * ks];
+    }
+  }
+
+  // folded positions of the lane's 8 modes (row pair r: first, partner)
+  const int64_t col = int64_t(strip) * 16 + lr;
+  int off[8];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = rt * 16 + lk + 4 * r;
+    const int i2 = h == 0 ? M - 1 - i : (i < Q - 1 ? M - 2 - i : M - 1);
+    off[2 * r] = int((h * M + i) * a.I + col);
+    off[2 * r + 1] = int((h * M + i2) * a.I + col);
+  }
+
+  const int nf = a.jc * a.s;
+  const double *Uin = a.Uin ? a.Uin + int64_t(nl) * a.dof : nullptr;
+  double W[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int64_t k = mode_index(a, off[m] / int(a.I), col);
+    W[m] = (Uin && k >= 0) ? Uin[k] : 0.0;
+  }
+
+  // strip loader: item = (folded row p, column pair), raw x_p and x_{n-1-p}
+  const int64_t fstride = int64_t(2 * M) * a.I;
+  const double *Xs = a.X + int64_t(nl) * nf * fstride + int64_t(strip) * 16;
+  double2 xa[ITEMS], xb[ITEMS];
+  auto load = [&](int e) {
+    const double *Xf = Xs + e * fstride;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const int idx = t + it * NTH, p = idx >> 3, c = (idx & 7) * 2;
+      xa[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(p) * a.I + c);
+      xb[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(a.n0 - 1 - p) * a.I + c);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const int idx = t + it * NTH, p = idx >> 3, c = (idx & 7) * 2;
+      const int g = p & 1, jj = p >> 1;
+      const bool mid = p == KH - 1;   // p = H: the middle node
+      double2 u, v;
+      u.x = mid ? xa[it].x : xa[it].x + xb[it].x;
+      u.y = mid ? xa[it].y : xa[it].y + xb[it].y;
+      v.x = mid ? 0.0 : xa[it].x - xb[it].x;
+      v.y = mid ? 0.0 : xa[it].y - xb[it].y;
+      if (HB == 2) {
+        *reinterpret_cast<double2 *>(&F[buf][0][g][jj][c]) = u;
+        *reinterpret_cast<double2 *>(&F[buf][HB - 1][g][jj][c]) = v;
+      } else {
+        *reinterpret_cast<double2 *>(&F[buf][0][g][jj][c]) = hb == 0 ? u : v;
+      }
+    }
+  };
+
+  load(0);
+  stash(0);
+  __syncthreads();
+  for (int e = 0; e < nf; ++e) {
+    const int buf = e & 1;
+    if (e + 1 < nf) load(e + 1);
+    const int i = e % a.s;
+    const double *Bi = a.Bf + int64_t(i) * a.dofp;
+    double bw[8], ew[8];
+    // the tables of this field: fetched ahead of the products where the
+    // registers allow it, after them for the larger Q
+    auto tables = [&]() {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) bw[m] = Bi[off[m]];
+      if (i == 0) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) ew[m] = a.Ef[off[m]];
+      }
+    };
+    if (!LATE_TABLES) tables();
+    d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const double b0 = F[buf][hl][0][4 * ks + lk][lr];
+      const double b1 = F[buf][hl][1][4 * ks + lk][lr];
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks], b0, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks], b1, c1, 0, 0, 0);
+    }
+    // next field's strip into the other buffer (its last readers passed the
+    // barrier that ended the previous field); frees the loader registers
+    if (e + 1 < nf) stash(buf ^ 1);
+    if (LATE_TABLES) tables();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double y1 = c0[r] + c1[r], y2 = c0[r] - c1[r];
+      double w1 = W[2 * r], w2 = W[2 * r + 1];
+      if (i == 0) {
+        w1 = ew[2 * r] * w1;
+        w2 = ew[2 * r + 1] * w2;
+      }
+      W[2 * r] = w1 + bw[2 * r] * y1;
+      W[2 * r + 1] = w2 + bw[2 * r + 1] * y2;
+    }
+    __syncthreads();
+  }
+
+  double *Uout = a.Uout + int64_t(nl) * a.dof;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int64_t k = mode_index(a, off[m] / int(a.I), col);
+    if (k >= 0) Uout[k] = W[m];
+  }
+}
+
+// Ef[P] = E[k(P)], Bf[i][P] = B[i][k(P)] sigma_k(P) at every padded folded
+// position P (zero at pads); sigma_k = prod_a sig_a(k_a), in the product
+// order of the separate update kernel.
+__global__ void k_update_tables(FuArgs a, int np0, int np1, const double *__restrict__ sig0,
+                                const double *__restrict__ sig1, const double *__restrict__ sig2,
+                                const double *__restrict__ E, const double *__restrict__ B,
+                                double *Ef, double *Bf, int d) {
+  for (int64_t P = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; P < a.dofp;
+       P += int64_t(gridDim.x) * blockDim.x) {
+    const int P0 = int(P / a.I);
+    const int64_t tt = P - int64_t(P0) * a.I;
+    const int64_t k = mode_index(a, P0, tt);
+    if (k < 0) {
+      Ef[P] = 0.0;
+      for (int i = 0; i < a.s; ++i) Bf[int64_t(i) * a.dofp + P] = 0.0;
+      continue;
+    }
+    const int k0 = unfold_pos(P0, a.Kh0);
+    const int p1 = int(tt / a.np2), p2 = int(tt - int64_t(p1) * a.np2);
+    const int k1 = unfold_pos(p1, a.Kh1), k2 = unfold_pos(p2, a.Kh2);
+    double sig = sig0[k0];
+    if (d > 1) sig *= sig1[k1];
+    if (d > 2) sig *= sig2[k2];
+    Ef[P] = E[k];
+    for (int i = 0; i < a.s; ++i) Bf[int64_t(i) * a.dofp + P] = B[int64_t(i) * a.dof + k] * sig;
+  }
+}
+
+static FuArgs base_args(pe_grid g, int s) {
+  FuArgs a{};
+  const Axis &x0 = g->ax[0];
+  a.I = g->dofp / x0.np;
+  a.dofp = g->dofp;
+  a.dof = g->dof;
+  a.n0 = x0.n;
+  a.Kh0 = x0.Kh;
+  a.n1 = g->ax[1].n;
+  a.Kh1 = g->ax[1].Kh;
+  if (g->dim == 3) {
+    a.n2 = g->ax[2].n;
+    a.Kh2 = g->ax[2].Kh;
+    a.np2 = g->ax[2].np;
+  } else {
+    a.n2 = a.Kh2 = a.np2 = 1;
+  }
+  a.s = s;
+  a.strips = int(a.I / 16);
+  return a;
+}
+
+// Largest Q whose quarter blocks, loader and states fit the 256 registers of
+// a lane at two waves per SIMD without spilling.
+constexpr int FUSED_MAX_Q = 80;
+
+bool fused_update_supported(pe_grid g) {
+  if (g->precision != PE_FP64 || g->dim < 2) return false;
+  const Axis &x0 = g->ax[0];
+  const int Q = x0.Kh / 2;
+  return x0.l2 && x0.n == 2 * x0.Kh - 1 && Q % 16 == 0 && Q >= 16 && Q <= FUSED_MAX_Q &&
+         (g->dofp / x0.np) % 16 == 0 && g->dofp < (int64_t(1) << 31);
+}
+
+size_t fused_update_table_bytes(pe_grid g) {
+  if (!fused_update_supported(g)) return 0;
+  return Arena::need(sizeof(double) * size_t(g->dofp) * (1 + PE_MAX_STAGES)) + 2 * 256;
+}
+
+pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Ef,
+                              double *Bf, hipStream_t st) {
+  FuArgs a = base_args(g, s);
+  const int64_t n = g->dofp;
+  const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
+  k_update_tables<<<blocks, 256, 0, st>>>(a, g->ax[0].np, g->ax[1].np, g->ax[0].d_sig,
+                                           g->ax[1].d_sig, g->dim > 2 ? g->ax[2].d_sig : nullptr,
+                                           E, B, Ef, Bf, g->dim);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+template <int Q>
+static void launch_q(const FuArgs &a, int64_t nslices, hipStream_t st) {
+  constexpr int HB = Q <= 64 ? 2 : 1;
+  const int64_t blocks = nslices * a.strips * (2 / HB);
+  k_final_update<Q, HB><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
+}
+
+pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Ef,
+                            const double *Bf, const double *Uin, double *Uout, hipStream_t st) {
+  if (!fused_update_supported(g)) return set_error(PE_E_ARG, "internal: no fused update here");
+  FuArgs a = base_args(g, b.s);
+  const Axis &x0 = g->ax[0];
+  a.X = X;
+  a.Sq = x0.d_Sq;
+  a.Ef = Ef;
+  a.Bf = Bf;
+  a.Uin = Uin;
+  a.Uout = Uout;
+  a.jc = b.jc;
+  const int Q = x0.Kh / 2;
+  const int64_t blocks = int64_t(b.nslices) * a.strips * (Q <= 64 ? 1 : 2);
+  if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: fused grid too large");
+  // axis-0 products (two fold levels) plus the update's reads and writes
+  const double fields = double(b.count());
+  const double flops = fields * 2.0 * double(g->dof / x0.n) * double(x0.Kh) * x0.Kh;
+  const double bytes = fields * double(g->dof) * 8.0 + 2.0 * b.nslices * double(g->dof) * 8.0 +
+                       double(1 + b.s) * double(g->dof) * 8.0;
+  TimedScope ts(g, PE_K_MID_UPDATE, flops, bytes, st);
+  switch (Q) {
+    case 16: launch_q<16>(a, b.nslices, st); break;
+    case 32: launch_q<32>(a, b.nslices, st); break;
+    case 48: launch_q<48>(a, b.nslices, st); break;
+    case 64: launch_q<64>(a, b.nslices, st); break;
+    case 80: launch_q<80>(a, b.nslices, st); break;
+    default: return set_error(PE_E_ARG, "internal: fused update Q %d", Q);
+  }
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+}  // namespace pe

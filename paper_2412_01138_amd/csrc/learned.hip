@@ -17,9 +17,6 @@
 
 namespace pe {
 
-pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
-                             double *coef, void **result, hipStream_t st);
-
 // out[f][k] = sigma_k G[f][pos(k)] for `count` fields (natural mode order)
 template <typename T>
 __global__ void k_compact_fields(int d, int n0, int n1, int n2, int np0, int np1, int np2, int Kh0,

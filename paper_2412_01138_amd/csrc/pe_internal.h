@@ -29,6 +29,17 @@ inline int half_pad(int n) { return ((n + 1) / 2 + KHALF - 1) / KHALF * KHALF; }
 // position of mode index k (0-based, mode k+1) in folded mode order
 __host__ __device__ inline int fold_pos(int k, int Kh) { return (k & 1) ? Kh + (k >> 1) : (k >> 1); }
 
+// mode index k at folded position p (inverse of fold_pos)
+__host__ __device__ inline int unfold_pos(int p, int Kh) { return p < Kh ? 2 * p : 2 * (p - Kh) + 1; }
+
+// Blocks are handed to the 8 XCDs round-robin by block index; remapping the
+// index gives every XCD a contiguous range of logical tiles, so neighbouring
+// tiles (the tiles of one field, the strips of one slice) share that XCD's L2.
+__device__ inline int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  if (nblocks % 8 != 0) return bid;
+  return (bid % 8) * (nblocks / 8) + bid / 8;
+}
+
 struct Axis {
   int n = 0, np = 0, Kh = 0, H = 0;
   double lo = 0, hi = 0, h = 0;
@@ -149,7 +160,21 @@ struct FieldBatch {
 // batch.count() padded fields of the grid's stage type; coef holds
 // count * n_terms doubles.  Returns the buffer holding the result.
 pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
-                             double *coef, void **result, hipStream_t st);
+                             double *coef, void **result, hipStream_t st, int stop_axis = 0);
+
+// Axis-0 pass fused with the diagonal update (FP64 grids, d >= 2, axis 0
+// with two fold levels and Q = Kh/2 a multiple of 16, up to a register
+// limit).  The
+// update tables at folded positions (E, and b_i sigma per stage) are built
+// once per propagation into fused_update_table_bytes of workspace.
+bool fused_update_supported(pe_grid g);
+size_t fused_update_table_bytes(pe_grid g);
+pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Ef,
+                              double *Bf, hipStream_t st);
+// X: the batch after the passes over axes d-1..1; Uin (nullable) / Uout:
+// the batch's slice states.
+pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Ef,
+                            const double *Bf, const double *Uin, double *Uout, hipStream_t st);
 
 // Load-vector generation inside the first (last-axis) transform pass: the
 // nodal load of field f at node (j_0, .., j_{d-1}) is
@@ -168,8 +193,10 @@ struct GenSrc {
 // the first pass generates its input (buf0 is then not read); otherwise
 // buf0 holds nodal fields.  Passes ping-pong between buf0 and buf1;
 // *result receives the buffer holding the coefficients (folded mode order).
+// With stop_axis = 1 the axis-0 pass is left out (done by the fused
+// axis-0 pass + update instead).
 pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
-                         double **result, hipStream_t st);
+                         double **result, hipStream_t st, int stop_axis = 0);
 // Split-bf16 variant (fp32 fields): each pass contracts the contiguous axis
 // and writes it outermost, so after d passes the axes are back in order.
 struct GenSrcF {

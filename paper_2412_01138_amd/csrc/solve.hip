@@ -63,7 +63,7 @@ size_t pe_solve_workspace_bytes(pe_grid g, const pe_solve_params *P) {
   // batch space: all fields of one fine pass, capped at 8 GiB but never
   // below one step of all slices (or one stage field set)
   int64_t all = int64_t(P->N) * P->J * P->q;
-  size_t pf = pe_fine_workspace_bytes(g, 1);
+  size_t pf = pe_fine_workspace_bytes(g, 2) - pe_fine_workspace_bytes(g, 1);
   int64_t cap = int64_t((size_t(8) << 30) / std::max<size_t>(pf, 1));
   int64_t want = std::min(all, std::max<int64_t>(cap, int64_t(P->N) * std::max(P->q, P->p)));
   want = std::max<int64_t>(want, std::max(P->q, P->p));

@@ -142,6 +142,33 @@ def test_fine_propagate_batching_is_exact():
         np.testing.assert_array_equal(part.cpu().numpy(), full)
 
 
+@pytest.mark.parametrize("dim,n,N,J,s", [
+    (2, (63, 63), 3, 4, 3),       # Q = 16, both halves per block
+    (2, (255, 40), 2, 3, 4),      # Q = 64 (the 255-node axes)
+    (2, (191, 31), 2, 2, 2),      # Q = 48
+    (2, (319, 17), 1, 2, 3),      # Q = 80, one half per block
+    (3, (127, 20, 9), 2, 2, 3),   # Q = 32, ragged inner axes
+])
+def test_fused_axis0_update_matches_separate_kernels(dim, n, N, J, s):
+    """Axis 0 with two fold levels: the axis-0 pass fused with the update
+    gives bitwise the result of the separate pass + update kernels (which run
+    when the workspace has no room for the update tables), and both match the
+    oracle."""
+    pe = _peifem()
+    prob, d, Uin = _fine_case(dim, n, N, J, s, seed=9)
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    U = _dev(Uin)
+    fused = g.fine_propagate(U, prob.t0, prob.dT, J, prob.c_fine, E, B).cpu().numpy()
+    per_field = g.fine_workspace_bytes(2) - g.fine_workspace_bytes(1)
+    work = g.workspace(3 * 256 + per_field * s)
+    sep = g.fine_propagate(U, prob.t0, prob.dT, J, prob.c_fine, E, B, work=work).cpu().numpy()
+    np.testing.assert_array_equal(fused, sep)
+    tab = d.tables(prob.dt, prob.c_fine)
+    ref = np.stack([fine_prop(d, Uin[k], prob.t0 + k * prob.dT, tab, J) for k in range(N)])
+    assert rel(fused, ref) <= 1e-12
+
+
 def test_fine_propagate_without_forcing_is_pure_decay():
     pe = _peifem()
     prob, d, Uin = _fine_case(2, (17, 12), 3, 5, 3)
