@@ -706,6 +706,142 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
     }
 }
 
+// ------------------------------------ generating LAST pass, register form
+// For two-level axes with Q a multiple of 32 up to 64 the generating pass
+// keeps its whole B operand, SqT[h] (both parities, Q x Q each), in LDS for
+// the block's lifetime and never stages the input: the quadrature product is
+// taken transposed, C[jj][r] = sum_m Cf[h][m][2 jj + g] rf[r][m], whose MFMA
+// result (lane l: jj = l/16 + 4 r', r = l%16) is exactly the A fragment of
+// the transform MFMAs for the four k-steps of its 16-wide jj chunk.  A wave
+// owns a 16-row tile and all Q output columns of its half (the quadrature is
+// done once per row tile), and walks the block's row tiles.
+//
+// LDS layout of SqT: element (g, jj, i) at g Q Q + jj Q + (i ^ 16 (jj & 1)):
+// the two 16-lane row groups of a fragment read land in opposite halves of
+// the bank space.
+constexpr int LG_TILES = 64;   // 16-row tiles per block
+
+template <int Q, int GK>
+__global__ __launch_bounds__(NT) void k_last2_gen(LastArgs a, int64_t tiles) {
+  constexpr int NC = Q / 16;           // jj chunks = output column tiles
+  __shared__ __attribute__((aligned(16))) double sq[2 * Q * Q];
+  __shared__ double cfl[2][4 * GK][Q];   // cfl[g][m][jj] = Cf[h][m][2 jj + g] (0 for m >= M)
+
+  const int h = int(blockIdx.x & 1);
+  const int64_t tile0 = int64_t(blockIdx.x >> 1) * LG_TILES;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int M = a.gen.M;
+
+  // SqT[h] -> LDS (16-byte moves, swizzled)
+  {
+    const double *src = a.ShT + int64_t(2 * h) * Q * Q;
+    for (int e = 2 * t; e < 2 * Q * Q; e += 2 * NT) {
+      const int g = e / (Q * Q), rem = e - g * Q * Q, jj = rem / Q, i = rem - jj * Q;
+      const double2 v = *reinterpret_cast<const double2 *>(src + e);
+      *reinterpret_cast<double2 *>(&sq[g * Q * Q + jj * Q + (i ^ ((jj & 1) << 4))]) = v;
+    }
+  }
+  // folded quadrature table of this half, split by parity
+  {
+    const double *cf = a.gen.Cf + int64_t(h) * M * a.Kh;
+    for (int e = t; e < 2 * 4 * GK * Q; e += NT) {
+      const int g = e / (4 * GK * Q), rem = e - g * 4 * GK * Q, m = rem / Q, jj = rem - m * Q;
+      cfl[g][m][jj] = m < M ? cf[int64_t(m) * a.Kh + 2 * jj + g] : 0.0;
+    }
+  }
+  __syncthreads();
+
+  const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
+  const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
+  // row factors rf[r][m] of row r = l%16 of a tile, m = 4 kk + l/16
+  auto row_factors = [&](int64_t tile, double (&rf)[GK]) {
+    const int64_t gr = tile * 16 + lr;
+    const int64_t f = gr / a.rows_per_field;
+    const int64_t rem = gr - f * a.rows_per_field;
+    int j0 = 0, j1 = 0;
+    if (a.d == 2) j0 = int(rem);
+    if (a.d == 3) {
+      j0 = int(rem / a.np1);
+      j1 = int(rem - int64_t(j0) * a.np1);
+    }
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      const int m = 4 * kk + lk;
+      const int mm = m < M ? m : M - 1;
+      double v = a.gen.coef[f * M + mm];
+      if (C0) v *= C0[int64_t(mm) * a.np0 + j0];
+      if (C1) v *= C1[int64_t(mm) * a.np1 + j1];
+      rf[kk] = m < M ? v : 0.0;
+    }
+  };
+
+  const int64_t tend = std::min<int64_t>(tile0 + LG_TILES, tiles);
+  int64_t tile = tile0 + wave;
+  double rf[GK], rfn[GK];
+  if (tile < tend) row_factors(tile, rf);
+  for (; tile < tend; tile += 4) {
+    if (tile + 4 < tend) row_factors(tile + 4, rfn);
+    d4 acc[NC][2];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[j][0] = acc[j][1] = d4{0.0, 0.0, 0.0, 0.0};
+    // one jj chunk per iteration (kept rolled: the operand reads of a chunk
+    // are all the registers it needs)
+#pragma unroll 1
+    for (int c = 0; c < NC; ++c) {
+      d4 gen[2];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        gen[g] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk)
+          gen[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(cfl[g][4 * kk + lk][16 * c + lr], rf[kk],
+                                                        gen[g], 0, 0, 0);
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int jj = 4 * (4 * c + rr) + lk;
+        const int sw = (jj & 1) << 4;
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            const double b = sq[g * Q * Q + jj * Q + ((16 * j + lr) ^ sw)];
+            acc[j][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(gen[g][rr], b, acc[j][g], 0, 0, 0);
+          }
+      }
+    }
+    // y_i = C_0 + C_1 at h Kh + i, C_0 - C_1 at the partner position
+    const int Mh = a.Kh;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int col = 16 * j + lr;
+      const int pos2 = h == 0 ? Mh - 1 - col : (col < Q - 1 ? Mh - 2 - col : Mh - 1);
+      const bool diff = h == 0 || col < Q - 1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = tile * 16 + lk + 4 * r;
+        const double A = acc[j][0][r], B = acc[j][1][r];
+        __builtin_nontemporal_store(A + B, &a.Y[row * a.np + h * Mh + col]);
+        __builtin_nontemporal_store(diff ? A - B : 0.0, &a.Y[row * a.np + h * Mh + pos2]);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) rf[kk] = rfn[kk];
+  }
+}
+
+template <int Q, int GM>
+static pe_status launch_last2_gen(const LastArgs &a, hipStream_t st) {
+  constexpr int GK = (GM + 3) / 4;
+  const int64_t tiles = a.R / 16;
+  const int64_t blocks = 2 * ((tiles + LG_TILES - 1) / LG_TILES);
+  if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: LAST2 grid too large");
+  k_last2_gen<Q, GK><<<dim3(unsigned(blocks)), NT, 0, st>>>(a, tiles);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
 // ------------------------------------------------------------------ dispatch
 static int pick(int64_t extent) { return extent >= 128 ? 128 : (extent >= 64 ? 64 : 32); }
 
@@ -817,6 +953,10 @@ static pe_status launch_last2_t(LastArgs a, size_t dyn, hipStream_t st) {
 template <int GM>
 static pe_status launch_last2(LastArgs a, hipStream_t st) {
   constexpr int BM = 64, BN = 64;
+  if constexpr (GM > 0) {
+    if (a.R % 16 == 0 && a.Kh == 128) return launch_last2_gen<64, GM>(a, st);
+    if (a.R % 16 == 0 && a.Kh == 64) return launch_last2_gen<32, GM>(a, st);
+  }
   a.tiles_m = int((a.R + BM - 1) / BM);
   a.tiles_n = (a.Kh / 2 + BN - 1) / BN;
   size_t dyn = GM > 0 ? sizeof(double) * size_t(a.gen.M) * a.Kh : 0;
