@@ -28,6 +28,7 @@
 namespace pe {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int KB = 16;
 constexpr int NT = 256;
@@ -97,6 +98,7 @@ struct LastArgs {
   int64_t R;
   int np, n, H, Kh;
   const double *ShT;   // [2][Kh][Kh]
+  const double *L3;    // third-level B operands (generating pass), or null
   int tiles_m, tiles_n;
   // generation (GEN kernels)
   int d;               // dimension
@@ -706,26 +708,71 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
     }
 }
 
-// ------------------------------------ generating LAST pass, register form
-// For two-level axes with Q a multiple of 32 up to 64 the generating pass
-// keeps its whole B operand, SqT[h] (both parities, Q x Q each), in LDS for
-// the block's lifetime and never stages the input: the quadrature product is
-// taken transposed, C[jj][r] = sum_m Cf[h][m][2 jj + g] rf[r][m], whose MFMA
-// result (lane l: jj = l/16 + 4 r', r = l%16) is exactly the A fragment of
-// the transform MFMAs for the four k-steps of its 16-wide jj chunk.  A wave
-// owns a 16-row tile and all Q output columns of its half (the quadrature is
-// done once per row tile), and walks the block's row tiles.
-//
-// LDS layout of SqT: element (g, jj, i) at g Q Q + jj Q + (i ^ 16 (jj & 1)):
-// the two 16-lane row groups of a fragment read land in opposite halves of
-// the bank space.
-constexpr int LG_TILES = 64;   // 16-row tiles per block
+// ------------------------------ generating LAST pass, three fold levels
+// For two-level axes with Q = Kh/2 in {32, 64} the generating pass splits
+// three of its four Q x Q quarter products once more (the fourth, a DST-IV,
+// has no sign symmetry):
+//   h = 0, g = 1 (a DST-III): rows i and Q-1-i differ by the sign (-1)^jj,
+//     so E_i (even jj) and O_i (odd jj) give B_i = E_i + O_i and
+//     B_{Q-1-i} = E_i - O_i for i < Q/2;
+//   h = 1, g = 0 (a DST-II): inputs jj and Q-1-jj enter row i with the sign
+//     (-1)^i, so even rows take their sums and odd rows their differences;
+//   h = 1, g = 1 (a DST-I of size Q-1): inputs jj and Q-2-jj likewise (the
+//     middle input jj = Q/2-1 counts once in the sums; the last input is
+//     multiplied by zeros throughout).
+// The matrix-core work drops from 4 Q^2 to 5 Q^2 / 2 multiply-adds per row.
+// Every input-side combination is linear in the quadrature table, so it is
+// applied to the table (the K-column table cfl, built per block) rather than
+// to data; the generated inputs come out of the transposed quadrature MFMA,
+// C[k][r] = sum_m cfl[m][k] rf[r][m], already in the A-fragment layout of the
+// transform MFMAs (lane l: k = l/16 + 4 r', r = l%16).  A wave owns a 16-row
+// tile and every output of its half and walks the block's row tiles; the
+// block keeps its half's reduced B operands (3 Q^2 / 2 doubles) in LDS, each
+// [K][N] matrix with N >= 32 stored with its two 16-lane row groups in
+// opposite bank halves (column n of row k at n ^ 16 (k & 1)).
+#ifndef L3_PAIR_STORE
+#define L3_PAIR_STORE 1
+#endif
+#ifndef L3_TILES
+#define L3_TILES 128
+#endif
+constexpr int LG_TILES = L3_TILES;   // 16-row tiles per block
+
+// One reduced product over a row tile: KCN chunks of 16 generated inputs
+// (K columns from chunk KC0 of cfl) times the [K][N] operand at sb + Boff,
+// accumulated into tiles [ACC0, ACC0 + N/16).
+template <int Q, int GK, int KC0, int KCN, int N, int ACC0, int NACC>
+__device__ inline void l3_product(const double *sb, int Boff, const double (*cfl)[2 * Q],
+                                  const double (&rf)[GK], d4 (&acc)[NACC], int lr, int lk) {
+  constexpr int NTL = N / 16;
+  constexpr int SW = N >= 32 ? 16 : 0;
+#pragma unroll 1
+  for (int cc = 0; cc < KCN; ++cc) {
+    d4 gen = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk)
+      gen = __builtin_amdgcn_mfma_f64_16x16x4f64(cfl[4 * kk + lk][16 * (KC0 + cc) + lr], rf[kk],
+                                                 gen, 0, 0, 0);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int k = 16 * cc + 4 * rr + lk;
+      const int sw = (k & 1) * SW;
+#pragma unroll
+      for (int j = 0; j < NTL; ++j) {
+        const double b = sb[Boff + k * N + ((16 * j + lr) ^ sw)];
+        acc[ACC0 + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(gen[rr], b, acc[ACC0 + j], 0, 0, 0);
+      }
+    }
+  }
+}
 
 template <int Q, int GK>
-__global__ __launch_bounds__(NT) void k_last2_gen(LastArgs a, int64_t tiles) {
-  constexpr int NC = Q / 16;           // jj chunks = output column tiles
-  __shared__ __attribute__((aligned(16))) double sq[2 * Q * Q];
-  __shared__ double cfl[2][4 * GK][Q];   // cfl[g][m][jj] = Cf[h][m][2 jj + g] (0 for m >= M)
+__global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles) {
+  constexpr int Q2 = Q / 2;
+  constexpr int NACC = Q / 8;          // accumulator tiles of a row tile
+  constexpr int PER = 3 * Q * Q / 2;   // B operands per half
+  __shared__ __attribute__((aligned(16))) double sb[PER];
+  __shared__ double cfl[4 * GK][2 * Q];
 
   const int h = int(blockIdx.x & 1);
   const int64_t tile0 = int64_t(blockIdx.x >> 1) * LG_TILES;
@@ -733,21 +780,56 @@ __global__ __launch_bounds__(NT) void k_last2_gen(LastArgs a, int64_t tiles) {
   const int lr = lane & 15, lk = lane >> 4;
   const int M = a.gen.M;
 
-  // SqT[h] -> LDS (16-byte moves, swizzled)
+  // this half's reduced B operands -> LDS
   {
-    const double *src = a.ShT + int64_t(2 * h) * Q * Q;
-    for (int e = 2 * t; e < 2 * Q * Q; e += 2 * NT) {
-      const int g = e / (Q * Q), rem = e - g * Q * Q, jj = rem / Q, i = rem - jj * Q;
-      const double2 v = *reinterpret_cast<const double2 *>(src + e);
-      *reinterpret_cast<double2 *>(&sq[g * Q * Q + jj * Q + (i ^ ((jj & 1) << 4))]) = v;
+    const double *src = a.L3 + int64_t(h) * PER;
+    const int nb = h == 0 ? PER : Q * Q;
+    for (int e = 2 * t; e < nb; e += 2 * NT) {
+      int base, N, r;
+      if (h == 0 && e < Q * Q) {
+        base = 0;
+        N = Q;
+        r = e;
+      } else {
+        const int e2 = h == 0 ? e - Q * Q : e;
+        base = (h == 0 ? Q * Q : 0) + (e2 / (Q2 * Q2)) * Q2 * Q2;
+        N = Q2;
+        r = e2 % (Q2 * Q2);
+      }
+      const int k = r / N, n = r - k * N;   // n even: the pair (n, n+1) moves together
+      const int sw = N >= 32 ? (k & 1) * 16 : 0;
+      *reinterpret_cast<double2 *>(&sb[base + k * N + (n ^ sw)]) =
+          *reinterpret_cast<const double2 *>(src + e);
     }
   }
-  // folded quadrature table of this half, split by parity
+  // K-column table of this half (input-side folds applied to the table)
   {
     const double *cf = a.gen.Cf + int64_t(h) * M * a.Kh;
-    for (int e = t; e < 2 * 4 * GK * Q; e += NT) {
-      const int g = e / (4 * GK * Q), rem = e - g * 4 * GK * Q, m = rem / Q, jj = rem - m * Q;
-      cfl[g][m][jj] = m < M ? cf[int64_t(m) * a.Kh + 2 * jj + g] : 0.0;
+    for (int e = t; e < 4 * GK * 2 * Q; e += NT) {
+      const int m = e / (2 * Q), kc = e - m * 2 * Q;
+      double v = 0.0;
+      if (m < M) {
+        const double *c = cf + int64_t(m) * a.Kh;
+        if (h == 0) {
+          if (kc < Q)
+            v = c[2 * kc];
+          else if (kc < 3 * Q2)
+            v = c[2 * (2 * (kc - Q)) + 1];
+          else
+            v = c[2 * (2 * (kc - 3 * Q2) + 1) + 1];
+        } else if (kc < Q) {
+          const int jj = kc < Q2 ? kc : kc - Q2;
+          v = kc < Q2 ? c[2 * jj] + c[2 * (Q - 1 - jj)] : c[2 * jj] - c[2 * (Q - 1 - jj)];
+        } else {
+          const int jj = kc < 3 * Q2 ? kc - Q : kc - 3 * Q2;
+          if (jj < Q2 - 1)
+            v = kc < 3 * Q2 ? c[2 * jj + 1] + c[2 * (Q - 2 - jj) + 1]
+                            : c[2 * jj + 1] - c[2 * (Q - 2 - jj) + 1];
+          else
+            v = kc < 3 * Q2 ? c[2 * jj + 1] : 0.0;
+        }
+      }
+      cfl[m][kc] = v;
     }
   }
   __syncthreads();
@@ -776,54 +858,68 @@ __global__ __launch_bounds__(NT) void k_last2_gen(LastArgs a, int64_t tiles) {
     }
   };
 
+  const int Mh = a.Kh;
   const int64_t tend = std::min<int64_t>(tile0 + LG_TILES, tiles);
   int64_t tile = tile0 + wave;
   double rf[GK], rfn[GK];
   if (tile < tend) row_factors(tile, rf);
   for (; tile < tend; tile += 4) {
     if (tile + 4 < tend) row_factors(tile + 4, rfn);
-    d4 acc[NC][2];
+    d4 acc[NACC];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) acc[j][0] = acc[j][1] = d4{0.0, 0.0, 0.0, 0.0};
-    // one jj chunk per iteration (kept rolled: the operand reads of a chunk
-    // are all the registers it needs)
-#pragma unroll 1
-    for (int c = 0; c < NC; ++c) {
-      d4 gen[2];
+    for (int j = 0; j < NACC; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+    if (h == 0) {
+      l3_product<Q, GK, 0, Q / 16, Q, 0, NACC>(sb, 0, cfl, rf, acc, lr, lk);
+      l3_product<Q, GK, Q / 16, Q / 32, Q2, Q / 16, NACC>(sb, Q * Q, cfl, rf, acc, lr, lk);
+      l3_product<Q, GK, 3 * Q / 32, Q / 32, Q2, 3 * Q / 32, NACC>(sb, Q * Q + Q2 * Q2, cfl, rf,
+                                                                   acc, lr, lk);
+      // outputs: A from P00 (upper slots reversed), B from E +- O
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        gen[g] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int tt = 0; tt < Q / 32; ++tt) {
+        const int ilo = 16 * tt + lr, ihi = Q - 1 - ilo;
 #pragma unroll
-        for (int kk = 0; kk < GK; ++kk)
-          gen[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(cfl[g][4 * kk + lk][16 * c + lr], rf[kk],
-                                                        gen[g], 0, 0, 0);
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = tile * 16 + lk + 4 * r;
+          double *y = a.Y + row * a.np;
+          const double Alo = acc[tt][r], Ahi = acc[Q / 32 + tt][r];
+          const double E = acc[Q / 16 + tt][r], O = acc[3 * Q / 32 + tt][r];
+          const double Blo = E + O, Bhi = E - O;
+          __builtin_nontemporal_store(Alo + Blo, &y[ilo]);
+          __builtin_nontemporal_store(Alo - Blo, &y[Mh - 1 - ilo]);
+          __builtin_nontemporal_store(Ahi + Bhi, &y[ihi]);
+          __builtin_nontemporal_store(Ahi - Bhi, &y[Mh - 1 - ihi]);
+        }
       }
+    } else {
+      l3_product<Q, GK, 0, Q / 32, Q2, 0, NACC>(sb, 0, cfl, rf, acc, lr, lk);
+      l3_product<Q, GK, Q / 32, Q / 32, Q2, Q / 32, NACC>(sb, Q2 * Q2, cfl, rf, acc, lr, lk);
+      l3_product<Q, GK, Q / 16, Q / 32, Q2, Q / 16, NACC>(sb, 2 * Q2 * Q2, cfl, rf, acc, lr, lk);
+      l3_product<Q, GK, 3 * Q / 32, Q / 32, Q2, 3 * Q / 32, NACC>(sb, 3 * Q2 * Q2, cfl, rf, acc,
+                                                                   lr, lk);
+      // outputs: even rows from the sums, odd rows from the differences
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int jj = 4 * (4 * c + rr) + lk;
-        const int sw = (jj & 1) << 4;
+      for (int tt = 0; tt < Q / 32; ++tt) {
+        const int ie = 2 * (16 * tt + lr), io = ie + 1;
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-          for (int j = 0; j < NC; ++j) {
-            const double b = sq[g * Q * Q + jj * Q + ((16 * j + lr) ^ sw)];
-            acc[j][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(gen[g][rr], b, acc[j][g], 0, 0, 0);
-          }
-      }
-    }
-    // y_i = C_0 + C_1 at h Kh + i, C_0 - C_1 at the partner position
-    const int Mh = a.Kh;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const int col = 16 * j + lr;
-      const int pos2 = h == 0 ? Mh - 1 - col : (col < Q - 1 ? Mh - 2 - col : Mh - 1);
-      const bool diff = h == 0 || col < Q - 1;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = tile * 16 + lk + 4 * r;
-        const double A = acc[j][0][r], B = acc[j][1][r];
-        __builtin_nontemporal_store(A + B, &a.Y[row * a.np + h * Mh + col]);
-        __builtin_nontemporal_store(diff ? A - B : 0.0, &a.Y[row * a.np + h * Mh + pos2]);
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = tile * 16 + lk + 4 * r;
+          double *y = a.Y + row * a.np + Mh;
+          const double Ae = acc[tt][r], Ao = acc[Q / 32 + tt][r];
+          const double Be = acc[Q / 16 + tt][r], Bo = acc[3 * Q / 32 + tt][r];
+#if L3_PAIR_STORE
+          // rows 2k and 2k+1 are adjacent: one 16-byte store
+          const d2 yy = {Ae + Be, Ao + Bo};
+          __builtin_nontemporal_store(yy, reinterpret_cast<d2 *>(&y[ie]));
+#else
+          __builtin_nontemporal_store(Ae + Be, &y[ie]);
+          __builtin_nontemporal_store(Ao + Bo, &y[io]);
+#endif
+          __builtin_nontemporal_store(Ae - Be, &y[Mh - 2 - ie]);
+          if (io < Q - 1)
+            __builtin_nontemporal_store(Ao - Bo, &y[Mh - 2 - io]);
+          else
+            __builtin_nontemporal_store(0.0, &y[Mh - 1]);   // pad position of half 1
+        }
       }
     }
 #pragma unroll
@@ -832,12 +928,12 @@ __global__ __launch_bounds__(NT) void k_last2_gen(LastArgs a, int64_t tiles) {
 }
 
 template <int Q, int GM>
-static pe_status launch_last2_gen(const LastArgs &a, hipStream_t st) {
+static pe_status launch_last3_gen(const LastArgs &a, hipStream_t st) {
   constexpr int GK = (GM + 3) / 4;
   const int64_t tiles = a.R / 16;
   const int64_t blocks = 2 * ((tiles + LG_TILES - 1) / LG_TILES);
-  if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: LAST2 grid too large");
-  k_last2_gen<Q, GK><<<dim3(unsigned(blocks)), NT, 0, st>>>(a, tiles);
+  if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: LAST3 grid too large");
+  k_last3_gen<Q, GK><<<dim3(unsigned(blocks)), NT, 0, st>>>(a, tiles);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }
@@ -954,8 +1050,8 @@ template <int GM>
 static pe_status launch_last2(LastArgs a, hipStream_t st) {
   constexpr int BM = 64, BN = 64;
   if constexpr (GM > 0) {
-    if (a.R % 16 == 0 && a.Kh == 128) return launch_last2_gen<64, GM>(a, st);
-    if (a.R % 16 == 0 && a.Kh == 64) return launch_last2_gen<32, GM>(a, st);
+    if (a.L3 && a.R % 16 == 0 && a.Kh == 128) return launch_last3_gen<64, GM>(a, st);
+    if (a.L3 && a.R % 16 == 0 && a.Kh == 64) return launch_last3_gen<32, GM>(a, st);
   }
   a.tiles_m = int((a.R + BM - 1) / BM);
   a.tiles_n = (a.Kh / 2 + BN - 1) / BN;
@@ -998,8 +1094,11 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
     // algorithmic work per line of n nodes: one fold level,
     // ceil(n/2)^2 + floor(n/2)^2 multiply-adds; two levels, 4 (Kh/2)^2
     double lines = double(count) * double(g->dof) / ax.n;
-    double fl = ax.l2 ? 2.0 * lines * double(ax.Kh) * ax.Kh
-                      : 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
+    // (the generating pass on a three-level axis: 5/8 Kh^2)
+    const bool l3_pass = gen && ax_i == d - 1 && ax.l3 && gen->M <= GEN_MAX_TERMS;
+    double fl = l3_pass  ? 2.0 * lines * 0.625 * double(ax.Kh) * ax.Kh
+                : ax.l2 ? 2.0 * lines * double(ax.Kh) * ax.Kh
+                        : 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
     // a generating pass writes its field and reads only the per-field
     // coefficients; the others read and write the field
     const bool gen_pass = gen && ax_i == d - 1;
@@ -1022,6 +1121,7 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
       a.np1 = d >= 2 ? g->ax[1].np : 1;
       if (ax.l2) {
         a.ShT = ax.d_SqT;
+        a.L3 = ax.l3 ? ax.d_L3 : nullptr;
         if (gen) {
           a.gen = *gen;
           if (gen->M <= 4)

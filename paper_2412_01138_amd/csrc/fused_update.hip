@@ -35,6 +35,19 @@
 
 namespace pe {
 
+#ifndef FUSED_CHAINS
+#define FUSED_CHAINS 1       // accumulation chains per parity
+#endif
+#ifndef FUSED_DEPTH
+#define FUSED_DEPTH 1        // strips in flight beyond the one being multiplied
+#endif
+#ifndef FUSED_STRIP_MAJOR
+#define FUSED_STRIP_MAJOR 1
+#endif
+#ifndef FUSED_HB2_MAX_Q
+#define FUSED_HB2_MAX_Q 64   // both halves per block up to this Q
+#endif
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct FuArgs {
@@ -49,7 +62,7 @@ struct FuArgs {
   int64_t dof;         // prod_a n_a
   int n0, Kh0;         // axis 0
   int n1, Kh1, n2, Kh2, np2;   // inner axes (2D: n2 = np2 = Kh2 = 1)
-  int jc, s, strips;
+  int jc, s, strips, nslices;
 };
 
 // compact index of the mode at folded position (P0, t), -1 at pads
@@ -61,7 +74,7 @@ __device__ inline int64_t mode_index(const FuArgs &a, int P0, int64_t t) {
   return (int64_t(k0) * a.n1 + k1) * a.n2 + k2;
 }
 
-template <int Q, int HB>
+template <int Q, int HB, int DEPTH>
 __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   constexpr int RT = Q / 16;            // row tiles per half
   constexpr int NTH = HB * RT * 64;     // threads
@@ -69,17 +82,25 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   constexpr int KH = 2 * Q;             // folded rows per half
   constexpr int ITEMS = KH * 8 / NTH;   // (row, column pair) loader items per thread
   static_assert(ITEMS * NTH == KH * 8, "loader items must tile the strip");
-  constexpr bool LATE_TABLES = Q > 64;
+  constexpr bool LATE_TABLES = HB == 1;   // one half per block: four loader items
   __shared__ __attribute__((aligned(16))) double F[2][HB][2][Q][16];
 
+  // strip-major block order: the blocks an XCD runs share a few strips (and
+  // so the few update-table columns its L2 has to hold), each reading other
+  // slices' fields
   int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   int hb = 0;
   if (HB == 1) {
     hb = int(bid % 2);
     bid /= 2;
   }
+#if FUSED_STRIP_MAJOR
+  const int nl = int(bid % a.nslices);
+  const int strip = int(bid / a.nslices);
+#else
   const int strip = int(bid % a.strips);
   const int nl = int(bid / a.strips);
+#endif
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int hl = HB == 2 ? wave / RT : 0;
   const int h = HB == 2 ? hl : hb;
@@ -119,30 +140,35 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     W[m] = (Uin && k >= 0) ? Uin[k] : 0.0;
   }
 
-  // strip loader: item = (folded row p, column pair), raw x_p and x_{n-1-p}
+  // strip loader: item = (folded row p, column pair), raw x_p and x_{n-1-p};
+  // DEPTH register sets, so the strip of field e + DEPTH is in flight while
+  // field e is multiplied
   const int64_t fstride = int64_t(2 * M) * a.I;
   const double *Xs = a.X + int64_t(nl) * nf * fstride + int64_t(strip) * 16;
-  double2 xa[ITEMS], xb[ITEMS];
-  auto load = [&](int e) {
+  struct Raw {
+    double2 xa[ITEMS], xb[ITEMS];
+  };
+  Raw S[DEPTH];
+  auto load = [&](Raw &R, int e) {
     const double *Xf = Xs + e * fstride;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       const int idx = t + it * NTH, p = idx >> 3, c = (idx & 7) * 2;
-      xa[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(p) * a.I + c);
-      xb[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(a.n0 - 1 - p) * a.I + c);
+      R.xa[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(p) * a.I + c);
+      R.xb[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(a.n0 - 1 - p) * a.I + c);
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const Raw &R, int buf) {
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       const int idx = t + it * NTH, p = idx >> 3, c = (idx & 7) * 2;
       const int g = p & 1, jj = p >> 1;
       const bool mid = p == KH - 1;   // p = H: the middle node
       double2 u, v;
-      u.x = mid ? xa[it].x : xa[it].x + xb[it].x;
-      u.y = mid ? xa[it].y : xa[it].y + xb[it].y;
-      v.x = mid ? 0.0 : xa[it].x - xb[it].x;
-      v.y = mid ? 0.0 : xa[it].y - xb[it].y;
+      u.x = mid ? R.xa[it].x : R.xa[it].x + R.xb[it].x;
+      u.y = mid ? R.xa[it].y : R.xa[it].y + R.xb[it].y;
+      v.x = mid ? 0.0 : R.xa[it].x - R.xb[it].x;
+      v.y = mid ? 0.0 : R.xa[it].y - R.xb[it].y;
       if (HB == 2) {
         *reinterpret_cast<double2 *>(&F[buf][0][g][jj][c]) = u;
         *reinterpret_cast<double2 *>(&F[buf][HB - 1][g][jj][c]) = v;
@@ -152,12 +178,12 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     }
   };
 
-  load(0);
-  stash(0);
-  __syncthreads();
-  for (int e = 0; e < nf; ++e) {
+  // one field: its products from LDS buffer e & 1, the next field's strip
+  // stashed into the other buffer (its last readers passed the barrier that
+  // ended the previous field), the update of the lane's states
+  auto field = [&](int e, Raw &issue, const Raw &next) {
     const int buf = e & 1;
-    if (e + 1 < nf) load(e + 1);
+    if (e + DEPTH < nf) load(issue, e + DEPTH);
     const int i = e % a.s;
     const double *Bi = a.Bf + int64_t(i) * a.dofp;
     double bw[8], ew[8];
@@ -173,6 +199,22 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     };
     if (!LATE_TABLES) tables();
     d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+#if FUSED_CHAINS == 2
+    d4 c0b = {0.0, 0.0, 0.0, 0.0}, c1b = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ks += 2) {
+      const double b0 = F[buf][hl][0][4 * ks + lk][lr];
+      const double b1 = F[buf][hl][1][4 * ks + lk][lr];
+      const double b0b = F[buf][hl][0][4 * ks + 4 + lk][lr];
+      const double b1b = F[buf][hl][1][4 * ks + 4 + lk][lr];
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks], b0, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks], b1, c1, 0, 0, 0);
+      c0b = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks + 1], b0b, c0b, 0, 0, 0);
+      c1b = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks + 1], b1b, c1b, 0, 0, 0);
+    }
+    c0 += c0b;
+    c1 += c1b;
+#else
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const double b0 = F[buf][hl][0][4 * ks + lk][lr];
@@ -180,9 +222,8 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
       c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks], b0, c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks], b1, c1, 0, 0, 0);
     }
-    // next field's strip into the other buffer (its last readers passed the
-    // barrier that ended the previous field); frees the loader registers
-    if (e + 1 < nf) stash(buf ^ 1);
+#endif
+    if (e + 1 < nf) stash(next, buf ^ 1);
     if (LATE_TABLES) tables();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -196,6 +237,21 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
       W[2 * r + 1] = w2 + bw[2 * r + 1] * y2;
     }
     __syncthreads();
+  };
+
+  load(S[0], 0);
+  if (DEPTH == 2 && nf > 1) load(S[DEPTH - 1], 1);
+  stash(S[0], 0);
+  __syncthreads();
+  if (DEPTH == 1) {
+    for (int e = 0; e < nf; ++e) field(e, S[0], S[0]);
+  } else {
+    // field e issues field e + 2 into the set that held field e and stashes
+    // field e + 1 from the other set
+    for (int e = 0; e < nf; e += 2) {
+      field(e, S[0], S[DEPTH - 1]);
+      if (e + 1 < nf) field(e + 1, S[DEPTH - 1], S[0]);
+    }
   }
 
   double *Uout = a.Uout + int64_t(nl) * a.dof;
@@ -287,9 +343,10 @@ pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B
 
 template <int Q>
 static void launch_q(const FuArgs &a, int64_t nslices, hipStream_t st) {
-  constexpr int HB = Q <= 64 ? 2 : 1;
+  constexpr int HB = Q <= FUSED_HB2_MAX_Q ? 2 : 1;
+  constexpr int DEPTH = HB == 2 ? FUSED_DEPTH : 1;   // two raw sets fit at Q <= 64
   const int64_t blocks = nslices * a.strips * (2 / HB);
-  k_final_update<Q, HB><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
+  k_final_update<Q, HB, DEPTH><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
 }
 
 pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Ef,
@@ -304,8 +361,9 @@ pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, con
   a.Uin = Uin;
   a.Uout = Uout;
   a.jc = b.jc;
+  a.nslices = b.nslices;
   const int Q = x0.Kh / 2;
-  const int64_t blocks = int64_t(b.nslices) * a.strips * (Q <= 64 ? 1 : 2);
+  const int64_t blocks = int64_t(b.nslices) * a.strips * (Q <= FUSED_HB2_MAX_Q ? 1 : 2);
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: fused grid too large");
   // axis-0 products (two fold levels) plus the update's reads and writes
   const double fields = double(b.count());

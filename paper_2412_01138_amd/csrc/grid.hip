@@ -115,6 +115,28 @@ __global__ void k_dst_quarter(int n, int Q, double *Sq, double *SqT) {
   SqT[(size_t(hg) * Q + jj) * Q + i] = v;
 }
 
+// Third-level B operands from the quarter blocks (layout in pe_internal.h).
+__global__ void k_dst_l3(int Q, const double *Sq, double *L3) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = 3 * Q * Q / 2, h = blockIdx.y, Q2 = Q / 2;
+  if (e >= per) return;
+  auto sq = [&](int hh, int g, int i, int jj) { return Sq[((size_t(2 * hh + g)) * Q + i) * Q + jj]; };
+  double v = 0.0;
+  if (h == 0) {
+    if (e < Q * Q) {
+      const int jj = e / Q, n = e % Q;
+      v = sq(0, 0, n < Q2 ? n : 3 * Q2 - 1 - n, jj);
+    } else {
+      const int r = e - Q * Q, part = r / (Q2 * Q2), k = (r % (Q2 * Q2)) / Q2, n = r % Q2;
+      v = sq(0, 1, n, 2 * k + part);
+    }
+  } else if (e < Q * Q) {
+    const int part = e / (Q2 * Q2), k = (e % (Q2 * Q2)) / Q2, n = e % Q2;
+    v = sq(1, part >> 1, 2 * n + (part & 1), k);
+  }
+  L3[size_t(h) * per + e] = v;
+}
+
 // Cf[h][m][p]: the even/odd fold of the last-axis 1D load table C[m][j].
 __global__ void k_fold_table(const double *C, int np, int n, int H, int Kh, int n_terms,
                              double *Cf) {
@@ -287,6 +309,7 @@ static void free_grid_tables(pe_grid g) {
     dev_free(g->ax[a].d_Slo);
     dev_free(g->ax[a].d_Sq);
     dev_free(g->ax[a].d_SqT);
+    dev_free(g->ax[a].d_L3);
     dev_free(g->d_C[a]);
     dev_free(g->d_spec[a]);
   }
@@ -442,6 +465,10 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
       e = hipMalloc(&ax.d_Sq, sizeof(double) * q2);
       if (e == hipSuccess) e = hipMalloc(&ax.d_SqT, sizeof(double) * q2);
     }
+    // third level for the generating pass of the last axis
+    ax.l3 = ax.l2 && a == dim - 1 && (ax.Kh == 64 || ax.Kh == 128);
+    if (e == hipSuccess && ax.l3)
+      e = hipMalloc(&ax.d_L3, sizeof(double) * 3 * size_t(ax.Kh / 2) * (ax.Kh / 2));
     if (e != hipSuccess)
       return fail(set_error(PE_E_HIP, "grid table allocation failed: %s", hipGetErrorString(e)));
     k_axis_eig<<<(ax.n + 127) / 128, 128, 0, st>>>(ax.n, ax.h, ax.d_lam, ax.d_sig);
@@ -450,6 +477,10 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
     if (ax.l2)
       k_dst_quarter<<<dim3((ax.Kh / 2 + 127) / 128, ax.Kh / 2, 4), 128, 0, st>>>(
           ax.n, ax.Kh / 2, ax.d_Sq, ax.d_SqT);
+    if (ax.l3) {
+      const int Q = ax.Kh / 2;
+      k_dst_l3<<<dim3((3 * Q * Q / 2 + 255) / 256, 2), 256, 0, st>>>(Q, ax.d_Sq, ax.d_L3);
+    }
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);

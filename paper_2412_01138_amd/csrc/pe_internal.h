@@ -54,6 +54,15 @@ struct Axis {
   bool l2 = false;
   double *d_Sq = nullptr;        // [2][2][Q][Q]
   double *d_SqT = nullptr;       // [2][2][Q][Q], SqT[h][g][jj][i]
+  // third level (generating last-axis pass, Q a multiple of 32): per half h,
+  // the B operands [K][N] of its reduced products, 3 Q^2 / 2 doubles per h:
+  //   h = 0: P00[jj][n] = Sq[0][0][i(n)][jj] (Q x Q; i(n) = n below Q/2, else
+  //          3Q/2 - 1 - n), P01E[k][n] = Sq[0][1][n][2k], P01O[k][n] =
+  //          Sq[0][1][n][2k+1] (Q/2 x Q/2 each)
+  //   h = 1: P10S[k][n] = Sq[1][0][2n][k], P10D[k][n] = Sq[1][0][2n+1][k],
+  //          P11S[k][n] = Sq[1][1][2n][k], P11D[k][n] = Sq[1][1][2n+1][k]
+  bool l3 = false;
+  double *d_L3 = nullptr;        // [2][3 Q^2 / 2]
 };
 
 struct PendingTiming {

@@ -101,6 +101,11 @@ def _fine_case(dim, n, N, J, s, seed=0, n_modes=4):
     (2, (255, 63), 1, 2, 3),
     (3, (63, 127, 31), 1, 2, 3),
     (3, (127, 63, 63), 1, 2, 2),
+    # last axis with n = 127 / 255: the generating pass takes a third level
+    (2, (40, 127), 2, 2, 3),
+    (2, (63, 255), 2, 2, 4),
+    (2, (255, 255), 1, 2, 2),
+    (3, (9, 20, 127), 2, 2, 3),
 ])
 def test_fine_propagate(dim, n, N, J, s):
     pe = _peifem()
