@@ -299,11 +299,10 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
   double *coef = ar.take<double>(size_t(maxf) * std::max(g->n_terms, 1));
   char *w0 = ar.take<char>(size_t(maxf) * field_bytes(g));
   char *w1 = ar.take<char>(size_t(maxf) * field_bytes(g));
-  double *Ef = fused ? ar.take<double>(size_t(g->dofp)) : nullptr;
-  double *Bf = fused ? ar.take<double>(size_t(g->dofp) * s) : nullptr;
-  if (!coef || !w0 || !w1 || (fused && (!Ef || !Bf)))
+  double *Tp = fused ? ar.take<double>(size_t(g->dofp) * (1 + s)) : nullptr;
+  if (!coef || !w0 || !w1 || (fused && !Tp))
     return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
-  if (fused) PE_TRY(fused_update_tables(g, s, d_E, d_B, Ef, Bf, st));
+  if (fused) PE_TRY(fused_update_tables(g, s, d_E, d_B, Tp, st));
 
   for (int n0 = 0; n0 < N; n0 += Nb) {
     int nb = std::min(Nb, N - n0);
@@ -326,7 +325,7 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
       if (uin) uin += size_t(n0) * dof * sbytes;
       char *uout = static_cast<char *>(d_Uout) + size_t(n0) * dof * sbytes;
       if (fused) {
-        PE_TRY(final_pass_update(g, b, static_cast<const double *>(res), Ef, Bf,
+        PE_TRY(final_pass_update(g, b, static_cast<const double *>(res), Tp,
                                  reinterpret_cast<const double *>(uin),
                                  reinterpret_cast<double *>(uout), st));
         continue;

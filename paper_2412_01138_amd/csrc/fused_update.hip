@@ -53,8 +53,11 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 struct FuArgs {
   const double *X;     // [count][np0][I]: partial transforms of the batch
   const double *Sq;    // [2][2][Q][Q] quarter blocks of axis 0
-  const double *Ef;    // [np0 * I] decay e^{-z} at folded positions (0 at pads)
-  const double *Bf;    // [s][np0 * I] b_i(z) sigma at folded positions (0 at pads)
+  // update tables in the kernel's lane order (zero at pads):
+  // Tp[strip][ws][t][pair][lane][2], ws = h Q/16 + rt the wave slot, t = 0 the
+  // decay e^{-z}, t = 1 + i the weight b_i(z) sigma, pair p holding the lane's
+  // modes 2p (row l/16 + 4p of the tile) and 2p + 1 (its partner)
+  const double *Tp;
   const double *Uin;   // [nslices][dof] states in, or null (zero)
   double *Uout;        // [nslices][dof] states out
   int64_t I;           // padded inner size prod_{a>0} np_a
@@ -132,6 +135,7 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   }
 
   const int nf = a.jc * a.s;
+  const double *Tl = a.Tp + (int64_t(strip) * (2 * RT) + h * RT + rt) * (1 + a.s) * 512 + 2 * lane;
   const double *Uin = a.Uin ? a.Uin + int64_t(nl) * a.dof : nullptr;
   double W[8];
 #pragma unroll
@@ -185,16 +189,24 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     const int buf = e & 1;
     if (e + DEPTH < nf) load(issue, e + DEPTH);
     const int i = e % a.s;
-    const double *Bi = a.Bf + int64_t(i) * a.dofp;
     double bw[8], ew[8];
-    // the tables of this field: fetched ahead of the products where the
-    // registers allow it, after them for the larger Q
+    // the tables of this field (16-byte loads, contiguous across the wave):
+    // fetched ahead of the products where the registers allow it, after them
+    // for the larger Q
     auto tables = [&]() {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) bw[m] = Bi[off[m]];
+      for (int pp = 0; pp < 4; ++pp) {
+        const double2 v = *reinterpret_cast<const double2 *>(Tl + ((1 + i) * 4 + pp) * 128);
+        bw[2 * pp] = v.x;
+        bw[2 * pp + 1] = v.y;
+      }
       if (i == 0) {
 #pragma unroll
-        for (int m = 0; m < 8; ++m) ew[m] = a.Ef[off[m]];
+        for (int pp = 0; pp < 4; ++pp) {
+          const double2 v = *reinterpret_cast<const double2 *>(Tl + pp * 128);
+          ew[2 * pp] = v.x;
+          ew[2 * pp + 1] = v.y;
+        }
       }
     };
     if (!LATE_TABLES) tables();
@@ -262,31 +274,46 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   }
 }
 
-// Ef[P] = E[k(P)], Bf[i][P] = B[i][k(P)] sigma_k(P) at every padded folded
-// position P (zero at pads); sigma_k = prod_a sig_a(k_a), in the product
-// order of the separate update kernel.
-__global__ void k_update_tables(FuArgs a, int np0, int np1, const double *__restrict__ sig0,
+// The update tables in the fused kernel's lane order (layout at FuArgs::Tp):
+// entry (strip, ws, t, pair, lane, c) is the table t of the lane's mode 2
+// pair + c, i.e. E[k] or B[t-1][k] sigma_k for the mode k at its folded
+// position (zero at pads); sigma_k = prod_a sig_a(k_a), in the product order
+// of the separate update kernel.
+__global__ void k_update_tables(FuArgs a, int RT, const double *__restrict__ sig0,
                                 const double *__restrict__ sig1, const double *__restrict__ sig2,
                                 const double *__restrict__ E, const double *__restrict__ B,
-                                double *Ef, double *Bf, int d) {
-  for (int64_t P = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; P < a.dofp;
-       P += int64_t(gridDim.x) * blockDim.x) {
-    const int P0 = int(P / a.I);
-    const int64_t tt = P - int64_t(P0) * a.I;
-    const int64_t k = mode_index(a, P0, tt);
-    if (k < 0) {
-      Ef[P] = 0.0;
-      for (int i = 0; i < a.s; ++i) Bf[int64_t(i) * a.dofp + P] = 0.0;
-      continue;
+                                double *Tp, int d) {
+  const int nt = 1 + a.s;
+  const int64_t total = int64_t(a.strips) * 2 * RT * nt * 512;
+  const int M = a.Kh0, Q = M / 2;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(e & 1), lane = int((e >> 1) & 63), pp = int((e >> 7) & 3);
+    const int64_t rest = e >> 9;
+    const int tt = int(rest % nt);
+    const int64_t ws_all = rest / nt;
+    const int ws = int(ws_all % (2 * RT)), strip = int(ws_all / (2 * RT));
+    const int h = ws / RT, rt = ws % RT, lr = lane & 15, lk = lane >> 4;
+    const int i = rt * 16 + lk + 4 * pp;
+    const int i2 = h == 0 ? M - 1 - i : (i < Q - 1 ? M - 2 - i : M - 1);
+    const int P0 = h * M + (c == 0 ? i : i2);
+    const int64_t col = int64_t(strip) * 16 + lr;
+    const int64_t k = mode_index(a, P0, col);
+    double v = 0.0;
+    if (k >= 0) {
+      if (tt == 0) {
+        v = E[k];
+      } else {
+        const int k0 = unfold_pos(P0, a.Kh0);
+        const int p1 = int(col / a.np2), p2 = int(col - int64_t(p1) * a.np2);
+        const int k1 = unfold_pos(p1, a.Kh1), k2 = unfold_pos(p2, a.Kh2);
+        double sig = sig0[k0];
+        if (d > 1) sig *= sig1[k1];
+        if (d > 2) sig *= sig2[k2];
+        v = B[int64_t(tt - 1) * a.dof + k] * sig;
+      }
     }
-    const int k0 = unfold_pos(P0, a.Kh0);
-    const int p1 = int(tt / a.np2), p2 = int(tt - int64_t(p1) * a.np2);
-    const int k1 = unfold_pos(p1, a.Kh1), k2 = unfold_pos(p2, a.Kh2);
-    double sig = sig0[k0];
-    if (d > 1) sig *= sig1[k1];
-    if (d > 2) sig *= sig2[k2];
-    Ef[P] = E[k];
-    for (int i = 0; i < a.s; ++i) Bf[int64_t(i) * a.dofp + P] = B[int64_t(i) * a.dof + k] * sig;
+    Tp[e] = v;
   }
 }
 
@@ -324,19 +351,22 @@ bool fused_update_supported(pe_grid g) {
          (g->dofp / x0.np) % 16 == 0 && g->dofp < (int64_t(1) << 31);
 }
 
+// (the packed tables hold strips * Q/8 wave slots * (1 + s) * 512 = (1 + s)
+// DOF_padded doubles)
 size_t fused_update_table_bytes(pe_grid g) {
   if (!fused_update_supported(g)) return 0;
-  return Arena::need(sizeof(double) * size_t(g->dofp) * (1 + PE_MAX_STAGES)) + 2 * 256;
+  return Arena::need(sizeof(double) * size_t(g->dofp) * (1 + PE_MAX_STAGES)) + 256;
 }
 
-pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Ef,
-                              double *Bf, hipStream_t st) {
+pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Tp,
+                              hipStream_t st) {
   FuArgs a = base_args(g, s);
-  const int64_t n = g->dofp;
+  const int RT = g->ax[0].Kh / 32;
+  const int64_t n = int64_t(a.strips) * 2 * RT * (1 + s) * 512;
   const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
-  k_update_tables<<<blocks, 256, 0, st>>>(a, g->ax[0].np, g->ax[1].np, g->ax[0].d_sig,
-                                           g->ax[1].d_sig, g->dim > 2 ? g->ax[2].d_sig : nullptr,
-                                           E, B, Ef, Bf, g->dim);
+  k_update_tables<<<blocks, 256, 0, st>>>(a, RT, g->ax[0].d_sig, g->ax[1].d_sig,
+                                           g->dim > 2 ? g->ax[2].d_sig : nullptr, E, B, Tp,
+                                           g->dim);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }
@@ -349,15 +379,14 @@ static void launch_q(const FuArgs &a, int64_t nslices, hipStream_t st) {
   k_final_update<Q, HB, DEPTH><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
 }
 
-pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Ef,
-                            const double *Bf, const double *Uin, double *Uout, hipStream_t st) {
+pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tp,
+                            const double *Uin, double *Uout, hipStream_t st) {
   if (!fused_update_supported(g)) return set_error(PE_E_ARG, "internal: no fused update here");
   FuArgs a = base_args(g, b.s);
   const Axis &x0 = g->ax[0];
   a.X = X;
   a.Sq = x0.d_Sq;
-  a.Ef = Ef;
-  a.Bf = Bf;
+  a.Tp = Tp;
   a.Uin = Uin;
   a.Uout = Uout;
   a.jc = b.jc;

@@ -173,17 +173,17 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
 
 // Axis-0 pass fused with the diagonal update (FP64 grids, d >= 2, axis 0
 // with two fold levels and Q = Kh/2 a multiple of 16, up to a register
-// limit).  The
-// update tables at folded positions (E, and b_i sigma per stage) are built
-// once per propagation into fused_update_table_bytes of workspace.
+// limit).  The update tables (E, and b_i sigma per stage, in the kernel's
+// lane order) are built once per propagation into (1 + s) * DOF_padded
+// doubles of the fused_update_table_bytes of workspace.
 bool fused_update_supported(pe_grid g);
 size_t fused_update_table_bytes(pe_grid g);
-pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Ef,
-                              double *Bf, hipStream_t st);
+pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Tp,
+                              hipStream_t st);
 // X: the batch after the passes over axes d-1..1; Uin (nullable) / Uout:
 // the batch's slice states.
-pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Ef,
-                            const double *Bf, const double *Uin, double *Uout, hipStream_t st);
+pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tp,
+                            const double *Uin, double *Uout, hipStream_t st);
 
 // Load-vector generation inside the first (last-axis) transform pass: the
 // nodal load of field f at node (j_0, .., j_{d-1}) is
