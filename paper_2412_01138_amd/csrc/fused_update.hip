@@ -149,23 +149,29 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   // field e is multiplied
   const int64_t fstride = int64_t(2 * M) * a.I;
   const double *Xs = a.X + int64_t(nl) * nf * fstride + int64_t(strip) * 16;
+  // one half per block (four loader items): the strip moves in two parts, the
+  // second loaded while the first half of the products runs, so only two
+  // items are ever live
+  constexpr int PARTS = HB == 1 ? 2 : 1;
+  constexpr int PI = ITEMS / PARTS;   // items per part
   struct Raw {
-    double2 xa[ITEMS], xb[ITEMS];
+    double2 xa[PI], xb[PI];
   };
   Raw S[DEPTH];
-  auto load = [&](Raw &R, int e) {
+  auto load = [&](Raw &R, int e, int part) {
     const double *Xf = Xs + e * fstride;
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int idx = t + it * NTH, p = idx >> 3, c = (idx & 7) * 2;
-      R.xa[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(p) * a.I + c);
-      R.xb[it] = *reinterpret_cast<const double2 *>(Xf + int64_t(a.n0 - 1 - p) * a.I + c);
+    for (int q = 0; q < PI; ++q) {
+      const int idx = t + (part * PI + q) * NTH, p = idx >> 3, c = (idx & 7) * 2;
+      R.xa[q] = *reinterpret_cast<const double2 *>(Xf + int64_t(p) * a.I + c);
+      R.xb[q] = *reinterpret_cast<const double2 *>(Xf + int64_t(a.n0 - 1 - p) * a.I + c);
     }
   };
-  auto stash = [&](const Raw &R, int buf) {
+  auto stash = [&](const Raw &R, int buf, int part) {
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const int idx = t + it * NTH, p = idx >> 3, c = (idx & 7) * 2;
+    for (int q = 0; q < PI; ++q) {
+      const int it = q;
+      const int idx = t + (part * PI + q) * NTH, p = idx >> 3, c = (idx & 7) * 2;
       const int g = p & 1, jj = p >> 1;
       const bool mid = p == KH - 1;   // p = H: the middle node
       double2 u, v;
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   // ended the previous field), the update of the lane's states
   auto field = [&](int e, Raw &issue, const Raw &next) {
     const int buf = e & 1;
-    if (e + DEPTH < nf) load(issue, e + DEPTH);
+    if (e + DEPTH < nf) load(issue, e + DEPTH, 0);
     const int i = e % a.s;
     double bw[8], ew[8];
     // the tables of this field (16-byte loads, contiguous across the wave):
@@ -229,13 +235,17 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
 #else
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
+      if (PARTS == 2 && ks == KS / 2 && e + 1 < nf) {
+        stash(next, buf ^ 1, 0);
+        load(issue, e + DEPTH, 1);
+      }
       const double b0 = F[buf][hl][0][4 * ks + lk][lr];
       const double b1 = F[buf][hl][1][4 * ks + lk][lr];
       c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks], b0, c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks], b1, c1, 0, 0, 0);
     }
 #endif
-    if (e + 1 < nf) stash(next, buf ^ 1);
+    if (e + 1 < nf) stash(next, buf ^ 1, PARTS - 1);
     if (LATE_TABLES) tables();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -251,9 +261,11 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     __syncthreads();
   };
 
-  load(S[0], 0);
-  if (DEPTH == 2 && nf > 1) load(S[DEPTH - 1], 1);
-  stash(S[0], 0);
+  for (int part = 0; part < PARTS; ++part) {
+    load(S[0], 0, part);
+    stash(S[0], 0, part);
+  }
+  if (DEPTH == 2 && nf > 1) load(S[DEPTH - 1], 1, 0);
   __syncthreads();
   if (DEPTH == 1) {
     for (int e = 0; e < nf; ++e) field(e, S[0], S[0]);
@@ -341,7 +353,7 @@ static FuArgs base_args(pe_grid g, int s) {
 
 // Largest Q whose quarter blocks, loader and states fit the 256 registers of
 // a lane at two waves per SIMD without spilling.
-constexpr int FUSED_MAX_Q = 80;
+constexpr int FUSED_MAX_Q = 128;
 
 bool fused_update_supported(pe_grid g) {
   if (g->precision != PE_FP64 || g->dim < 2) return false;
@@ -406,6 +418,9 @@ pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, con
     case 48: launch_q<48>(a, b.nslices, st); break;
     case 64: launch_q<64>(a, b.nslices, st); break;
     case 80: launch_q<80>(a, b.nslices, st); break;
+    case 96: launch_q<96>(a, b.nslices, st); break;
+    case 112: launch_q<112>(a, b.nslices, st); break;
+    case 128: launch_q<128>(a, b.nslices, st); break;
     default: return set_error(PE_E_ARG, "internal: fused update Q %d", Q);
   }
   PE_HIP(hipGetLastError());

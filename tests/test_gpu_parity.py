@@ -152,6 +152,8 @@ def test_fine_propagate_batching_is_exact():
     (2, (255, 40), 2, 3, 4),      # Q = 64 (the 255-node axes)
     (2, (191, 31), 2, 2, 2),      # Q = 48
     (2, (319, 17), 1, 2, 3),      # Q = 80, one half per block
+    (2, (383, 12), 1, 2, 3),      # Q = 96
+    (2, (511, 20), 1, 2, 2),      # Q = 128 (the 511-node axes)
     (3, (127, 20, 9), 2, 2, 3),   # Q = 32, ragged inner axes
 ])
 def test_fused_axis0_update_matches_separate_kernels(dim, n, N, J, s):
