@@ -158,7 +158,9 @@ pe_status pe_fine_propagate(pe_grid g, int32_t n_slices, double t0, double dT, i
  *  - d_Uprev != NULL and d_Fout != NULL (correction sweep, eq. (2.8)):
  *        d_U[n+1] = G(d_U[n]) + d_Fout[n] - G(d_Uprev[n])
  *    d_U[0] is read, never written.  d_U, d_Uprev are [N+1][DOF] states,
- *    d_Fout, d_r and d_corr (nullable: no learned correction) [N][DOF].
+ *    d_Fout, d_r and d_corr (nullable: no learned correction) [N][DOF];
+ *    d_U must not overlap any of the arrays it is computed from (PE_E_ARG
+ *    when it starts at the same address as one of them).
  *  - d_norms (nullable, 2 doubles, device): d_norms[0] = sum over n = 1..N of
  *    ||d_U[n] - d_Uprev[n]||^2 (0 without d_Uprev), d_norms[1] = sum over
  *    n = 1..N of ||d_U[n]||^2, accumulated in FP64 in a fixed order (bitwise

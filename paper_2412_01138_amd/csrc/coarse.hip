@@ -49,42 +49,68 @@ __device__ inline void block_sum2(double &a, double &b) {
   }
 }
 
-template <typename TS>
+// CORR: a learned correction is added to r; CORRECT: the correction sweep
+// (Uprev and Fout given).  The reads of a slice do not depend on the
+// recurrence, so those of the next two slices are issued ahead.
+template <typename TS, bool CORR, bool CORRECT>
 __global__ __launch_bounds__(SWEEP_BS) void k_sweep(const double *__restrict__ E,
                                                     const TS *__restrict__ r,
                                                     const TS *__restrict__ corr,
                                                     const TS *__restrict__ Uprev,
-                                                    const TS *__restrict__ Fout, TS *U, int N,
-                                                    int64_t dof, double *partials) {
+                                                    const TS *__restrict__ Fout,
+                                                    TS *__restrict__ U, int N, int64_t dof,
+                                                    double *partials) {
   int64_t k = int64_t(blockIdx.x) * SWEEP_BS + threadIdx.x;
   double acc_jump = 0.0, acc_norm = 0.0;
   if (k < dof) {
     const double e = E[k];
     double u = double(U[k]);
-    double up = Uprev ? double(Uprev[k]) : 0.0;
-    const bool correct = Uprev != nullptr && Fout != nullptr;
-    for (int n = 0; n < N; ++n) {
+    double up = CORRECT ? double(Uprev[k]) : 0.0;
+    // slice n: base = r (+ corr), fo = Fout, un = Uprev[n+1]
+    struct Slice {
+      double base, fo, un;
+    };
+    auto fetch = [&](int n) {
       const int64_t o = int64_t(n) * dof + k;
-      double base = double(r[o]);
-      if (corr) base += double(corr[o]);
-      double gnew = e * u + base;                 // G(U^{n,(k+1)})
+      Slice v;
+      v.base = double(r[o]);
+      if (CORR) v.base += double(corr[o]);
+      v.fo = CORRECT ? double(Fout[o]) : 0.0;
+      v.un = CORRECT ? double(Uprev[o + dof]) : 0.0;
+      return v;
+    };
+    auto step = [&](int n, const Slice &c) {
+      const int64_t o = int64_t(n) * dof + k;
+      const double gnew = e * u + c.base;             // G(U^{n,(k+1)})
       double next = gnew;
-      if (correct) {
-        double gold = e * up + base;              // G(U^{n,(k)})
-        next = (gnew + double(Fout[o])) - gold;   // eq. (2.8)
+      if (CORRECT) {
+        const double gold = e * up + c.base;          // G(U^{n,(k)})
+        next = (gnew + c.fo) - gold;                  // eq. (2.8)
       }
-      TS stored = TS(next);
+      const TS stored = TS(next);
       U[o + dof] = stored;
-      double nv = double(stored);
-      if (Uprev) {
-        double upn = double(Uprev[o + dof]);
-        double dlt = nv - upn;
+      const double nv = double(stored);
+      if (CORRECT) {
+        const double dlt = nv - c.un;
         acc_jump += dlt * dlt;
-        up = upn;
+        up = c.un;
       }
       acc_norm += nv * nv;
       u = nv;
+    };
+    // two slice sets, each refilled right after use, without branches in the
+    // loop (fetches past the last slice re-read it), so the loads of the
+    // next slices stay in flight across the steps
+    const int last = N - 1;
+    Slice A = fetch(0), B = fetch(last < 1 ? last : 1);
+    int n = 0;
+    for (; n + 1 < N; n += 2) {
+      step(n, A);
+      A = fetch(n + 2 < last ? n + 2 : last);
+      step(n + 1, B);
+      B = fetch(n + 3 < last ? n + 3 : last);
     }
+    if (n < N) step(n, A);
   }
   if (partials) {
     block_sum2(acc_jump, acc_norm);
@@ -92,6 +118,26 @@ __global__ __launch_bounds__(SWEEP_BS) void k_sweep(const double *__restrict__ E
       partials[2 * blockIdx.x] = acc_jump;
       partials[2 * blockIdx.x + 1] = acc_norm;
     }
+  }
+}
+
+template <typename TS>
+static void launch_sweep(int nb, hipStream_t st, const double *E, const void *r, const void *corr,
+                         const void *Uprev, const void *Fout, void *U, int N, int64_t dof,
+                         double *partials) {
+  const TS *rr = static_cast<const TS *>(r), *cc = static_cast<const TS *>(corr);
+  const TS *up = static_cast<const TS *>(Uprev), *fo = static_cast<const TS *>(Fout);
+  TS *uu = static_cast<TS *>(U);
+  if (Uprev) {
+    if (corr)
+      k_sweep<TS, true, true><<<nb, SWEEP_BS, 0, st>>>(E, rr, cc, up, fo, uu, N, dof, partials);
+    else
+      k_sweep<TS, false, true><<<nb, SWEEP_BS, 0, st>>>(E, rr, cc, up, fo, uu, N, dof, partials);
+  } else {
+    if (corr)
+      k_sweep<TS, true, false><<<nb, SWEEP_BS, 0, st>>>(E, rr, cc, up, fo, uu, N, dof, partials);
+    else
+      k_sweep<TS, false, false><<<nb, SWEEP_BS, 0, st>>>(E, rr, cc, up, fo, uu, N, dof, partials);
   }
 }
 
@@ -123,15 +169,11 @@ pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const voi
   int arrays = 2 + (d_corr ? 1 : 0) + (d_Uprev ? 2 : 0);   // r, U write, corr, Uprev, Fout
   TimedScope ts(g, PE_K_SWEEP, 0.0, double(N) * double(g->dof) * sb * arrays + g->dof * 8.0, st);
   if (g->precision == PE_FP64)
-    k_sweep<double><<<nb, SWEEP_BS, 0, st>>>(
-        d_EG, static_cast<const double *>(d_r), static_cast<const double *>(d_corr),
-        static_cast<const double *>(d_Uprev), static_cast<const double *>(d_Fout),
-        static_cast<double *>(d_U), N, g->dof, d_norms ? partials : nullptr);
+    launch_sweep<double>(nb, st, d_EG, d_r, d_corr, d_Uprev, d_Fout, d_U, N, g->dof,
+                         d_norms ? partials : nullptr);
   else
-    k_sweep<float><<<nb, SWEEP_BS, 0, st>>>(
-        d_EG, static_cast<const float *>(d_r), static_cast<const float *>(d_corr),
-        static_cast<const float *>(d_Uprev), static_cast<const float *>(d_Fout),
-        static_cast<float *>(d_U), N, g->dof, d_norms ? partials : nullptr);
+    launch_sweep<float>(nb, st, d_EG, d_r, d_corr, d_Uprev, d_Fout, d_U, N, g->dof,
+                        d_norms ? partials : nullptr);
   PE_HIP(hipGetLastError());
   if (d_norms) {
     k_reduce_partials<<<1, SWEEP_BS, 0, st>>>(partials, nb, d_norms);
@@ -163,7 +205,8 @@ pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int
   if (n_slices < 1) return set_error(PE_E_ARG, "n_slices must be >= 1");
   if ((d_Uprev == nullptr) != (d_Fout == nullptr))
     return set_error(PE_E_ARG, "d_Uprev and d_Fout must be given together");
-  if (d_Uprev == d_U && d_U) return set_error(PE_E_ARG, "d_Uprev must differ from d_U");
+  if (d_Uprev == d_U || d_r == d_U || (d_Fout && d_Fout == d_U) || (d_corr && d_corr == d_U))
+    return set_error(PE_E_ARG, "d_U must not overlap d_r, d_corr, d_Uprev or d_Fout");
   hipStream_t st = as_stream(stream);
   Arena ar(d_work, work_bytes);
   double *partials = nullptr;

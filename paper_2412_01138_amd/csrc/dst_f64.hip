@@ -733,10 +733,13 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
 #ifndef L3_PAIR_STORE
 #define L3_PAIR_STORE 1
 #endif
-#ifndef L3_TILES
-#define L3_TILES 128
-#endif
-constexpr int LG_TILES = L3_TILES;   // 16-row tiles per block
+// 16-row tiles per block: up to LG_TILES_MAX (the block's LDS staging is
+// amortised over its tiles), fewer for small launches so that about 1024
+// blocks fill the chip
+constexpr int LG_TILES_MAX = 128;
+static int64_t lg_tiles(int64_t tiles) {
+  return std::max<int64_t>(4, std::min<int64_t>(LG_TILES_MAX, tiles / 512));
+}
 
 // One reduced product over a row tile: KCN chunks of 16 generated inputs
 // (K columns from chunk KC0 of cfl) times the [K][N] operand at sb + Boff,
@@ -767,7 +770,7 @@ __device__ inline void l3_product(const double *sb, int Boff, const double (*cfl
 }
 
 template <int Q, int GK>
-__global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles) {
+__global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles, int64_t per_block) {
   constexpr int Q2 = Q / 2;
   constexpr int NACC = Q / 8;          // accumulator tiles of a row tile
   constexpr int PER = 3 * Q * Q / 2;   // B operands per half
@@ -775,7 +778,7 @@ __global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles) {
   __shared__ double cfl[4 * GK][2 * Q];
 
   const int h = int(blockIdx.x & 1);
-  const int64_t tile0 = int64_t(blockIdx.x >> 1) * LG_TILES;
+  const int64_t tile0 = int64_t(blockIdx.x >> 1) * per_block;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int M = a.gen.M;
@@ -859,7 +862,7 @@ __global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles) {
   };
 
   const int Mh = a.Kh;
-  const int64_t tend = std::min<int64_t>(tile0 + LG_TILES, tiles);
+  const int64_t tend = std::min<int64_t>(tile0 + per_block, tiles);
   int64_t tile = tile0 + wave;
   double rf[GK], rfn[GK];
   if (tile < tend) row_factors(tile, rf);
@@ -931,9 +934,10 @@ template <int Q, int GM>
 static pe_status launch_last3_gen(const LastArgs &a, hipStream_t st) {
   constexpr int GK = (GM + 3) / 4;
   const int64_t tiles = a.R / 16;
-  const int64_t blocks = 2 * ((tiles + LG_TILES - 1) / LG_TILES);
+  const int64_t per = lg_tiles(tiles);
+  const int64_t blocks = 2 * ((tiles + per - 1) / per);
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: LAST3 grid too large");
-  k_last3_gen<Q, GK><<<dim3(unsigned(blocks)), NT, 0, st>>>(a, tiles);
+  k_last3_gen<Q, GK><<<dim3(unsigned(blocks)), NT, 0, st>>>(a, tiles, per);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }

@@ -35,11 +35,8 @@
 
 namespace pe {
 
-#ifndef FUSED_CHAINS
-#define FUSED_CHAINS 1       // accumulation chains per parity
-#endif
-#ifndef FUSED_DEPTH
-#define FUSED_DEPTH 1        // strips in flight beyond the one being multiplied
+#ifndef FUSED_FPB
+#define FUSED_FPB 1          // fields per barrier (two measured slower)
 #endif
 #ifndef FUSED_STRIP_MAJOR
 #define FUSED_STRIP_MAJOR 1
@@ -77,7 +74,7 @@ __device__ inline int64_t mode_index(const FuArgs &a, int P0, int64_t t) {
   return (int64_t(k0) * a.n1 + k1) * a.n2 + k2;
 }
 
-template <int Q, int HB, int DEPTH>
+template <int Q, int HB, int FPB>
 __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   constexpr int RT = Q / 16;            // row tiles per half
   constexpr int NTH = HB * RT * 64;     // threads
@@ -86,7 +83,8 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   constexpr int ITEMS = KH * 8 / NTH;   // (row, column pair) loader items per thread
   static_assert(ITEMS * NTH == KH * 8, "loader items must tile the strip");
   constexpr bool LATE_TABLES = HB == 1;   // one half per block: four loader items
-  __shared__ __attribute__((aligned(16))) double F[2][HB][2][Q][16];
+  // [stage][field of the group][half][parity][jj][column]
+  __shared__ __attribute__((aligned(16))) double F[2][FPB][HB][2][Q][16];
 
   // strip-major block order: the blocks an XCD runs share a few strips (and
   // so the few update-table columns its L2 has to hold), each reading other
@@ -144,9 +142,7 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     W[m] = (Uin && k >= 0) ? Uin[k] : 0.0;
   }
 
-  // strip loader: item = (folded row p, column pair), raw x_p and x_{n-1-p};
-  // DEPTH register sets, so the strip of field e + DEPTH is in flight while
-  // field e is multiplied
+  // strip loader: item = (folded row p, column pair), raw x_p and x_{n-1-p}
   const int64_t fstride = int64_t(2 * M) * a.I;
   const double *Xs = a.X + int64_t(nl) * nf * fstride + int64_t(strip) * 16;
   // one half per block (four loader items): the strip moves in two parts, the
@@ -154,10 +150,11 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   // items are ever live
   constexpr int PARTS = HB == 1 ? 2 : 1;
   constexpr int PI = ITEMS / PARTS;   // items per part
+  static_assert(PARTS == 1 || FPB == 1, "split loader only with one field per barrier");
   struct Raw {
     double2 xa[PI], xb[PI];
   };
-  Raw S[DEPTH];
+  Raw S[FPB];
   auto load = [&](Raw &R, int e, int part) {
     const double *Xf = Xs + e * fstride;
 #pragma unroll
@@ -167,115 +164,104 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
       R.xb[q] = *reinterpret_cast<const double2 *>(Xf + int64_t(a.n0 - 1 - p) * a.I + c);
     }
   };
-  auto stash = [&](const Raw &R, int buf, int part) {
+  auto stash = [&](const Raw &R, int stage, int slot, int part) {
 #pragma unroll
     for (int q = 0; q < PI; ++q) {
-      const int it = q;
       const int idx = t + (part * PI + q) * NTH, p = idx >> 3, c = (idx & 7) * 2;
       const int g = p & 1, jj = p >> 1;
       const bool mid = p == KH - 1;   // p = H: the middle node
       double2 u, v;
-      u.x = mid ? R.xa[it].x : R.xa[it].x + R.xb[it].x;
-      u.y = mid ? R.xa[it].y : R.xa[it].y + R.xb[it].y;
-      v.x = mid ? 0.0 : R.xa[it].x - R.xb[it].x;
-      v.y = mid ? 0.0 : R.xa[it].y - R.xb[it].y;
+      u.x = mid ? R.xa[q].x : R.xa[q].x + R.xb[q].x;
+      u.y = mid ? R.xa[q].y : R.xa[q].y + R.xb[q].y;
+      v.x = mid ? 0.0 : R.xa[q].x - R.xb[q].x;
+      v.y = mid ? 0.0 : R.xa[q].y - R.xb[q].y;
       if (HB == 2) {
-        *reinterpret_cast<double2 *>(&F[buf][0][g][jj][c]) = u;
-        *reinterpret_cast<double2 *>(&F[buf][HB - 1][g][jj][c]) = v;
+        *reinterpret_cast<double2 *>(&F[stage][slot][0][g][jj][c]) = u;
+        *reinterpret_cast<double2 *>(&F[stage][slot][HB - 1][g][jj][c]) = v;
       } else {
-        *reinterpret_cast<double2 *>(&F[buf][0][g][jj][c]) = hb == 0 ? u : v;
+        *reinterpret_cast<double2 *>(&F[stage][slot][0][g][jj][c]) = hb == 0 ? u : v;
       }
     }
   };
+  auto load2 = [&](const double *src, double (&dst)[8]) {
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) {
+      const double2 v = *reinterpret_cast<const double2 *>(src + pp * 128);
+      dst[2 * pp] = v.x;
+      dst[2 * pp + 1] = v.y;
+    }
+  };
 
-  // one field: its products from LDS buffer e & 1, the next field's strip
-  // stashed into the other buffer (its last readers passed the barrier that
-  // ended the previous field), the update of the lane's states
-  auto field = [&](int e, Raw &issue, const Raw &next) {
-    const int buf = e & 1;
-    if (e + DEPTH < nf) load(issue, e + DEPTH, 0);
-    const int i = e % a.s;
-    double bw[8], ew[8];
-    // the tables of this field (16-byte loads, contiguous across the wave):
-    // fetched ahead of the products where the registers allow it, after them
-    // for the larger Q
+  // Fields go in groups of FPB: the group's products from LDS stage g & 1,
+  // the next group's strips stashed into the other stage (its last readers
+  // passed the barrier that ended the previous group), then the updates of
+  // the lane's states in field order, one barrier per group.
+  for (int f = 0; f < FPB && f < nf; ++f)
+    for (int part = 0; part < PARTS; ++part) {
+      load(S[f], f, part);
+      stash(S[f], 0, f, part);
+    }
+  __syncthreads();
+  for (int e0 = 0; e0 < nf; e0 += FPB) {
+    const int stage = (e0 / FPB) & 1;
+    const int nxt = e0 + FPB;
+#pragma unroll
+    for (int f = 0; f < FPB; ++f)
+      if (nxt + f < nf) load(S[f], nxt + f, 0);
+    // tables of the group (16-byte loads, contiguous across the wave): the
+    // decay once per group (it does not depend on the stage), a weight set
+    // per field; ahead of the products where the registers allow it
+    int ist[FPB];
+    bool need_e = false;
+#pragma unroll
+    for (int f = 0; f < FPB; ++f) {
+      ist[f] = (e0 + f) % a.s;
+      need_e = need_e || (ist[f] == 0 && e0 + f < nf);
+    }
+    double bw[FPB][8], ew[8];
     auto tables = [&]() {
 #pragma unroll
-      for (int pp = 0; pp < 4; ++pp) {
-        const double2 v = *reinterpret_cast<const double2 *>(Tl + ((1 + i) * 4 + pp) * 128);
-        bw[2 * pp] = v.x;
-        bw[2 * pp + 1] = v.y;
-      }
-      if (i == 0) {
-#pragma unroll
-        for (int pp = 0; pp < 4; ++pp) {
-          const double2 v = *reinterpret_cast<const double2 *>(Tl + pp * 128);
-          ew[2 * pp] = v.x;
-          ew[2 * pp + 1] = v.y;
-        }
-      }
+      for (int f = 0; f < FPB; ++f) load2(Tl + (1 + ist[f]) * 512, bw[f]);
+      if (need_e) load2(Tl, ew);
     };
     if (!LATE_TABLES) tables();
-    d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
-#if FUSED_CHAINS == 2
-    d4 c0b = {0.0, 0.0, 0.0, 0.0}, c1b = {0.0, 0.0, 0.0, 0.0};
+    d4 c0[FPB], c1[FPB];
 #pragma unroll
-    for (int ks = 0; ks < KS; ks += 2) {
-      const double b0 = F[buf][hl][0][4 * ks + lk][lr];
-      const double b1 = F[buf][hl][1][4 * ks + lk][lr];
-      const double b0b = F[buf][hl][0][4 * ks + 4 + lk][lr];
-      const double b1b = F[buf][hl][1][4 * ks + 4 + lk][lr];
-      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks], b0, c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks], b1, c1, 0, 0, 0);
-      c0b = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks + 1], b0b, c0b, 0, 0, 0);
-      c1b = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks + 1], b1b, c1b, 0, 0, 0);
-    }
-    c0 += c0b;
-    c1 += c1b;
-#else
+    for (int f = 0; f < FPB; ++f) c0[f] = c1[f] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      if (PARTS == 2 && ks == KS / 2 && e + 1 < nf) {
-        stash(next, buf ^ 1, 0);
-        load(issue, e + DEPTH, 1);
+      if (PARTS == 2 && ks == KS / 2 && nxt < nf) {
+        stash(S[0], stage ^ 1, 0, 0);
+        load(S[0], nxt, 1);
       }
-      const double b0 = F[buf][hl][0][4 * ks + lk][lr];
-      const double b1 = F[buf][hl][1][4 * ks + lk][lr];
-      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks], b0, c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks], b1, c1, 0, 0, 0);
+#pragma unroll
+      for (int f = 0; f < FPB; ++f) {
+        const double b0 = F[stage][f][hl][0][4 * ks + lk][lr];
+        const double b1 = F[stage][f][hl][1][4 * ks + lk][lr];
+        c0[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(s0[ks], b0, c0[f], 0, 0, 0);
+        c1[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(s1[ks], b1, c1[f], 0, 0, 0);
+      }
     }
-#endif
-    if (e + 1 < nf) stash(next, buf ^ 1, PARTS - 1);
+#pragma unroll
+    for (int f = 0; f < FPB; ++f)
+      if (nxt + f < nf) stash(S[f], stage ^ 1, f, PARTS - 1);
     if (LATE_TABLES) tables();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double y1 = c0[r] + c1[r], y2 = c0[r] - c1[r];
-      double w1 = W[2 * r], w2 = W[2 * r + 1];
-      if (i == 0) {
-        w1 = ew[2 * r] * w1;
-        w2 = ew[2 * r + 1] * w2;
+    for (int f = 0; f < FPB; ++f) {
+      if (e0 + f >= nf) break;   // a short last group (its LDS slot holds no field)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double y1 = c0[f][r] + c1[f][r], y2 = c0[f][r] - c1[f][r];
+        double w1 = W[2 * r], w2 = W[2 * r + 1];
+        if (ist[f] == 0) {
+          w1 = ew[2 * r] * w1;
+          w2 = ew[2 * r + 1] * w2;
+        }
+        W[2 * r] = w1 + bw[f][2 * r] * y1;
+        W[2 * r + 1] = w2 + bw[f][2 * r + 1] * y2;
       }
-      W[2 * r] = w1 + bw[2 * r] * y1;
-      W[2 * r + 1] = w2 + bw[2 * r + 1] * y2;
     }
     __syncthreads();
-  };
-
-  for (int part = 0; part < PARTS; ++part) {
-    load(S[0], 0, part);
-    stash(S[0], 0, part);
-  }
-  if (DEPTH == 2 && nf > 1) load(S[DEPTH - 1], 1, 0);
-  __syncthreads();
-  if (DEPTH == 1) {
-    for (int e = 0; e < nf; ++e) field(e, S[0], S[0]);
-  } else {
-    // field e issues field e + 2 into the set that held field e and stashes
-    // field e + 1 from the other set
-    for (int e = 0; e < nf; e += 2) {
-      field(e, S[0], S[DEPTH - 1]);
-      if (e + 1 < nf) field(e + 1, S[DEPTH - 1], S[0]);
-    }
   }
 
   double *Uout = a.Uout + int64_t(nl) * a.dof;
@@ -386,9 +372,9 @@ pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B
 template <int Q>
 static void launch_q(const FuArgs &a, int64_t nslices, hipStream_t st) {
   constexpr int HB = Q <= FUSED_HB2_MAX_Q ? 2 : 1;
-  constexpr int DEPTH = HB == 2 ? FUSED_DEPTH : 1;   // two raw sets fit at Q <= 64
+  constexpr int FPB = HB == 2 ? FUSED_FPB : 1;   // two strips fit the registers at Q <= 64
   const int64_t blocks = nslices * a.strips * (2 / HB);
-  k_final_update<Q, HB, DEPTH><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
+  k_final_update<Q, HB, FPB><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
 }
 
 pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tp,
