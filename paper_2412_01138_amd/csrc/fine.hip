@@ -287,6 +287,12 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
   if (fit >= total) {
     Nb = N;
     Jc = J;
+  } else if (fused && fit >= int64_t(J) * s) {
+    // the fused update walks a slice's fields in one block: whole slices
+    // (all J steps) per batch, so each block amortises its operator load
+    // over the slice's J s fields and the states never leave its registers
+    Nb = int(fit / (int64_t(J) * s));
+    Jc = J;
   } else if (fit >= int64_t(N) * s) {
     Nb = N;
     Jc = int(fit / (int64_t(N) * s));
