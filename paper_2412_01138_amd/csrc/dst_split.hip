@@ -376,12 +376,12 @@ bool gen_supported_split(pe_grid g, int n_terms) {
 }
 
 pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,
-                           float **result, hipStream_t st) {
+                           float **result, hipStream_t st, int stop_axis) {
   if (!g->ax[0].d_Shi) return set_error(PE_E_UNSUPPORTED, "grid has no split-bf16 tables");
   float *in = buf0, *out = buf1;
   const int d = g->dim;
   // axis contracted by pass q: d-1, d-2, ..., 0 (rotating layout)
-  for (int q = 0; q < d; ++q) {
+  for (int q = 0; q < d - stop_axis; ++q) {
     const int ax_i = d - 1 - q;
     const Axis &ax = g->ax[ax_i];
     const int64_t R = g->dofp / ax.np;

@@ -218,7 +218,7 @@ static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *wo
       gf.M = gen->M;
     }
     PE_TRY(dst_fields_split(g, count, gen ? &gf : nullptr, static_cast<float *>(work0),
-                            static_cast<float *>(work1), &r, st));
+                            static_cast<float *>(work1), &r, st, stop_axis));
     *result = r;
   }
   return PE_OK;
@@ -331,9 +331,7 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
       if (uin) uin += size_t(n0) * dof * sbytes;
       char *uout = static_cast<char *>(d_Uout) + size_t(n0) * dof * sbytes;
       if (fused) {
-        PE_TRY(final_pass_update(g, b, static_cast<const double *>(res), Tp,
-                                 reinterpret_cast<const double *>(uin),
-                                 reinterpret_cast<double *>(uout), st));
+        PE_TRY(final_pass_update(g, b, res, Tp, uin, uout, st));
         continue;
       }
       const int chunk = update_chunk(nb, dof);

@@ -38,6 +38,9 @@ namespace pe {
 #ifndef FUSED_FPB
 #define FUSED_FPB 1          // fields per barrier (two measured slower)
 #endif
+#ifndef SPLIT_DEPTH
+#define SPLIT_DEPTH 3        // strips in flight per block, split-bf16 fused update
+#endif
 #ifndef FUSED_STRIP_MAJOR
 #define FUSED_STRIP_MAJOR 1
 #endif
@@ -63,6 +66,13 @@ struct FuArgs {
   int n0, Kh0;         // axis 0
   int n1, Kh1, n2, Kh2, np2;   // inner axes (2D: n2 = np2 = Kh2 = 1)
   int jc, s, strips, nslices;
+  // split-bf16 grids: fp32 partial transforms and states, bf16 hi/lo halves
+  // of axis 0's folded matrix
+  const float *Xs;
+  const float *Uins;
+  float *Uouts;
+  const uint16_t *Shi, *Slo;   // [2][Kh][Kh]
+  int H0;
 };
 
 // compact index of the mode at folded position (P0, t), -1 at pads
@@ -315,6 +325,232 @@ __global__ void k_update_tables(FuArgs a, int RT, const double *__restrict__ sig
   }
 }
 
+// ------------------------------------------------------ split-bf16 grids
+// In the split path every pass contracts the contiguous axis and writes it
+// outermost, so the last pass contracts axis 0 and its input is
+// X[f][r][p] (r the folded positions of the other axes, p the nodes of axis
+// 0).  Fused with the update: a block owns one slice and 16 rows r and walks
+// the slice's stage fields; each field's 16 rows are read once (float4 runs,
+// the mirrored half as one ascending run), folded for both halves, split into
+// bf16 hi + lo in LDS, and multiplied on v_mfma_f32_16x16x32_bf16 by the
+// bf16 halves of Sh held in registers: three products per k-step (hi hi, hi
+// lo, lo hi) with fp32 accumulation, in the order of the separate split pass.
+// Waves: half h = wave / 4 and TM = Kh/64 mode tiles each; lane l holds
+// C[4 (l/16) + r][l%16], i.e. 4 TM modes of row l%16, whose states stay in
+// FP64 registers for the whole slice (as the separate update computes them).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4_t __attribute__((ext_vector_type(4)));
+
+template <int KH, int DEPTH>
+__global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
+  constexpr int NTH = 512;
+  constexpr int TM = KH / 64;     // mode tiles per wave
+  constexpr int KT = KH / 32;     // k-steps
+  constexpr int LDB = KH + 8;     // bf16 per LDS row (16-byte pad)
+  constexpr int CPR = KH / 4;     // 4-wide p chunks per row
+  constexpr int ITEMS = 16 * CPR; // loader items (one per thread at most)
+  static_assert(TM >= 1 && ITEMS <= NTH, "Kh of 64 or 128");
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][2][2][16][LDB];   // [buf][h][hi/lo][row][p]
+
+  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int nl = int(bid % a.nslices);
+  const int rt = int(bid / a.nslices);     // 16-row tile (strip-major: shared tables per XCD)
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int h = wave >> 2, wt = wave & 3;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // bf16 hi / lo of the wave's rows of Sh[h] as MFMA A fragments
+  bf16x8_t ah[TM][KT], al[TM][KT];
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int64_t o = (int64_t(h) * KH + 16 * (wt * TM + tm) + lr) * KH + 32 * kt + 8 * lk;
+      ah[tm][kt] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t *>(a.Shi + o));
+      al[tm][kt] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t *>(a.Slo + o));
+    }
+
+  // the lane's modes: m = 4 tm + q -> folded position (h Kh + i, row)
+  const int64_t row = int64_t(rt) * 16 + lr;
+  const int nf = a.jc * a.s;
+  const float *Uin = a.Uins ? a.Uins + int64_t(nl) * a.dof : nullptr;
+  double W[4 * TM];
+#pragma unroll
+  for (int m = 0; m < 4 * TM; ++m) {
+    const int i = 16 * (wt * TM + m / 4) + 4 * lk + (m % 4);
+    const int64_t k = mode_index(a, h * KH + i, row);
+    W[m] = (Uin && k >= 0) ? double(Uin[k]) : 0.0;
+  }
+  const double *Tl = a.Tp + (int64_t(rt) * 8 + wave) * (1 + a.s) * (2 * TM * 128) + 2 * lane;
+
+  // loader item (one per thread): row lrow of the tile, p = 4 c .. 4 c + 3.
+  // The kernel is bound by HBM: DEPTH register sets keep the strips of the
+  // next DEPTH fields in flight (field e + 1 + DEPTH is loaded right after
+  // field e + 1 is stashed), so each load has DEPTH fields of time to land.
+  const int lrow = t / CPR, lc = t % CPR, p0 = 4 * lc;
+  const bool active = t < ITEMS;
+  const int64_t fstride = int64_t(a.I) * (2 * KH);
+  const float *Xr = a.Xs + int64_t(nl) * nf * fstride + (int64_t(rt) * 16 + (active ? lrow : 0)) * (2 * KH);
+  struct Raw {
+    f4_t xa, xb;
+  };
+  Raw S[DEPTH];
+  auto load = [&](Raw &R, int e) {
+    if (!active || e >= nf) return;
+    const float *x = Xr + e * fstride;
+    R.xa = *reinterpret_cast<const f4_t *>(x + p0);
+    const int mb = a.n0 - 4 - p0;   // x[n-1-p0-e], e = 0..3: one ascending run
+    if (mb >= 0) {
+      const f4u_t v = *reinterpret_cast<const f4u_t *>(x + mb);
+      R.xb = f4_t{v.w, v.z, v.y, v.x};
+    } else {
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        const int i = a.n0 - 1 - p0 - e2;
+        R.xb[e2] = x[i > 0 ? i : 0];
+      }
+    }
+  };
+  auto stash = [&](const Raw &R, int buf) {
+    if (!active) return;
+    f4_t u, v;
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+      const int p = p0 + e2;
+      const bool has_b = p < a.H0;
+      const bool has_a0 = has_b || (p == a.H0 && (a.n0 & 1));
+      u[e2] = (has_a0 ? R.xa[e2] : 0.0f) + (has_b ? R.xb[e2] : 0.0f);
+      v[e2] = (has_b ? R.xa[e2] : 0.0f) + (has_b ? -R.xb[e2] : 0.0f);
+    }
+    const bf16x4_t uh = __builtin_convertvector(u, bf16x4_t);
+    const bf16x4_t ul = __builtin_convertvector(u - __builtin_convertvector(uh, f4_t), bf16x4_t);
+    const bf16x4_t vh = __builtin_convertvector(v, bf16x4_t);
+    const bf16x4_t vl = __builtin_convertvector(v - __builtin_convertvector(vh, f4_t), bf16x4_t);
+    *reinterpret_cast<u16x4_t *>(&Bs[buf][0][0][lrow][p0]) = __builtin_bit_cast(u16x4_t, uh);
+    *reinterpret_cast<u16x4_t *>(&Bs[buf][0][1][lrow][p0]) = __builtin_bit_cast(u16x4_t, ul);
+    *reinterpret_cast<u16x4_t *>(&Bs[buf][1][0][lrow][p0]) = __builtin_bit_cast(u16x4_t, vh);
+    *reinterpret_cast<u16x4_t *>(&Bs[buf][1][1][lrow][p0]) = __builtin_bit_cast(u16x4_t, vl);
+  };
+
+  // one field: products from LDS buffer e & 1, the next field stashed from
+  // its register set (then refilled DEPTH fields ahead), the update
+  auto field = [&](int e, Raw &nextset) {
+    const int buf = e & 1;
+    const int i_st = e % a.s;
+    double bw[4 * TM], ew[4 * TM];
+#pragma unroll
+    for (int pp = 0; pp < 2 * TM; ++pp) {
+      const double2 w2 = *reinterpret_cast<const double2 *>(Tl + ((1 + i_st) * 2 * TM + pp) * 128);
+      bw[2 * pp] = w2.x;
+      bw[2 * pp + 1] = w2.y;
+    }
+    if (i_st == 0) {
+#pragma unroll
+      for (int pp = 0; pp < 2 * TM; ++pp) {
+        const double2 w2 = *reinterpret_cast<const double2 *>(Tl + pp * 128);
+        ew[2 * pp] = w2.x;
+        ew[2 * pp + 1] = w2.y;
+      }
+    }
+    f4_t acc[TM];
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) acc[tm] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const bf16x8_t bh = __builtin_bit_cast(
+          bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][0][lr][32 * kt + 8 * lk]));
+      const bf16x8_t bl = __builtin_bit_cast(
+          bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][1][lr][32 * kt + 8 * lk]));
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bh, acc[tm], 0, 0, 0);
+        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bl, acc[tm], 0, 0, 0);
+        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm][kt], bh, acc[tm], 0, 0, 0);
+      }
+    }
+    if (e + 1 < nf) {
+      stash(nextset, buf ^ 1);
+      load(nextset, e + 1 + DEPTH);
+    }
+#pragma unroll
+    for (int m = 0; m < 4 * TM; ++m) {
+      double w = W[m];
+      if (i_st == 0) w = ew[m] * w;
+      W[m] = w + bw[m] * double(acc[m / 4][m % 4]);
+    }
+    __syncthreads();
+  };
+
+  // set d holds field d (d < DEPTH); field 0 goes to LDS and its set is
+  // refilled with field DEPTH
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) load(S[d], d);
+  stash(S[0], 0);
+  load(S[0], DEPTH);
+  __syncthreads();
+  for (int e0 = 0; e0 < nf; e0 += DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      if (e0 + d >= nf) break;
+      field(e0 + d, S[(d + 1) % DEPTH]);
+    }
+  }
+
+  float *Uout = a.Uouts + int64_t(nl) * a.dof;
+#pragma unroll
+  for (int m = 0; m < 4 * TM; ++m) {
+    const int i = 16 * (wt * TM + m / 4) + 4 * lk + (m % 4);
+    const int64_t k = mode_index(a, h * KH + i, row);
+    if (k >= 0) Uout[k] = float(W[m]);
+  }
+}
+
+// Update tables in the split kernel's lane order: entry (rt, wave, t, pair,
+// lane, c) is table t of the lane's mode 2 pair + c (rows of tile rt).
+__global__ void k_split_tables(FuArgs a, int TM, const double *__restrict__ sig0,
+                               const double *__restrict__ sig1, const double *__restrict__ sig2,
+                               const double *__restrict__ E, const double *__restrict__ B,
+                               double *Tp, int d) {
+  const int nt = 1 + a.s, NP = 2 * TM;
+  const int64_t total = (a.I / 16) * 8 * nt * NP * 128;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(e & 1), lane = int((e >> 1) & 63);
+    int64_t rest = e >> 7;
+    const int pp = int(rest % NP);
+    rest /= NP;
+    const int tt = int(rest % nt);
+    rest /= nt;
+    const int wave = int(rest % 8);
+    const int64_t rt = rest / 8;
+    const int h = wave >> 2, wt = wave & 3, lr = lane & 15, lk = lane >> 4;
+    const int m = 2 * pp + c;
+    const int i = 16 * (wt * TM + m / 4) + 4 * lk + (m % 4);
+    const int P0 = h * a.Kh0 + i;
+    const int64_t row = rt * 16 + lr;
+    const int64_t k = mode_index(a, P0, row);
+    double v = 0.0;
+    if (k >= 0) {
+      if (tt == 0) {
+        v = E[k];
+      } else {
+        const int k0 = unfold_pos(P0, a.Kh0);
+        const int p1 = int(row / a.np2), p2 = int(row - int64_t(p1) * a.np2);
+        const int k1 = unfold_pos(p1, a.Kh1), k2 = unfold_pos(p2, a.Kh2);
+        double sig = sig0[k0];
+        if (d > 1) sig *= sig1[k1];
+        if (d > 2) sig *= sig2[k2];
+        v = B[int64_t(tt - 1) * a.dof + k] * sig;
+      }
+    }
+    Tp[e] = v;
+  }
+}
+
 static FuArgs base_args(pe_grid g, int s) {
   FuArgs a{};
   const Axis &x0 = g->ax[0];
@@ -342,8 +578,12 @@ static FuArgs base_args(pe_grid g, int s) {
 constexpr int FUSED_MAX_Q = 128;
 
 bool fused_update_supported(pe_grid g) {
-  if (g->precision != PE_FP64 || g->dim < 2) return false;
+  if (g->dim < 2) return false;
   const Axis &x0 = g->ax[0];
+  if (g->precision == PE_SPLIT_BF16)
+    return (x0.Kh == 64 || x0.Kh == 128) && x0.d_Shi && (g->dofp / x0.np) % 16 == 0 &&
+           g->dofp < (int64_t(1) << 31);
+  if (g->precision != PE_FP64) return false;
   const int Q = x0.Kh / 2;
   return x0.l2 && x0.n == 2 * x0.Kh - 1 && Q % 16 == 0 && Q >= 16 && Q <= FUSED_MAX_Q &&
          (g->dofp / x0.np) % 16 == 0 && g->dofp < (int64_t(1) << 31);
@@ -359,6 +599,16 @@ size_t fused_update_table_bytes(pe_grid g) {
 pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Tp,
                               hipStream_t st) {
   FuArgs a = base_args(g, s);
+  if (g->precision == PE_SPLIT_BF16) {
+    const int TM = g->ax[0].Kh / 64;
+    const int64_t n = (a.I / 16) * 8 * (1 + s) * 2 * TM * 128;
+    const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
+    k_split_tables<<<blocks, 256, 0, st>>>(a, TM, g->ax[0].d_sig, g->ax[1].d_sig,
+                                            g->dim > 2 ? g->ax[2].d_sig : nullptr, E, B, Tp,
+                                            g->dim);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+  }
   const int RT = g->ax[0].Kh / 32;
   const int64_t n = int64_t(a.strips) * 2 * RT * (1 + s) * 512;
   const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
@@ -377,18 +627,48 @@ static void launch_q(const FuArgs &a, int64_t nslices, hipStream_t st) {
   k_final_update<Q, HB, FPB><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
 }
 
-pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tp,
-                            const double *Uin, double *Uout, hipStream_t st) {
+static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, hipStream_t st) {
+  const Axis &x0 = g->ax[0];
+  a.Shi = x0.d_Shi;
+  a.Slo = x0.d_Slo;
+  a.H0 = x0.H;
+  const int64_t blocks = int64_t(b.nslices) * (a.I / 16);
+  if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: fused grid too large");
+  // axis-0 products (three bf16 products of the folded pass) plus the update
+  const double fields = double(b.count());
+  const double lines = double(g->dof / x0.n);
+  const double flops =
+      fields * 3.0 * 2.0 * lines *
+      (double((x0.n + 1) / 2) * ((x0.n + 1) / 2) + double(x0.H) * x0.H);
+  const double bytes = fields * double(g->dof) * 4.0 + 2.0 * b.nslices * double(g->dof) * 4.0 +
+                       double(1 + b.s) * double(g->dof) * 8.0;
+  TimedScope ts(g, PE_K_MID_UPDATE, flops, bytes, st);
+  if (x0.Kh == 128)
+    k_split_final_update<128, SPLIT_DEPTH><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
+  else
+    k_split_final_update<64, SPLIT_DEPTH><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status final_pass_update(pe_grid g, const FieldBatch &b, const void *X, const double *Tp,
+                            const void *Uin, void *Uout, hipStream_t st) {
   if (!fused_update_supported(g)) return set_error(PE_E_ARG, "internal: no fused update here");
   FuArgs a = base_args(g, b.s);
   const Axis &x0 = g->ax[0];
-  a.X = X;
-  a.Sq = x0.d_Sq;
   a.Tp = Tp;
-  a.Uin = Uin;
-  a.Uout = Uout;
   a.jc = b.jc;
   a.nslices = b.nslices;
+  if (g->precision == PE_SPLIT_BF16) {
+    a.Xs = static_cast<const float *>(X);
+    a.Uins = static_cast<const float *>(Uin);
+    a.Uouts = static_cast<float *>(Uout);
+    return split_final_update(g, b, a, st);
+  }
+  a.X = static_cast<const double *>(X);
+  a.Sq = x0.d_Sq;
+  a.Uin = static_cast<const double *>(Uin);
+  a.Uout = static_cast<double *>(Uout);
   const int Q = x0.Kh / 2;
   const int64_t blocks = int64_t(b.nslices) * a.strips * (Q <= FUSED_HB2_MAX_Q ? 1 : 2);
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: fused grid too large");

@@ -171,19 +171,19 @@ struct FieldBatch {
 pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
                              double *coef, void **result, hipStream_t st, int stop_axis = 0);
 
-// Axis-0 pass fused with the diagonal update (FP64 grids, d >= 2, axis 0
-// with two fold levels and Q = Kh/2 a multiple of 16, up to a register
-// limit).  The update tables (E, and b_i sigma per stage, in the kernel's
+// Axis-0 pass fused with the diagonal update (d >= 2): FP64 grids whose
+// axis 0 has two fold levels and Q = Kh/2 a multiple of 16 up to 128;
+// split-bf16 grids whose axis 0 has Kh = 64 or 128.  The update tables (E, and b_i sigma per stage, in the kernel's
 // lane order) are built once per propagation into (1 + s) * DOF_padded
 // doubles of the fused_update_table_bytes of workspace.
 bool fused_update_supported(pe_grid g);
 size_t fused_update_table_bytes(pe_grid g);
 pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Tp,
                               hipStream_t st);
-// X: the batch after the passes over axes d-1..1; Uin (nullable) / Uout:
-// the batch's slice states.
-pe_status final_pass_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tp,
-                            const double *Uin, double *Uout, hipStream_t st);
+// X: the batch after the passes over axes d-1..1 (stage type of the grid);
+// Uin (nullable) / Uout: the batch's slice states (state type).
+pe_status final_pass_update(pe_grid g, const FieldBatch &b, const void *X, const double *Tp,
+                            const void *Uin, void *Uout, hipStream_t st);
 
 // Load-vector generation inside the first (last-axis) transform pass: the
 // nodal load of field f at node (j_0, .., j_{d-1}) is
@@ -215,8 +215,10 @@ struct GenSrcF {
   const double *Cf = nullptr;     // [2][M][Kh_last]
   int M = 0;
 };
+// (stop_axis = 1 leaves out the last pass, the one that contracts axis 0:
+// the batch is then [count][R][np_0] with the other axes transformed)
 pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,
-                           float **result, hipStream_t st);
+                           float **result, hipStream_t st, int stop_axis = 0);
 bool gen_supported_split(pe_grid g, int n_terms);
 // true when the fused generation path can take n_terms terms
 bool gen_supported(pe_grid g, int n_terms);

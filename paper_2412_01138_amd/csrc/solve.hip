@@ -60,11 +60,11 @@ extern "C" {
 
 size_t pe_solve_workspace_bytes(pe_grid g, const pe_solve_params *P) {
   if (!g || check_params(g, P) != PE_OK) return 0;
-  // batch space: all fields of one fine pass, capped at 8 GiB but never
+  // batch space: all fields of one fine pass, capped at 32 GiB but never
   // below one step of all slices (or one stage field set)
   int64_t all = int64_t(P->N) * P->J * P->q;
   size_t pf = pe_fine_workspace_bytes(g, 2) - pe_fine_workspace_bytes(g, 1);
-  int64_t cap = int64_t((size_t(8) << 30) / std::max<size_t>(pf, 1));
+  int64_t cap = int64_t((size_t(32) << 30) / std::max<size_t>(pf, 1));
   int64_t want = std::min(all, std::max<int64_t>(cap, int64_t(P->N) * std::max(P->q, P->p)));
   want = std::max<int64_t>(want, std::max(P->q, P->p));
   return fixed_bytes(g, P) + pe_fine_workspace_bytes(g, want);

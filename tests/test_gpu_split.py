@@ -52,6 +52,11 @@ def test_split_project(dim, n):
     (2, (64, 64), 2, 3, 4, 20),
     (3, (9, 33, 20), 2, 3, 4, 5),
     (3, (31, 63, 17), 2, 2, 3, 40),       # more terms than the fused path takes
+    # axis 0 with Kh = 64 / 128: the last pass is fused with the update
+    (2, (127, 40), 2, 3, 3, 4),
+    (3, (100, 20, 9), 2, 2, 3, 4),
+    (2, (200, 33), 1, 2, 4, 5),
+    (3, (255, 9, 12), 1, 2, 3, 4),
 ])
 def test_split_fine_propagate(dim, n, N, J, s, modes):
     pe = _peifem()
@@ -69,7 +74,28 @@ def test_split_fine_propagate(dim, n, N, J, s, modes):
     assert rel(out.cpu().numpy(), ref) <= SPLIT_TOL
 
 
-@pytest.mark.parametrize("dim,n", [(2, (45, 38)), (3, (15, 31, 9))])
+@pytest.mark.parametrize("dim,n,N,J,s", [(2, (127, 40), 3, 4, 3), (3, (200, 12, 9), 2, 2, 4)])
+def test_split_fused_update_matches_separate_kernels(dim, n, N, J, s):
+    """Split-bf16 grids with Kh = 64 / 128 on axis 0: the last pass fused
+    with the update against the separate pass + update (which run when the
+    workspace has no room for the update tables; the separate path then
+    rounds the fp32 state after every step, the fused one keeps it in FP64
+    across a slice's steps)."""
+    pe = _peifem()
+    prob = wl.tiny_problem(dim, n, seed=8, s=s, N=N, J=J, n_modes=4, T=0.9,
+                           precision="split_bf16")
+    rng = np.random.default_rng(9)
+    Uin = _dev32(rng.normal(size=(N,) + prob.n))
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    fused = g.fine_propagate(Uin, prob.t0, prob.dT, J, prob.c_fine, E, B).cpu().numpy()
+    per_field = g.fine_workspace_bytes(2) - g.fine_workspace_bytes(1)
+    work = g.workspace(3 * 256 + per_field * s)
+    sep = g.fine_propagate(Uin, prob.t0, prob.dT, J, prob.c_fine, E, B, work=work).cpu().numpy()
+    assert rel(fused, sep) <= 2e-6
+
+
+@pytest.mark.parametrize("dim,n", [(2, (45, 38)), (3, (15, 31, 9)), (2, (127, 20))])
 def test_split_parareal(dim, n):
     pe = _peifem()
     prob = wl.tiny_problem(dim, n, seed=51, N=5, J=4, s=3, u0_modes=2, precision="split_bf16")
