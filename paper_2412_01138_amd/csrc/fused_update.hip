@@ -39,7 +39,7 @@ namespace pe {
 #define FUSED_FPB 1          // fields per barrier (two measured slower)
 #endif
 #ifndef SPLIT_DEPTH
-#define SPLIT_DEPTH 3        // strips in flight per block, split-bf16 fused update
+#define SPLIT_DEPTH 2        // strips in flight per block, split-bf16 fused update (3+ costs Kh = 64 its second block per CU)
 #endif
 #ifndef FUSED_STRIP_MAJOR
 #define FUSED_STRIP_MAJOR 1
