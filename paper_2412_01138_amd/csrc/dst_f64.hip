@@ -730,15 +730,21 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
 // block keeps its half's reduced B operands (3 Q^2 / 2 doubles) in LDS, each
 // [K][N] matrix with N >= 32 stored with its two 16-lane row groups in
 // opposite bank halves (column n of row k at n ^ 16 (k & 1)).
-#ifndef L3_PAIR_STORE
-#define L3_PAIR_STORE 1
-#endif
 // 16-row tiles per block: up to LG_TILES_MAX (the block's LDS staging is
 // amortised over its tiles), fewer for small launches so that about 1024
 // blocks fill the chip
 constexpr int LG_TILES_MAX = 128;
 static int64_t lg_tiles(int64_t tiles) {
   return std::max<int64_t>(4, std::min<int64_t>(LG_TILES_MAX, tiles / 512));
+}
+
+// x of lane (i - 1) mod 16 within each 16-lane row (DPP row_ror:1, on the
+// two 32-bit halves)
+__device__ inline double row_rotate1(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), 0x121, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), 0x121, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
 }
 
 // One reduced product over a row tile: KCN chunks of 16 generated inputs
@@ -899,29 +905,27 @@ __global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles, int
       l3_product<Q, GK, Q / 16, Q / 32, Q2, Q / 16, NACC>(sb, 2 * Q2 * Q2, cfl, rf, acc, lr, lk);
       l3_product<Q, GK, 3 * Q / 32, Q / 32, Q2, 3 * Q / 32, NACC>(sb, 3 * Q2 * Q2, cfl, rf, acc,
                                                                    lr, lk);
-      // outputs: even rows from the sums, odd rows from the differences
+      // outputs: even rows from the sums, odd rows from the differences.
+      // Lane k (= 16 tt + l%16) writes the pair (2k, 2k+1) and the partner
+      // pair (M-2-2k, M-1-2k); the second partner is lane k-1's odd one
+      // (M-2-(2k-1)), brought over by a rotation within the 16-lane row,
+      // with lane 15 of the previous tile (or the pad, 0) for k's first lane.
+      double carry[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int tt = 0; tt < Q / 32; ++tt) {
-        const int ie = 2 * (16 * tt + lr), io = ie + 1;
+        const int ie = 2 * (16 * tt + lr);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t row = tile * 16 + lk + 4 * r;
           double *y = a.Y + row * a.np + Mh;
           const double Ae = acc[tt][r], Ao = acc[Q / 32 + tt][r];
           const double Be = acc[Q / 16 + tt][r], Bo = acc[3 * Q / 32 + tt][r];
-#if L3_PAIR_STORE
-          // rows 2k and 2k+1 are adjacent: one 16-byte store
           const d2 yy = {Ae + Be, Ao + Bo};
           __builtin_nontemporal_store(yy, reinterpret_cast<d2 *>(&y[ie]));
-#else
-          __builtin_nontemporal_store(Ae + Be, &y[ie]);
-          __builtin_nontemporal_store(Ao + Bo, &y[io]);
-#endif
-          __builtin_nontemporal_store(Ae - Be, &y[Mh - 2 - ie]);
-          if (io < Q - 1)
-            __builtin_nontemporal_store(Ao - Bo, &y[Mh - 2 - io]);
-          else
-            __builtin_nontemporal_store(0.0, &y[Mh - 1]);   // pad position of half 1
+          const double rot = row_rotate1(Ao - Bo);   // lane i gets lane (i - 1) mod 16
+          const d2 pp = {Ae - Be, lr == 0 ? carry[r] : rot};
+          carry[r] = rot;   // its lane 0 holds this tile's lane 15
+          __builtin_nontemporal_store(pp, reinterpret_cast<d2 *>(&y[Mh - 2 - ie]));
         }
       }
     }
