@@ -102,6 +102,23 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
 /* Release a grid and its device tables (NULL is ignored). */
 void pe_free_grid(pe_grid g);
 
+/* How the per-axis sine transforms of pe_fine_propagate, pe_coarse_sweep's
+ * forcing, pe_project and the learned calls are computed (Section 2.3: the
+ * sine matrix diagonalises M and A on every axis and is applied as a fast
+ * transform).
+ *   PE_TRANSFORM_DENSE (default): even/odd folds plus dense products on the
+ *     matrix cores.
+ *   PE_TRANSFORM_FFT: each line as the imaginary part of a complex FFT of
+ *     length 2(n_a + 1) of its odd extension (two lines per FFT), in LDS.
+ *     FP64 grids only, every axis with n_a + 1 in {64, 128, 256, 512}.
+ * Both give the same coefficients up to rounding.  The FFT's twiddle tables
+ * (2(n_a + 1) complex doubles per axis) are allocated here and owned by the
+ * grid.  Errors: PE_E_ARG for an unknown kind or a grid the FFT does not
+ * support (the grid keeps its transform), PE_E_HIP on allocation failure.
+ * Synchronises the device. */
+typedef enum { PE_TRANSFORM_DENSE = 0, PE_TRANSFORM_FFT = 1 } pe_transform;
+pe_status pe_set_transform(pe_grid g, int32_t kind);
+
 /* Set the forcing f (paper eq. (2.1)) as n_terms (0..PE_MAX_TERMS) separable
  * terms (host array).  Builds on the device the 1D load tables
  * C_{m,a}[j] = int X_{m,a}(x) phi_j(x) dx by the grid's Gauss rule (the load

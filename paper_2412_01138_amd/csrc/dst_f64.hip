@@ -1086,6 +1086,7 @@ static pe_status launch_mid2(Mid2Args a, hipStream_t st) {
 }
 
 bool gen_supported(pe_grid g, int n_terms) {
+  if (g->transform == PE_TRANSFORM_FFT) return fft_gen_supported(g, n_terms);
   const Axis &last = g->ax[g->dim - 1];
   return n_terms >= 1 && n_terms <= GEN_MAX_TERMS && int64_t(n_terms) * last.Kh <= GEN_MAX_CF;
 }

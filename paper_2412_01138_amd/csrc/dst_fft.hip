@@ -1,0 +1,551 @@
+// Per-axis DST-I by FFT (FP64), the alternative to the dense matrix-core
+// products of the fine propagator.
+//
+// Section 2.3 applies the diagonalising sine matrix with a fast transform.
+// With L = n + 1 (a power of two) and S[k][j] = sqrt(2/L) sin(pi j k / L), a
+// line x_1..x_n is extended to the odd sequence z of length 2L
+//     z_0 = z_L = 0,   z_j = x_j,   z_{2L-j} = -x_j   (1 <= j < L),
+// whose DFT is Z_k = -2i sum_j x_j sin(pi j k / L).  Two real lines x, x' go
+// into one complex sequence z + i z', so one complex DFT of length N = 2L
+// gives both transforms:
+//     (S x)_k = -Im Z_k / sqrt(2L),   (S x')_k = Re Z_k / sqrt(2L).
+// The DFT is a Stockham autosort FFT in LDS: radix-8 stages, then one radix-4
+// or radix-2 stage, 512 threads per block holding 4096 complex points (4096/N
+// line pairs), N/8 threads per FFT.  Results are written in the folded mode
+// order of the dense path, so both paths feed the same update.
+//
+// Kernels: k_fft_pass (one axis of a batch of fields; on the last axis it can
+// generate its input from the separable load tables) and k_fft_final (axis 0
+// fused with the diagonal update of eq. (2.6): a block owns one slice and a
+// strip of columns and walks the slice's stage fields with the states in
+// registers).
+#include <algorithm>
+#include <cmath>
+
+#include "pe_internal.h"
+
+namespace pe {
+
+namespace {
+
+using c2 = double2;
+
+constexpr int FFT_THREADS = 512;
+constexpr int FFT_POINTS = 4096;       // complex points per block
+constexpr int FFT_GEN_MAX_TERMS = 32;  // separable terms generated in registers
+
+template <int N>
+struct Shape {
+  static constexpr int L = N / 2;           // n + 1
+  static constexpr int P = FFT_POINTS / N;  // FFTs (line pairs) per block
+  static constexpr int LINES = 2 * P;
+  static constexpr int TF = N / 8;          // threads per FFT
+  // LDS stride of one FFT in complex entries: one pad entry per 8 (the
+  // stride-R writes of a stage spread over the banks), plus one so that the
+  // FFTs of a block start on different banks
+  static constexpr int FS = N + N / 8 + 1;
+  static_assert(P * TF == FFT_THREADS, "one radix-8 butterfly per thread and stage");
+};
+
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+
+__device__ __forceinline__ c2 cadd(c2 a, c2 b) { return c2{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c2 csub(c2 a, c2 b) { return c2{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c2 cmul(c2 a, c2 b) {
+  return c2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// -i z
+__device__ __forceinline__ c2 mul_mi(c2 a) { return c2{a.y, -a.x}; }
+
+// In-register DFTs, natural order in and out: v_r <- sum_q v_q e^{-2 pi i q r / R}.
+__device__ __forceinline__ void dft2(c2 *v) {
+  const c2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+__device__ __forceinline__ void dft4(c2 &x0, c2 &x1, c2 &x2, c2 &x3) {
+  const c2 s0 = cadd(x0, x2), d0 = csub(x0, x2), s1 = cadd(x1, x3), d1 = mul_mi(csub(x1, x3));
+  x0 = cadd(s0, s1);
+  x2 = csub(s0, s1);
+  x1 = cadd(d0, d1);
+  x3 = csub(d0, d1);
+}
+__device__ __forceinline__ void dft8(c2 *v) {
+  constexpr double R2 = 0.70710678118654752440;   // sqrt(1/2)
+  c2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  c2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  // o_r times w^r, w = e^{-2 pi i / 8} = sqrt(1/2) (1 - i)
+  o1 = c2{R2 * (o1.x + o1.y), R2 * (o1.y - o1.x)};
+  o2 = mul_mi(o2);
+  o3 = c2{R2 * (o3.y - o3.x), -R2 * (o3.x + o3.y)};
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+// One Stockham stage of radix R on the sub-transforms of size NS: butterfly
+// j takes the R inputs j + r N/R, twists input r by w_N^{r k N/(NS R)}
+// (k = j mod NS), transforms them and stores output r at
+// (j / NS) NS R + k + r NS.  A thread does 8/R butterflies; the block reads
+// everything before anyone writes (the stage is in place).
+template <int N, int R, int NS>
+__device__ __forceinline__ void fft_stage(c2 *Z, const c2 *__restrict__ tw, int u) {
+  constexpr int B = 8 / R;
+  c2 v[8];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = u + b * (N / 8);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b * R + r] = Z[pidx(j + r * (N / R))];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = u + b * (N / 8);
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[r * k * (N / (NS * R))]);
+    }
+    if constexpr (R == 8) dft8(&v[b * R]);
+    if constexpr (R == 4) dft4(v[b * R], v[b * R + 1], v[b * R + 2], v[b * R + 3]);
+    if constexpr (R == 2) dft2(&v[b * R]);
+    const int dst = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) Z[pidx(dst + r * NS)] = v[b * R + r];
+  }
+  __syncthreads();
+}
+
+template <int N, int NS>
+__device__ __forceinline__ void fft_stages(c2 *Z, const c2 *__restrict__ tw, int u) {
+  if constexpr (NS < N) {
+    constexpr int R = N / NS >= 8 ? 8 : N / NS;
+    fft_stage<N, R, NS>(Z, tw, u);
+    fft_stages<N, NS * R>(Z, tw, u);
+  }
+}
+
+// Writes node j (0-based, value x) of tile line l into the odd extension:
+// line l is the real (l < P) or imaginary part of FFT l mod P.  The thread of
+// the position j = L - 1 (beyond the last node) writes the two zeros.
+template <int N>
+__device__ __forceinline__ void put_node(double *Zd, int l, int j, double x) {
+  using Sh = Shape<N>;
+  const int p = l % Sh::P, part = l / Sh::P;
+  double *z = Zd + 2 * p * Sh::FS + part;
+  if (j < Sh::L - 1) {
+    z[2 * pidx(j + 1)] = x;
+    z[2 * pidx(N - 1 - j)] = -x;
+  } else {
+    z[2 * pidx(0)] = 0.0;
+    z[2 * pidx(Sh::L)] = 0.0;
+  }
+}
+
+// Raw sine sum of mode m (0-based) of tile line l, times sqrt(2L).
+template <int N>
+__device__ __forceinline__ double get_mode(const c2 *Zs, int l, int m) {
+  using Sh = Shape<N>;
+  const int p = l % Sh::P, part = l / Sh::P;
+  const c2 F = Zs[p * Sh::FS + pidx(m + 1)];
+  return part ? F.x : -F.y;
+}
+
+}  // namespace
+
+struct FftPassArgs {
+  const double *in;          // nodal lines (unused when generating)
+  double *out;               // DST coefficients, folded mode order
+  int64_t nlines;            // lines of the pass
+  int64_t inner;             // stride between the nodes of a line
+  const c2 *tw;              // [N] e^{-2 pi i k / N}
+  // load generation (last axis): node (f, r, j) has the load
+  // sum_m coef[f][m] pre_r[m] Cl[m][j], pre_r the product of the other axes'
+  // tables at the line's nodes
+  const double *coef;        // [fields][M]
+  const double *C0, *C1;     // [M][np_0], [M][np_1] (d >= 2, d == 3)
+  const double *Cl;          // [M][L] last-axis loads
+  int M, d, np0, np1;
+  int64_t rows;              // lines per field (product of the other axes' np)
+};
+
+// MT: the generated terms rounded up (8, 16 or 32; sizes the LDS of the
+// per-line factors and the registers of the last-axis tables)
+template <int N, bool GEN, bool CONTIG, int MT>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_pass(FftPassArgs a) {
+  using Sh = Shape<N>;
+  constexpr int L = Sh::L, LINES = Sh::LINES;
+  __shared__ c2 Zs[Sh::P * Sh::FS];
+  __shared__ double pre[GEN ? LINES * MT : 1];
+  double *Zd = reinterpret_cast<double *>(Zs);
+  const int t = threadIdx.x;
+  const int64_t l0 = int64_t(blockIdx.x) * LINES;
+  auto line_base = [&](int64_t ln) -> int64_t {
+    if (CONTIG) return ln * L;
+    const int64_t o = ln / a.inner;
+    return o * L * a.inner + (ln - o * a.inner);
+  };
+
+  if constexpr (GEN) {
+    for (int e = t; e < LINES * a.M; e += FFT_THREADS) {
+      const int l = e / a.M, m = e - l * a.M;
+      const int64_t ln = l0 + l;
+      double v = 0.0;
+      if (ln < a.nlines) {
+        const int64_t f = ln / a.rows;
+        const int64_t r = ln - f * a.rows;
+        v = a.coef[f * a.M + m];
+        if (a.d == 2) v *= a.C0[int64_t(m) * a.np0 + r];
+        if (a.d == 3) {
+          v *= a.C0[int64_t(m) * a.np0 + r / a.np1];
+          v *= a.C1[int64_t(m) * a.np1 + r % a.np1];
+        }
+      }
+      pre[l * MT + m] = v;
+    }
+    // thread = node position j (fixed, 512 is a multiple of L), 8 lines
+    const int j = t % L;
+    double cl[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+      cl[m] = (m < a.M && j < L - 1) ? a.Cl[int64_t(m) * L + j] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int l = t / L + k * (FFT_THREADS / L);
+      const double *pl = pre + l * MT;
+      double x = 0.0;
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        if (m < a.M) x += pl[m] * cl[m];
+      put_node<N>(Zd, l, j, x);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = t + k * FFT_THREADS;
+      // contiguous lines: consecutive threads walk a line; strided lines:
+      // consecutive threads take consecutive lines (adjacent columns)
+      const int l = CONTIG ? e / L : e % LINES;
+      const int j = CONTIG ? e % L : e / LINES;
+      const int64_t ln = l0 + l;
+      const double x = (ln < a.nlines && j < L - 1) ? a.in[line_base(ln) + int64_t(j) * a.inner] : 0.0;
+      put_node<N>(Zd, l, j, x);
+    }
+  }
+  __syncthreads();
+  fft_stages<N, 1>(Zs + (t / Sh::TF) * Sh::FS, a.tw, t % Sh::TF);
+
+  const double scale = 1.0 / sqrt(double(N));
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int e = t + k * FFT_THREADS;
+    const int l = CONTIG ? e / L : e % LINES;
+    const int q = CONTIG ? e % L : e / LINES;
+    const int64_t ln = l0 + l;
+    if (ln >= a.nlines) continue;
+    const int m = unfold_pos(q, L / 2);
+    const double y = m < L - 1 ? get_mode<N>(Zs, l, m) * scale : 0.0;
+    a.out[line_base(ln) + int64_t(q) * a.inner] = y;
+  }
+}
+
+// Axis-0 pass fused with the update.  Block = (slice nl, strip of LINES
+// columns); thread t owns column l = t mod LINES and the modes
+// m = t / LINES + k (512 / LINES), k < 8, of every field of the slice.
+struct FftFinalArgs {
+  const double *X;        // [fields][L][inner] after the other axes' passes
+  const double *Tf;       // update tables in the thread order (fft_tables)
+  const double *Uin;      // nullable
+  double *Uout;
+  const c2 *tw;
+  int64_t inner, dof;
+  int nslices, strips, jc, s;
+  int n1, Kh1, n2, Kh2, np2, d;
+};
+
+// state index of (mode m, padded column c) or -1 at pads (DOF < 2^31 here)
+__device__ __forceinline__ int fft_state_index(const FftFinalArgs &a, int L, int m, int64_t c) {
+  if (m >= L - 1) return -1;
+  int k1, k2 = 0;
+  if (a.d == 3) {
+    k1 = unfold_pos(int(c / a.np2), a.Kh1);
+    k2 = unfold_pos(int(c % a.np2), a.Kh2);
+    if (k2 >= a.n2) return -1;
+  } else {
+    k1 = unfold_pos(int(c), a.Kh1);
+  }
+  if (k1 >= a.n1) return -1;
+  return (m * a.n1 + k1) * (a.d == 3 ? a.n2 : 1) + k2;
+}
+
+template <int N>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_final(FftFinalArgs a) {
+  using Sh = Shape<N>;
+  constexpr int L = Sh::L, LINES = Sh::LINES;
+  __shared__ c2 Zs[Sh::P * Sh::FS];
+  double *Zd = reinterpret_cast<double *>(Zs);
+  const int t = threadIdx.x;
+  const int nl = int(blockIdx.x % a.nslices);
+  const int strip = int(blockIdx.x / a.nslices);
+  const int l = t % LINES;
+  const int64_t col = int64_t(strip) * LINES + l;
+  const int nf = a.jc * a.s;
+
+  int kidx[8];
+  double W[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int m = t / LINES + k * (FFT_THREADS / LINES);
+    kidx[k] = fft_state_index(a, L, m, col);
+    W[k] = (a.Uin && kidx[k] >= 0) ? a.Uin[int64_t(nl) * a.dof + kidx[k]] : 0.0;
+  }
+  const double *Xs = a.X + int64_t(nl) * nf * L * a.inner + col;
+  const double *Tl = a.Tf + int64_t(strip) * (1 + a.s) * 8 * FFT_THREADS + t;
+  double S[8];
+  auto load = [&](int e) {
+    const double *Xf = Xs + int64_t(e) * L * a.inner;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int j = t / LINES + k * (FFT_THREADS / LINES);
+      S[k] = j < L - 1 ? Xf[int64_t(j) * a.inner] : 0.0;
+    }
+  };
+  load(0);
+  for (int e = 0; e < nf; ++e) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) put_node<N>(Zd, l, t / LINES + k * (FFT_THREADS / LINES), S[k]);
+    __syncthreads();
+    if (e + 1 < nf) load(e + 1);   // in flight during the transform
+    fft_stages<N, 1>(Zs + (t / Sh::TF) * Sh::FS, a.tw, t % Sh::TF);
+    // eq. (2.6): W = E W at a step's first stage, then W += (b_i sigma) y;
+    // the tables carry sigma and the 1/sqrt(2L)
+    const int i = e % a.s;
+    const double *Ti = Tl + (1 + i) * 8 * FFT_THREADS;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int m = t / LINES + k * (FFT_THREADS / LINES);
+      const double y = get_mode<N>(Zs, l, m < L - 1 ? m : 0);
+      double w = W[k];
+      if (i == 0) w = Tl[k * FFT_THREADS] * w;
+      W[k] = w + Ti[k * FFT_THREADS] * y;
+    }
+    __syncthreads();
+  }
+  double *Uo = a.Uout + int64_t(nl) * a.dof;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (kidx[k] >= 0) Uo[kidx[k]] = W[k];
+}
+
+// Tables of k_fft_final: Tf[strip][tbl][k][t], tbl 0 = E, tbl 1 + i =
+// b_i sigma / sqrt(2L) (zero at pads).
+__global__ void k_fft_tables(FftFinalArgs a, int L, int LINES, const double *__restrict__ sig0,
+                             const double *__restrict__ sig1, const double *__restrict__ sig2,
+                             const double *__restrict__ E, const double *__restrict__ B,
+                             double *Tf) {
+  const int64_t total = int64_t(a.strips) * (1 + a.s) * 8 * FFT_THREADS;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int t = int(e % FFT_THREADS);
+    const int k = int((e / FFT_THREADS) % 8);
+    const int tbl = int((e / (8 * FFT_THREADS)) % (1 + a.s));
+    const int64_t strip = e / (int64_t(8) * FFT_THREADS * (1 + a.s));
+    const int l = t % LINES;
+    const int m = t / LINES + k * (FFT_THREADS / LINES);
+    const int64_t col = strip * LINES + l;
+    const int64_t ki = fft_state_index(a, L, m, col);
+    double v = 0.0;
+    if (ki >= 0) {
+      if (tbl == 0) {
+        v = E[ki];
+      } else {
+        const int64_t rest = ki % (a.dof / (L - 1));
+        double sig = sig0[m];
+        if (a.d == 3) {
+          sig *= sig1[rest / a.n2];
+          sig *= sig2[rest % a.n2];
+        } else {
+          sig *= sig1[rest];
+        }
+        v = B[int64_t(tbl - 1) * a.dof + ki] * sig * (1.0 / sqrt(2.0 * L));
+      }
+    }
+    Tf[e] = v;
+  }
+}
+
+// ------------------------------------------------------------------ host
+
+bool fft_axis_ok(int n) {
+  const int L = n + 1;
+  return L == 64 || L == 128 || L == 256 || L == 512;
+}
+
+bool fft_gen_supported(pe_grid g, int n_terms) {
+  return n_terms >= 1 && n_terms <= FFT_GEN_MAX_TERMS;
+}
+
+__global__ void k_fft_twiddles(int N, c2 *tw) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double s, c;
+  sincospi(2.0 * double(k) / double(N), &s, &c);
+  tw[k] = c2{c, -s};
+}
+
+pe_status fft_prepare(pe_grid g) {
+  for (int a = 0; a < g->dim; ++a) {
+    Axis &ax = g->ax[a];
+    if (ax.d_tw) continue;
+    const int N = 2 * (ax.n + 1);
+    PE_HIP(hipMalloc(&ax.d_tw, sizeof(c2) * size_t(N)));
+    k_fft_twiddles<<<(N + 255) / 256, 256>>>(N, reinterpret_cast<c2 *>(ax.d_tw));
+    PE_HIP(hipGetLastError());
+  }
+  PE_HIP(hipDeviceSynchronize());
+  return PE_OK;
+}
+
+template <int N>
+static void launch_pass(const FftPassArgs &a, bool gen, bool contig, hipStream_t st) {
+  const unsigned blocks = unsigned((a.nlines + Shape<N>::LINES - 1) / Shape<N>::LINES);
+  if (gen && a.M <= 8)
+    k_fft_pass<N, true, true, 8><<<blocks, FFT_THREADS, 0, st>>>(a);
+  else if (gen && a.M <= 16)
+    k_fft_pass<N, true, true, 16><<<blocks, FFT_THREADS, 0, st>>>(a);
+  else if (gen)
+    k_fft_pass<N, true, true, FFT_GEN_MAX_TERMS><<<blocks, FFT_THREADS, 0, st>>>(a);
+  else if (contig)
+    k_fft_pass<N, false, true, 1><<<blocks, FFT_THREADS, 0, st>>>(a);
+  else
+    k_fft_pass<N, false, false, 1><<<blocks, FFT_THREADS, 0, st>>>(a);
+}
+
+pe_status dst_fields_fft(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
+                         double **result, hipStream_t st, int stop_axis) {
+  double *in = buf0, *out = buf1;
+  const int d = g->dim;
+  for (int ax_i = d - 1; ax_i >= stop_axis; --ax_i) {
+    const Axis &ax = g->ax[ax_i];
+    const int N = 2 * (ax.n + 1);
+    FftPassArgs a{};
+    int64_t inner = 1;
+    for (int b = ax_i + 1; b < d; ++b) inner *= g->ax[b].np;
+    a.in = in;
+    a.out = out;
+    a.inner = inner;
+    a.nlines = count * (g->dofp / ax.np);
+    a.tw = reinterpret_cast<const c2 *>(ax.d_tw);
+    const bool gen_pass = gen && ax_i == d - 1;
+    if (gen_pass) {
+      a.coef = gen->coef;
+      a.C0 = gen->C0;
+      a.C1 = gen->C1;
+      a.Cl = gen->Cl;
+      a.M = gen->M;
+      a.d = d;
+      a.np0 = g->ax[0].np;
+      a.np1 = d == 3 ? g->ax[1].np : 1;
+      a.rows = g->dofp / ax.np;
+    }
+    if (a.nlines / Shape<128>::LINES >= (int64_t(1) << 31))
+      return set_error(PE_E_ARG, "internal: FFT pass grid too large");
+    // flops of a complex FFT of N points, 5 N log2 N, per line pair
+    const double lines = double(count) * double(g->dof / ax.n);
+    const double flops = lines * 2.5 * N * std::log2(double(N));
+    const double fb = double(count) * double(g->dof) * 8.0;
+    TimedScope ts(g, ax_i == d - 1 ? PE_K_DST_LAST : PE_K_DST_MID, flops,
+                  gen_pass ? fb : 2.0 * fb, st);
+    const bool contig = inner == 1;
+    switch (N) {
+      case 128: launch_pass<128>(a, gen_pass, contig, st); break;
+      case 256: launch_pass<256>(a, gen_pass, contig, st); break;
+      case 512: launch_pass<512>(a, gen_pass, contig, st); break;
+      case 1024: launch_pass<1024>(a, gen_pass, contig, st); break;
+      default: return set_error(PE_E_ARG, "internal: FFT length %d", N);
+    }
+    PE_HIP(hipGetLastError());
+    std::swap(in, out);
+  }
+  *result = in;
+  return PE_OK;
+}
+
+static FftFinalArgs final_args(pe_grid g, int s) {
+  FftFinalArgs a{};
+  const Axis &x0 = g->ax[0];
+  a.inner = g->dofp / x0.np;
+  a.dof = g->dof;
+  a.d = g->dim;
+  a.n1 = g->ax[1].n;
+  a.Kh1 = g->ax[1].Kh;
+  if (g->dim == 3) {
+    a.n2 = g->ax[2].n;
+    a.Kh2 = g->ax[2].Kh;
+    a.np2 = g->ax[2].np;
+  } else {
+    a.n2 = a.Kh2 = a.np2 = 1;
+  }
+  a.s = s;
+  const int N = 2 * (x0.n + 1);
+  a.strips = int(a.inner / (2 * (FFT_POINTS / N)));
+  a.tw = reinterpret_cast<const c2 *>(x0.d_tw);
+  return a;
+}
+
+bool fft_final_supported(pe_grid g) {
+  return g->dim >= 2 && g->dofp < (int64_t(1) << 31) && g->dof < (int64_t(1) << 31);
+}
+
+pe_status fft_tables(pe_grid g, int s, const double *E, const double *B, double *Tf,
+                     hipStream_t st) {
+  FftFinalArgs a = final_args(g, s);
+  const int L = g->ax[0].n + 1;
+  const int LINES = 2 * (FFT_POINTS / (2 * L));
+  const int64_t n = int64_t(a.strips) * (1 + s) * 8 * FFT_THREADS;
+  const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
+  k_fft_tables<<<blocks, 256, 0, st>>>(a, L, LINES, g->ax[0].d_sig, g->ax[1].d_sig,
+                                        g->dim > 2 ? g->ax[2].d_sig : nullptr, E, B, Tf);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status fft_final_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tf,
+                           const double *Uin, double *Uout, hipStream_t st) {
+  FftFinalArgs a = final_args(g, b.s);
+  a.X = X;
+  a.Tf = Tf;
+  a.Uin = Uin;
+  a.Uout = Uout;
+  a.jc = b.jc;
+  a.nslices = b.nslices;
+  const Axis &x0 = g->ax[0];
+  const int N = 2 * (x0.n + 1);
+  const int64_t blocks = int64_t(b.nslices) * a.strips;
+  if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: FFT grid too large");
+  const double fields = double(b.count());
+  const double flops = fields * double(g->dof / x0.n) * 2.5 * N * std::log2(double(N));
+  const double bytes = fields * double(g->dof) * 8.0 + 2.0 * b.nslices * double(g->dof) * 8.0 +
+                       double(1 + b.s) * double(g->dof) * 8.0;
+  TimedScope ts(g, PE_K_MID_UPDATE, flops, bytes, st);
+  switch (N) {
+    case 128: k_fft_final<128><<<dim3(unsigned(blocks)), FFT_THREADS, 0, st>>>(a); break;
+    case 256: k_fft_final<256><<<dim3(unsigned(blocks)), FFT_THREADS, 0, st>>>(a); break;
+    case 512: k_fft_final<512><<<dim3(unsigned(blocks)), FFT_THREADS, 0, st>>>(a); break;
+    case 1024: k_fft_final<1024><<<dim3(unsigned(blocks)), FFT_THREADS, 0, st>>>(a); break;
+    default: return set_error(PE_E_ARG, "internal: FFT length %d", N);
+  }
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+}  // namespace pe

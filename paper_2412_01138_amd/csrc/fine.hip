@@ -202,7 +202,12 @@ static pe_status launch_load(pe_grid g, double *const *C, int n_terms, const dou
 
 static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *work0, void *work1,
                            void **result, hipStream_t st, int stop_axis = 0) {
-  if (g->precision == PE_FP64) {
+  if (g->transform == PE_TRANSFORM_FFT) {
+    double *r = nullptr;
+    PE_TRY(dst_fields_fft(g, count, gen, static_cast<double *>(work0), static_cast<double *>(work1),
+                          &r, st, stop_axis));
+    *result = r;
+  } else if (g->precision == PE_FP64) {
     double *r = nullptr;
     PE_TRY(dst_fields_f64(g, count, gen, static_cast<double *>(work0), static_cast<double *>(work1),
                           &r, st, stop_axis));
@@ -239,6 +244,7 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
     gs.C1 = g->dim >= 3 ? g->d_C[1] : nullptr;
     gs.coef = coef;
     gs.Cf = g->d_Cf;
+    gs.Cl = g->d_C[g->dim - 1];
     gs.M = g->n_terms;
     return transform(g, count, &gs, work0, work1, result, st, stop_axis);
   }
@@ -433,6 +439,7 @@ pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W
     gs.C1 = g->dim >= 3 ? C[1] : nullptr;
     gs.coef = coef;
     gs.Cf = Cf;
+    gs.Cl = C[g->dim - 1];
     gs.M = n_terms;
     PE_TRY(transform(g, 1, &gs, w0, w1, &res, st));
   } else {

@@ -578,6 +578,7 @@ static FuArgs base_args(pe_grid g, int s) {
 constexpr int FUSED_MAX_Q = 128;
 
 bool fused_update_supported(pe_grid g) {
+  if (g->transform == PE_TRANSFORM_FFT) return fft_final_supported(g);
   if (g->dim < 2) return false;
   const Axis &x0 = g->ax[0];
   if (g->precision == PE_SPLIT_BF16)
@@ -598,6 +599,7 @@ size_t fused_update_table_bytes(pe_grid g) {
 
 pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Tp,
                               hipStream_t st) {
+  if (g->transform == PE_TRANSFORM_FFT) return fft_tables(g, s, E, B, Tp, st);
   FuArgs a = base_args(g, s);
   if (g->precision == PE_SPLIT_BF16) {
     const int TM = g->ax[0].Kh / 64;
@@ -654,6 +656,9 @@ static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, hi
 pe_status final_pass_update(pe_grid g, const FieldBatch &b, const void *X, const double *Tp,
                             const void *Uin, void *Uout, hipStream_t st) {
   if (!fused_update_supported(g)) return set_error(PE_E_ARG, "internal: no fused update here");
+  if (g->transform == PE_TRANSFORM_FFT)
+    return fft_final_update(g, b, static_cast<const double *>(X), Tp,
+                            static_cast<const double *>(Uin), static_cast<double *>(Uout), st);
   FuArgs a = base_args(g, b.s);
   const Axis &x0 = g->ax[0];
   a.Tp = Tp;

@@ -310,6 +310,7 @@ static void free_grid_tables(pe_grid g) {
     dev_free(g->ax[a].d_Sq);
     dev_free(g->ax[a].d_SqT);
     dev_free(g->ax[a].d_L3);
+    dev_free(g->ax[a].d_tw);
     dev_free(g->d_C[a]);
     dev_free(g->d_spec[a]);
   }
@@ -495,6 +496,24 @@ void pe_free_grid(pe_grid g) {
   drop_pending(g);
   free_grid_tables(g);
   delete g;
+}
+
+pe_status pe_set_transform(pe_grid g, int32_t kind) {
+  clear_error();
+  if (!g) return set_error(PE_E_ARG, "null grid");
+  if (kind == PE_TRANSFORM_DENSE) {
+    g->transform = kind;
+    return PE_OK;
+  }
+  if (kind != PE_TRANSFORM_FFT) return set_error(PE_E_ARG, "unknown transform %d", kind);
+  if (g->precision != PE_FP64) return set_error(PE_E_ARG, "the FFT transform needs an FP64 grid");
+  for (int a = 0; a < g->dim; ++a)
+    if (!fft_axis_ok(g->ax[a].n))
+      return set_error(PE_E_ARG, "the FFT transform needs n + 1 in {64, 128, 256, 512} (axis %d: n = %d)",
+                       a, g->ax[a].n);
+  PE_TRY(fft_prepare(g));
+  g->transform = kind;
+  return PE_OK;
 }
 
 pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream) {

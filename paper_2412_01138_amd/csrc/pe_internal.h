@@ -63,6 +63,8 @@ struct Axis {
   //          P11S[k][n] = Sq[1][1][2n][k], P11D[k][n] = Sq[1][1][2n+1][k]
   bool l3 = false;
   double *d_L3 = nullptr;        // [2][3 Q^2 / 2]
+  // FFT transform: w^k = exp(-2 pi i k / N), N = 2 (n + 1), as (re, im)
+  double *d_tw = nullptr;        // [N][2]
 };
 
 struct PendingTiming {
@@ -89,6 +91,7 @@ struct pe_grid_s {
   int dim = 0;
   int precision = PE_FP64;
   int quad_q = 3;
+  int transform = PE_TRANSFORM_DENSE;
   double D = 0;
   int64_t dof = 0;               // prod n_a
   int64_t dofp = 0;              // prod np_a (padded field size)
@@ -195,6 +198,7 @@ struct GenSrc {
   const double *C1 = nullptr;     // [M][np_1]  (d == 3)
   const double *coef = nullptr;   // [count][M]
   const double *Cf = nullptr;     // [2][M][Kh_last]
+  const double *Cl = nullptr;     // [M][np_last] (the FFT transform's generation)
   int M = 0;
 };
 
@@ -225,6 +229,21 @@ bool gen_supported(pe_grid g, int n_terms);
 // Cf[h][m][p] from C[m][j] of the last axis (device)
 pe_status fold_table(pe_grid g, const double *C_last, int n_terms, double *Cf, hipStream_t st);
 pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst, hipStream_t st);
+
+// FFT transform (FP64): axes with n + 1 in {64, .., 512}; the twiddle
+// tables are built by fft_prepare.  dst_fields_fft has the contract of
+// dst_fields_f64 (gen->Cl the plain last-axis table); the fused axis-0 pass
+// + update takes (1 + s) DOF_padded doubles of tables from fft_tables.
+bool fft_axis_ok(int n);
+bool fft_gen_supported(pe_grid g, int n_terms);
+pe_status fft_prepare(pe_grid g);
+pe_status dst_fields_fft(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
+                         double **result, hipStream_t st, int stop_axis = 0);
+bool fft_final_supported(pe_grid g);
+pe_status fft_tables(pe_grid g, int s, const double *E, const double *B, double *Tf,
+                     hipStream_t st);
+pe_status fft_final_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tf,
+                           const double *Uin, double *Uout, hipStream_t st);
 
 // bytes of one padded stage field
 size_t field_bytes(pe_grid g);

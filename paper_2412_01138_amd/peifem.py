@@ -28,9 +28,11 @@ PE_MAX_TERMS = 64
 PE_MAX_ITERS = 64
 PE_FP64 = 0
 PE_SPLIT_BF16 = 1
+PE_TRANSFORM_DENSE = 0
+PE_TRANSFORM_FFT = 1
 
 EXPORTS = [
-    "pe_init_grid", "pe_free_grid", "pe_set_forcing", "pe_phi_tables",
+    "pe_init_grid", "pe_free_grid", "pe_set_transform", "pe_set_forcing", "pe_phi_tables",
     "pe_project_workspace_bytes", "pe_project", "pe_fine_workspace_bytes",
     "pe_fine_propagate", "pe_coarse_workspace_bytes", "pe_coarse_sweep",
     "pe_solve_workspace_bytes", "pe_parareal_solve", "pe_grid_dof",
@@ -104,6 +106,7 @@ def load_library():
     L.pe_init_grid.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), dp, dp, dbl, i32, i32, vp]
     L.pe_free_grid.argtypes = [vp]
     L.pe_free_grid.restype = None
+    L.pe_set_transform.argtypes = [vp, i32]
     L.pe_set_forcing.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
     L.pe_phi_tables.argtypes = [vp, dbl, i32, dp, vp, vp, vp]
     L.pe_project_workspace_bytes.argtypes = [vp]
@@ -147,7 +150,7 @@ def load_library():
                                         vp, sz, vp]
     L.pe_last_error.argtypes = []
     L.pe_last_error.restype = ctypes.c_char_p
-    for name in ("pe_init_grid", "pe_set_forcing", "pe_phi_tables", "pe_project",
+    for name in ("pe_init_grid", "pe_set_transform", "pe_set_forcing", "pe_phi_tables", "pe_project",
                  "pe_fine_propagate", "pe_coarse_sweep", "pe_parareal_solve", "pe_set_timing",
                  "pe_get_timing", "pe_mlp_create", "pe_mlp_get_params", "pe_mlp_set_params",
                  "pe_mlp_forward", "pe_mlp_train_step", "pe_learned_samples", "pe_learned_rows",
@@ -209,7 +212,8 @@ class Grid:
     """A pe_grid handle plus its forcing."""
 
     def __init__(self, n: Sequence[int], lo: Sequence[float], hi: Sequence[float], D: float,
-                 precision: str = "fp64", quad_q: int = 3, device: str = "cuda:0", stream=None):
+                 precision: str = "fp64", quad_q: int = 3, device: str = "cuda:0", stream=None,
+                 transform: str = "dense"):
         import torch
         self.L = load_library()
         self.device = torch.device(device)
@@ -227,12 +231,25 @@ class Grid:
                                        _stream(stream)))
         self.h = handle
         self.dof = int(self.L.pe_grid_dof(self.h))
+        self.transform = "dense"
+        if transform != "dense":
+            self.set_transform(transform)
 
     @classmethod
-    def from_problem(cls, prob, quad_q: int = 3, device: str = "cuda:0", stream=None) -> "Grid":
-        g = cls(prob.n, prob.lo, prob.hi, prob.D, prob.precision, quad_q, device, stream)
+    def from_problem(cls, prob, quad_q: int = 3, device: str = "cuda:0", stream=None,
+                     transform: str = "dense") -> "Grid":
+        g = cls(prob.n, prob.lo, prob.hi, prob.D, prob.precision, quad_q, device, stream,
+                transform)
         g.set_forcing(prob.forcing)
         return g
+
+    def set_transform(self, kind: str):
+        """"dense" (matrix-core products) or "fft" (LDS FFT of the odd extension)."""
+        import torch
+        code = {"dense": PE_TRANSFORM_DENSE, "fft": PE_TRANSFORM_FFT}[kind]
+        with torch.cuda.device(self.device):
+            _check(self.L.pe_set_transform(self.h, code))
+        self.transform = kind
 
     def close(self):
         if getattr(self, "h", None):
@@ -443,9 +460,10 @@ class Mlp:
 
 
 def solve_problem(prob, K_max: Optional[int] = None, tol: Optional[float] = None,
-                  corr=None, device: str = "cuda:0", mlp: Optional[Mlp] = None):
+                  corr=None, device: str = "cuda:0", mlp: Optional[Mlp] = None,
+                  transform: str = "dense"):
     """Grid + forcing + P_h u0 + Algorithm 1 for a workloads.Problem."""
-    g = Grid.from_problem(prob, device=device)
+    g = Grid.from_problem(prob, device=device, transform=transform)
     U0 = g.project(prob.u0) if prob.u0 else None
     P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
                        prob.K_max if K_max is None else K_max, prob.tol if tol is None else tol, corr,
