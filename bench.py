@@ -201,6 +201,50 @@ def split_workloads(repeats: int = 2):
     return out
 
 
+def fft_transform(prob, U_dense, repeats: int):
+    """The same solve with the FFT sine transform (pe_set_transform): wall time
+    per solve, fine-pass rate, per-kernel HIP-event time, and the answer's
+    distance from the dense-transform answer."""
+    import torch
+    from paper_2412_01138_amd import peifem
+
+    g = peifem.Grid.from_problem(prob, transform="fft")
+    P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
+                       prob.K_max, prob.tol)
+    work = g.workspace(g.solve_workspace_bytes(P))
+    U = g.empty_states(prob.N + 1)
+    g.parareal_solve(P, U=U, work=work)
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    reports = []
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        _, rep = g.parareal_solve(P, U=U, work=work)
+        reports.append(rep)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / repeats
+    stats = g.get_timing()
+    g.set_timing(False)
+    iters = reports[-1].iterations
+    fine_updates = prob.dof * prob.N * prob.J * prob.q
+    fine_ms = sum(r.ms_fine for r in reports) / len(reports) / max(iters, 1)
+    diff = float(torch.linalg.vector_norm(U - U_dense) / torch.linalg.vector_norm(U_dense))
+    out = {"ms_per_solve": ms, "iterations": iters,
+           "fine_updates_per_s": iters * fine_updates / (ms / 1e3),
+           "ms_fine_per_pass": fine_ms,
+           "fine_pass_updates_per_s": fine_updates / (fine_ms / 1e3),
+           "kernels_ms_per_launch": {k: v["ms"] / v["launches"] for k, v in stats.items()
+                                     if v["launches"]},
+           "kernels_TFLOP_s": {k: v["flops"] / v["ms"] / 1e9 for k, v in stats.items()
+                               if v["launches"] and v["ms"] > 0},
+           "kernels_GB_s": {k: v["bytes"] / v["ms"] / 1e6 for k, v in stats.items()
+                            if v["launches"] and v["ms"] > 0},
+           "answer_rel_diff_vs_dense": diff}
+    del work, U, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +256,8 @@ def main():
                     help="skip the learned-vs-plain G comparison")
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3D split-bf16 workloads")
+    ap.add_argument("--no-fft", action="store_true",
+                    help="skip the FFT-transform comparison solve")
     ap.add_argument("--only-3d", action="store_true",
                     help="run only the 3D split-bf16 workloads (profiling)")
     ap.add_argument("--learned-forcings", type=int, default=4096)
@@ -341,6 +387,8 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+    if not args.no_fft:
+        out["fft_transform"] = fft_transform(prob, U, max(args.steps, 3))
     if not args.no_learned:
         out["learned_vs_plain_G"] = learned_vs_plain(args.learned_forcings, args.learned_steps)
     if not args.no_3d:

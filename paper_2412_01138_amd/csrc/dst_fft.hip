@@ -90,22 +90,46 @@ __device__ __forceinline__ void dft8(c2 *v) {
   v[7] = csub(e3, o3);
 }
 
+// Radix of the last Stockham stage (radix-8 stages, then the remainder).
+constexpr int last_radix(int N) {
+  int ns = 1, r = 8;
+  while (ns < N) {
+    r = N / ns >= 8 ? 8 : N / ns;
+    ns *= r;
+  }
+  return r;
+}
+
+// The FFTs of up to 512 points run inside one wave (N/8 <= 64 threads), so
+// their stages need only the wave's own ordering of its LDS accesses; longer
+// ones span two waves and take the block barrier.
+template <int N>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (N / 8 <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage of radix R on the sub-transforms of size NS: butterfly
 // j takes the R inputs j + r N/R, twists input r by w_N^{r k N/(NS R)}
 // (k = j mod NS), transforms them and stores output r at
-// (j / NS) NS R + k + r NS.  A thread does 8/R butterflies; the block reads
-// everything before anyone writes (the stage is in place).
-template <int N, int R, int NS>
-__device__ __forceinline__ void fft_stage(c2 *Z, const c2 *__restrict__ tw, int u) {
+// (j / NS) NS R + k + r NS.  A thread does 8/R butterflies; all reads come
+// before any write (the stage is in place).  Without STORE the outputs stay
+// in v.
+template <int N, int R, int NS, bool STORE>
+__device__ __forceinline__ void fft_stage(c2 *Z, const c2 *__restrict__ tw, int u, c2 (&v)[8]) {
   constexpr int B = 8 / R;
-  c2 v[8];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = u + b * (N / 8);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b * R + r] = Z[pidx(j + r * (N / R))];
   }
-  __syncthreads();
+  fft_sync<N>();
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = u + b * (N / 8);
@@ -117,20 +141,35 @@ __device__ __forceinline__ void fft_stage(c2 *Z, const c2 *__restrict__ tw, int 
     if constexpr (R == 8) dft8(&v[b * R]);
     if constexpr (R == 4) dft4(v[b * R], v[b * R + 1], v[b * R + 2], v[b * R + 3]);
     if constexpr (R == 2) dft2(&v[b * R]);
-    const int dst = (j / NS) * NS * R + k;
+    if constexpr (STORE) {
+      const int dst = (j / NS) * NS * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) Z[pidx(dst + r * NS)] = v[b * R + r];
+      for (int r = 0; r < R; ++r) Z[pidx(dst + r * NS)] = v[b * R + r];
+    }
   }
-  __syncthreads();
+  if constexpr (STORE) fft_sync<N>();
 }
 
-template <int N, int NS>
-__device__ __forceinline__ void fft_stages(c2 *Z, const c2 *__restrict__ tw, int u) {
+// All stages of the FFT in Z (thread u of its N/8).  With KEEP_LAST the last
+// stage's outputs stay in v: there NS = N/R, so butterfly j = u + b N/8 holds
+// the outputs j + r N/R, and those below L = N/2 (the sine sums) are the
+// four slots s = b (R/2) + r, r < R/2 (last_slot).
+template <int N, int NS, bool KEEP_LAST>
+__device__ __forceinline__ void fft_run(c2 *Z, const c2 *__restrict__ tw, int u, c2 (&v)[8]) {
   if constexpr (NS < N) {
     constexpr int R = N / NS >= 8 ? 8 : N / NS;
-    fft_stage<N, R, NS>(Z, tw, u);
-    fft_stages<N, NS * R>(Z, tw, u);
+    fft_stage<N, R, NS, !(KEEP_LAST && NS * R == N)>(Z, tw, u, v);
+    fft_run<N, NS * R, KEEP_LAST>(Z, tw, u, v);
   }
+}
+
+// slot s (0..3) of a kept last stage: register vi and DFT index fi < L
+template <int N>
+__device__ __forceinline__ void last_slot(int u, int s, int &vi, int &fi) {
+  constexpr int R = last_radix(N), H = R / 2;
+  const int b = s / H, r = s % H;
+  vi = b * R + r;
+  fi = u + b * (N / 8) + r * (N / R);
 }
 
 // Writes node j (0-based, value x) of tile line l into the odd extension:
@@ -177,14 +216,14 @@ struct FftPassArgs {
   int64_t rows;              // lines per field (product of the other axes' np)
 };
 
-// MT: the generated terms rounded up (8, 16 or 32; sizes the LDS of the
-// per-line factors and the registers of the last-axis tables)
-template <int N, bool GEN, bool CONTIG, int MT>
+// One axis of a batch of fields, lines read from `in`.  Block = LINES
+// lines; contiguous lines (the last axis) are read and written by the wave
+// that transforms them, strided lines (adjacent columns) across the block.
+template <int N, bool CONTIG>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_pass(FftPassArgs a) {
   using Sh = Shape<N>;
   constexpr int L = Sh::L, LINES = Sh::LINES;
   __shared__ c2 Zs[Sh::P * Sh::FS];
-  __shared__ double pre[GEN ? LINES * MT : 1];
   double *Zd = reinterpret_cast<double *>(Zs);
   const int t = threadIdx.x;
   const int64_t l0 = int64_t(blockIdx.x) * LINES;
@@ -193,74 +232,118 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_pass(FftPassArgs a) {
     const int64_t o = ln / a.inner;
     return o * L * a.inner + (ln - o * a.inner);
   };
-
-  if constexpr (GEN) {
-    for (int e = t; e < LINES * a.M; e += FFT_THREADS) {
-      const int l = e / a.M, m = e - l * a.M;
-      const int64_t ln = l0 + l;
-      double v = 0.0;
-      if (ln < a.nlines) {
-        const int64_t f = ln / a.rows;
-        const int64_t r = ln - f * a.rows;
-        v = a.coef[f * a.M + m];
-        if (a.d == 2) v *= a.C0[int64_t(m) * a.np0 + r];
-        if (a.d == 3) {
-          v *= a.C0[int64_t(m) * a.np0 + r / a.np1];
-          v *= a.C1[int64_t(m) * a.np1 + r % a.np1];
-        }
-      }
-      pre[l * MT + m] = v;
-    }
-    // thread = node position j (fixed, 512 is a multiple of L), 8 lines
-    const int j = t % L;
-    double cl[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-      cl[m] = (m < a.M && j < L - 1) ? a.Cl[int64_t(m) * L + j] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int l = t / L + k * (FFT_THREADS / L);
-      const double *pl = pre + l * MT;
-      double x = 0.0;
-#pragma unroll
-      for (int m = 0; m < MT; ++m)
-        if (m < a.M) x += pl[m] * cl[m];
-      put_node<N>(Zd, l, j, x);
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int e = t + k * FFT_THREADS;
-      // contiguous lines: consecutive threads walk a line; strided lines:
-      // consecutive threads take consecutive lines (adjacent columns)
-      const int l = CONTIG ? e / L : e % LINES;
-      const int j = CONTIG ? e % L : e / LINES;
-      const int64_t ln = l0 + l;
-      const double x = (ln < a.nlines && j < L - 1) ? a.in[line_base(ln) + int64_t(j) * a.inner] : 0.0;
-      put_node<N>(Zd, l, j, x);
-    }
-  }
-  __syncthreads();
-  fft_stages<N, 1>(Zs + (t / Sh::TF) * Sh::FS, a.tw, t % Sh::TF);
-
-  const double scale = 1.0 / sqrt(double(N));
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int e = t + k * FFT_THREADS;
+    // contiguous lines: consecutive threads walk a line; strided lines:
+    // consecutive threads take consecutive lines (adjacent columns)
     const int l = CONTIG ? e / L : e % LINES;
-    const int q = CONTIG ? e % L : e / LINES;
+    const int j = CONTIG ? e % L : e / LINES;
     const int64_t ln = l0 + l;
-    if (ln >= a.nlines) continue;
-    const int m = unfold_pos(q, L / 2);
-    const double y = m < L - 1 ? get_mode<N>(Zs, l, m) * scale : 0.0;
-    a.out[line_base(ln) + int64_t(q) * a.inner] = y;
+    const double x = (ln < a.nlines && j < L - 1) ? a.in[line_base(ln) + int64_t(j) * a.inner] : 0.0;
+    put_node<N>(Zd, l, j, x);
+  }
+  __syncthreads();
+  const int p = t / Sh::TF, u = t % Sh::TF;
+  c2 v[8];
+  fft_run<N, 1, CONTIG>(Zs + p * Sh::FS, a.tw, u, v);
+
+  const double scale = 1.0 / sqrt(double(N));
+  if constexpr (CONTIG) {
+    // straight from the registers: the FFT's two lines, mode m = fi - 1 at
+    // folded position fold_pos(m); the slot of fi = 0 writes the pad L - 1
+    const int64_t ln0 = l0 + p, ln1 = l0 + p + Sh::P;
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      int vi, fi;
+      last_slot<N>(u, sl, vi, fi);
+      const int q = fi > 0 ? fold_pos(fi - 1, L / 2) : L - 1;
+      if (ln0 < a.nlines) a.out[ln0 * L + q] = fi > 0 ? -v[vi].y * scale : 0.0;
+      if (ln1 < a.nlines) a.out[ln1 * L + q] = fi > 0 ? v[vi].x * scale : 0.0;
+    }
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = t + k * FFT_THREADS;
+      const int l = e % LINES, q = e / LINES;
+      const int64_t ln = l0 + l;
+      if (ln >= a.nlines) continue;
+      const int m = unfold_pos(q, L / 2);
+      const double y = m < L - 1 ? get_mode<N>(Zs, l, m) * scale : 0.0;
+      a.out[line_base(ln) + int64_t(q) * a.inner] = y;
+    }
+  }
+}
+
+// The last-axis pass generating its lines from the separable load tables:
+// block = LINES lines, the thread's node position j = t mod L.  MT: the
+// terms rounded up (8, 16 or 32; sizes the factor buffer and the table
+// registers).  (A persistent form that keeps the table column in registers
+// across tiles holds too many registers for two blocks per CU and is slower.)
+template <int N, int MT>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_gen(FftPassArgs a) {
+  using Sh = Shape<N>;
+  constexpr int L = Sh::L, LINES = Sh::LINES;
+  __shared__ c2 Zs[Sh::P * Sh::FS];
+  __shared__ double pre[LINES * MT];
+  double *Zd = reinterpret_cast<double *>(Zs);
+  const int t = threadIdx.x;
+  const int64_t l0 = int64_t(blockIdx.x) * LINES;
+  // factor (l, m): coef[f][m] times the other axes' tables at the line's
+  // nodes (zero beyond the lines)
+  for (int e = t; e < LINES * a.M; e += FFT_THREADS) {
+    const int l = e / a.M, m = e - l * a.M;
+    const int64_t ln = l0 + l;
+    double v = 0.0;
+    if (ln < a.nlines) {
+      const int64_t f = ln / a.rows;
+      const int64_t r = ln - f * a.rows;
+      v = a.coef[f * a.M + m];
+      if (a.d == 2) v *= a.C0[int64_t(m) * a.np0 + r];
+      if (a.d == 3) {
+        v *= a.C0[int64_t(m) * a.np0 + r / a.np1];
+        v *= a.C1[int64_t(m) * a.np1 + r % a.np1];
+      }
+    }
+    pre[l * MT + m] = v;
+  }
+  const int j = t % L;
+  double cl[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) cl[m] = (m < a.M && j < L - 1) ? a.Cl[int64_t(m) * L + j] : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int l = t / L + k * (FFT_THREADS / L);
+    const double *pl = pre + l * MT;
+    double x = 0.0;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+      if (m < a.M) x += pl[m] * cl[m];
+    put_node<N>(Zd, l, j, x);
+  }
+  __syncthreads();
+  const int p = t / Sh::TF, u = t % Sh::TF;
+  c2 v[8];
+  fft_run<N, 1, true>(Zs + p * Sh::FS, a.tw, u, v);
+  const double scale = 1.0 / sqrt(double(N));
+  const int64_t ln0 = l0 + p, ln1 = ln0 + Sh::P;
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    int vi, fi;
+    last_slot<N>(u, sl, vi, fi);
+    const int q = fi > 0 ? fold_pos(fi - 1, L / 2) : L - 1;
+    if (ln0 < a.nlines) a.out[ln0 * L + q] = fi > 0 ? -v[vi].y * scale : 0.0;
+    if (ln1 < a.nlines) a.out[ln1 * L + q] = fi > 0 ? v[vi].x * scale : 0.0;
   }
 }
 
 // Axis-0 pass fused with the update.  Block = (slice nl, strip of LINES
-// columns); thread t owns column l = t mod LINES and the modes
-// m = t / LINES + k (512 / LINES), k < 8, of every field of the slice.
+// columns).  The strip is loaded across the block (adjacent columns per
+// thread), transformed per line pair inside a wave, and the thread updates
+// the modes of its own last FFT stage: slot s (0..3) and part h (0: the real
+// line p, 1: the imaginary line p + P), state k = 2 s + h.
 struct FftFinalArgs {
   const double *X;        // [fields][L][inner] after the other axes' passes
   const double *Tf;       // update tables in the thread order (fft_tables)
@@ -274,7 +357,7 @@ struct FftFinalArgs {
 
 // state index of (mode m, padded column c) or -1 at pads (DOF < 2^31 here)
 __device__ __forceinline__ int fft_state_index(const FftFinalArgs &a, int L, int m, int64_t c) {
-  if (m >= L - 1) return -1;
+  if (m < 0 || m >= L - 1) return -1;
   int k1, k2 = 0;
   if (a.d == 3) {
     k1 = unfold_pos(int(c / a.np2), a.Kh1);
@@ -287,6 +370,17 @@ __device__ __forceinline__ int fft_state_index(const FftFinalArgs &a, int L, int
   return (m * a.n1 + k1) * (a.d == 3 ? a.n2 : 1) + k2;
 }
 
+// (mode, column) of state k of thread t in strip `strip`
+template <int N>
+__device__ __forceinline__ void final_state(int t, int k, int64_t strip, int &m, int64_t &col) {
+  using Sh = Shape<N>;
+  const int p = t / Sh::TF, u = t % Sh::TF;
+  int vi, fi;
+  last_slot<N>(u, k / 2, vi, fi);
+  m = fi - 1;
+  col = strip * Sh::LINES + p + (k & 1) * Sh::P;
+}
+
 template <int N>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_final(FftFinalArgs a) {
   using Sh = Shape<N>;
@@ -296,19 +390,22 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_final(FftFinalArgs a) {
   const int t = threadIdx.x;
   const int nl = int(blockIdx.x % a.nslices);
   const int strip = int(blockIdx.x / a.nslices);
-  const int l = t % LINES;
-  const int64_t col = int64_t(strip) * LINES + l;
+  const int p = t / Sh::TF, u = t % Sh::TF;
   const int nf = a.jc * a.s;
 
   int kidx[8];
   double W[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int m = t / LINES + k * (FFT_THREADS / LINES);
-    kidx[k] = fft_state_index(a, L, m, col);
+    int m;
+    int64_t c;
+    final_state<N>(t, k, strip, m, c);
+    kidx[k] = fft_state_index(a, L, m, c);
     W[k] = (a.Uin && kidx[k] >= 0) ? a.Uin[int64_t(nl) * a.dof + kidx[k]] : 0.0;
   }
-  const double *Xs = a.X + int64_t(nl) * nf * L * a.inner + col;
+  // loader: thread = column l (adjacent across threads), rows j = t / LINES + k 512/LINES
+  const int l = t % LINES;
+  const double *Xs = a.X + int64_t(nl) * nf * L * a.inner + int64_t(strip) * LINES + l;
   const double *Tl = a.Tf + int64_t(strip) * (1 + a.s) * 8 * FFT_THREADS + t;
   double S[8];
   auto load = [&](int e) {
@@ -325,20 +422,26 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_final(FftFinalArgs a) {
     for (int k = 0; k < 8; ++k) put_node<N>(Zd, l, t / LINES + k * (FFT_THREADS / LINES), S[k]);
     __syncthreads();
     if (e + 1 < nf) load(e + 1);   // in flight during the transform
-    fft_stages<N, 1>(Zs + (t / Sh::TF) * Sh::FS, a.tw, t % Sh::TF);
+    c2 v[8];
+    fft_run<N, 1, true>(Zs + p * Sh::FS, a.tw, u, v);
     // eq. (2.6): W = E W at a step's first stage, then W += (b_i sigma) y;
     // the tables carry sigma and the 1/sqrt(2L)
     const int i = e % a.s;
     const double *Ti = Tl + (1 + i) * 8 * FFT_THREADS;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int m = t / LINES + k * (FFT_THREADS / LINES);
-      const double y = get_mode<N>(Zs, l, m < L - 1 ? m : 0);
-      double w = W[k];
-      if (i == 0) w = Tl[k * FFT_THREADS] * w;
-      W[k] = w + Ti[k * FFT_THREADS] * y;
+    for (int sl = 0; sl < 4; ++sl) {
+      int vi, fi;
+      last_slot<N>(u, sl, vi, fi);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * sl + h;
+        const double y = h ? v[vi].x : -v[vi].y;
+        double w = W[k];
+        if (i == 0) w = Tl[k * FFT_THREADS] * w;
+        W[k] = w + Ti[k * FFT_THREADS] * y;
+      }
     }
-    __syncthreads();
+    __syncthreads();   // every wave is done with LDS before the next strip lands
   }
   double *Uo = a.Uout + int64_t(nl) * a.dof;
 #pragma unroll
@@ -348,7 +451,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_final(FftFinalArgs a) {
 
 // Tables of k_fft_final: Tf[strip][tbl][k][t], tbl 0 = E, tbl 1 + i =
 // b_i sigma / sqrt(2L) (zero at pads).
-__global__ void k_fft_tables(FftFinalArgs a, int L, int LINES, const double *__restrict__ sig0,
+__global__ void k_fft_tables(FftFinalArgs a, int L, const double *__restrict__ sig0,
                              const double *__restrict__ sig1, const double *__restrict__ sig2,
                              const double *__restrict__ E, const double *__restrict__ B,
                              double *Tf) {
@@ -359,9 +462,12 @@ __global__ void k_fft_tables(FftFinalArgs a, int L, int LINES, const double *__r
     const int k = int((e / FFT_THREADS) % 8);
     const int tbl = int((e / (8 * FFT_THREADS)) % (1 + a.s));
     const int64_t strip = e / (int64_t(8) * FFT_THREADS * (1 + a.s));
-    const int l = t % LINES;
-    const int m = t / LINES + k * (FFT_THREADS / LINES);
-    const int64_t col = strip * LINES + l;
+    int m;
+    int64_t col;
+    if (L == 64) final_state<128>(t, k, strip, m, col);
+    else if (L == 128) final_state<256>(t, k, strip, m, col);
+    else if (L == 256) final_state<512>(t, k, strip, m, col);
+    else final_state<1024>(t, k, strip, m, col);
     const int64_t ki = fft_state_index(a, L, m, col);
     double v = 0.0;
     if (ki >= 0) {
@@ -417,17 +523,19 @@ pe_status fft_prepare(pe_grid g) {
 
 template <int N>
 static void launch_pass(const FftPassArgs &a, bool gen, bool contig, hipStream_t st) {
-  const unsigned blocks = unsigned((a.nlines + Shape<N>::LINES - 1) / Shape<N>::LINES);
-  if (gen && a.M <= 8)
-    k_fft_pass<N, true, true, 8><<<blocks, FFT_THREADS, 0, st>>>(a);
-  else if (gen && a.M <= 16)
-    k_fft_pass<N, true, true, 16><<<blocks, FFT_THREADS, 0, st>>>(a);
-  else if (gen)
-    k_fft_pass<N, true, true, FFT_GEN_MAX_TERMS><<<blocks, FFT_THREADS, 0, st>>>(a);
-  else if (contig)
-    k_fft_pass<N, false, true, 1><<<blocks, FFT_THREADS, 0, st>>>(a);
-  else
-    k_fft_pass<N, false, false, 1><<<blocks, FFT_THREADS, 0, st>>>(a);
+  const int64_t tiles = (a.nlines + Shape<N>::LINES - 1) / Shape<N>::LINES;
+  if (gen) {
+    if (a.M <= 8)
+      k_fft_gen<N, 8><<<unsigned(tiles), FFT_THREADS, 0, st>>>(a);
+    else if (a.M <= 16)
+      k_fft_gen<N, 16><<<unsigned(tiles), FFT_THREADS, 0, st>>>(a);
+    else
+      k_fft_gen<N, FFT_GEN_MAX_TERMS><<<unsigned(tiles), FFT_THREADS, 0, st>>>(a);
+  } else if (contig) {
+    k_fft_pass<N, true><<<unsigned(tiles), FFT_THREADS, 0, st>>>(a);
+  } else {
+    k_fft_pass<N, false><<<unsigned(tiles), FFT_THREADS, 0, st>>>(a);
+  }
 }
 
 pe_status dst_fields_fft(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
@@ -510,10 +618,9 @@ pe_status fft_tables(pe_grid g, int s, const double *E, const double *B, double 
                      hipStream_t st) {
   FftFinalArgs a = final_args(g, s);
   const int L = g->ax[0].n + 1;
-  const int LINES = 2 * (FFT_POINTS / (2 * L));
   const int64_t n = int64_t(a.strips) * (1 + s) * 8 * FFT_THREADS;
   const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
-  k_fft_tables<<<blocks, 256, 0, st>>>(a, L, LINES, g->ax[0].d_sig, g->ax[1].d_sig,
+  k_fft_tables<<<blocks, 256, 0, st>>>(a, L, g->ax[0].d_sig, g->ax[1].d_sig,
                                         g->dim > 2 ? g->ax[2].d_sig : nullptr, E, B, Tf);
   PE_HIP(hipGetLastError());
   return PE_OK;
