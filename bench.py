@@ -53,6 +53,9 @@ KERNEL_SOURCES = {
     "update": ("fine.hip", "pe_internal.h"),
     "sweep": ("coarse.hip", "pe_internal.h"),
     "mid_update": ("fused_update.hip", "pe_internal.h"),
+    # FFT transform kernels (the fft_transform comparison solve)
+    "fft_gen": ("dst_fft.hip", "pe_internal.h"),
+    "fft_final": ("dst_fft.hip", "pe_internal.h"),
 }
 
 
