@@ -16,6 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import phi
+from .boundary import FullGrid
 from .fem import Grid, gauss_legendre_01
 from .forcing import load_field, eval_terms, space_factor, time_factor
 
@@ -37,6 +38,9 @@ class Discretization:
         self.D = float(prob.D)
         self.q = q
         self.lam = self.grid.eigenvalues()
+        # non-homogeneous Dirichlet data: the interior system's load gains
+        # -(M_IB G_B' + D A_IB G_B) (oracle/boundary.py)
+        self.full = FullGrid(prob) if getattr(prob, "boundary", None) else None
 
     def tables(self, h: float, c: Sequence[float]) -> StepTables:
         z = h * self.D * self.lam
@@ -44,14 +48,21 @@ class Discretization:
         return StepTables(h, tuple(c), E, b)
 
     def spectral_forcing(self, t: float) -> np.ndarray:
-        """Coefficients of P_h f(t): Q^T F(t)."""
-        return self.grid.to_spectral(load_field(self.grid, self.prob.forcing, t, self.q))
+        """Coefficients of P_h f(t): Q^T F(t) (with the boundary coupling)."""
+        F = load_field(self.grid, self.prob.forcing, t, self.q)
+        if self.full is not None:
+            F = F + self.full.load_correction(t)
+        return self.grid.to_spectral(F)
 
     def initial(self) -> np.ndarray:
-        """Coefficients of P_h u0."""
-        if not self.prob.u0:
-            return np.zeros(self.grid.n)
-        return self.grid.to_spectral(load_field(self.grid, self.prob.u0, 0.0, self.q, use_time=False))
+        """Coefficients of P_h u0 (with boundary data: the interior part of
+        the L2 projection whose boundary values are g(t0))."""
+        F = np.zeros(self.grid.n)
+        if self.prob.u0:
+            F = load_field(self.grid, self.prob.u0, 0.0, self.q, use_time=False)
+        if self.full is not None:
+            F = F + self.full.initial_correction(self.prob.t0)
+        return self.grid.to_spectral(F)
 
 
 def eife_step(disc: Discretization, W: np.ndarray, t: float, tab: StepTables) -> np.ndarray:

@@ -92,6 +92,9 @@ class Problem:
     exact: Optional[List[Term]] = None
     seed: Optional[int] = None
     notes: str = ""
+    # Dirichlet data u = g on the boundary (separable terms with time
+    # factors); empty: homogeneous data
+    boundary: List[Term] = field(default_factory=list)
 
     @property
     def q(self) -> int:
