@@ -125,6 +125,25 @@ pe_status pe_set_transform(pe_grid g, int32_t kind);
  * vector of P_h f, paper eq. (2.6)).  Errors: PE_E_ARG.  Synchronises. */
 pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream);
 
+/* Dirichlet data u = g on the boundary of the box, as n_terms (0..) separable
+ * terms with time factors (host array; n_terms = 0: homogeneous data, the
+ * default).  The paper states the method for homogeneous data (Section 2)
+ * and notes the extension to non-homogeneous data at the start of Sections
+ * 3 and 4; the reading used here: u_h(t) = sum over interior nodes of
+ * U_j(t) phi_j + g_h(t), g_h the Q1 interpolant of g on the boundary nodes,
+ * so the interior system keeps its matrices and its load vector gains
+ *     -(M_IB g_B'(t) + D A_IB g_B(t)),
+ * g_B the data at the boundary nodes.  For separable data that load is
+ * 2 + 2d separable terms per data term (1D tables from the data's nodal
+ * values on each axis); they join the forcing's terms, so every call that
+ * evaluates the forcing (pe_fine_propagate, pe_coarse_sweep's r_n,
+ * pe_parareal_solve, the learned calls) includes them.  States stay the
+ * interior coefficients; the full solution adds g_h(t).  The initial state
+ * comes from pe_project_state.  Errors: PE_E_ARG when the forcing's terms
+ * plus (2 + 2d) n_terms exceed PE_MAX_TERMS or for null terms (the grid keeps
+ * its previous data).  Synchronises `stream`. */
+pe_status pe_set_boundary(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream);
+
 /* Exponential Runge-Kutta tables for step h > 0 and s (1..PE_MAX_STAGES)
  * distinct nodes c[0..s-1] in [0, 1] (host):
  *     d_E[k]       = exp(-h D lambda_k)
@@ -145,6 +164,17 @@ pe_status pe_phi_tables(pe_grid g, double h, int32_t s, const double *c, double 
 size_t pe_project_workspace_bytes(pe_grid g);
 pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W, void *d_work,
                      size_t work_bytes, void *stream);
+
+/* The interior state of the FE function whose boundary values are the grid's
+ * Dirichlet data at time t (pe_set_boundary) and which is otherwise the L2
+ * projection of v (n_terms separable terms, time factors ignored): d_W
+ * receives (kron_a Q_a)^T (F_v - M_IB g_B(t)).  This is the initial state
+ * U(t0) with non-homogeneous data; without data it equals pe_project.  Same
+ * workspace as pe_project.  Errors: PE_E_ARG (null pointers, non-finite t,
+ * more than PE_MAX_TERMS terms with the data's two per data term),
+ * PE_E_WORKSPACE. */
+pe_status pe_project_state(pe_grid g, int32_t n_terms, const pe_term *terms, double t, void *d_W,
+                           void *d_work, size_t work_bytes, void *stream);
 
 /* Fine propagator F on all slices at once (paper, Section 2.3: F is J steps
  * of eq. (2.6) with step dt = dT/J and q nodes):

@@ -401,49 +401,53 @@ size_t pe_project_workspace_bytes(pe_grid g) {
   return b;
 }
 
-pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W, void *d_work,
-                     size_t work_bytes, void *stream) {
-  clear_error();
-  if (!g || !d_W) return set_error(PE_E_ARG, "null argument");
-  if (n_terms < 0 || n_terms > PE_MAX_TERMS) return set_error(PE_E_ARG, "n_terms out of range");
-  if (n_terms > 0 && (!terms || !d_work)) return set_error(PE_E_ARG, "null terms/workspace");
-  hipStream_t st = as_stream(stream);
+// P_h of n_terms separable terms plus explicit-table terms `der` (their
+// amplitudes already include any time factor): W = (kron Q_a)^T F.
+static pe_status project_impl(pe_grid g, int32_t n_terms, const pe_term *terms,
+                              const std::vector<DerivedTerm> &der, void *d_W, void *d_work,
+                              size_t work_bytes, hipStream_t st) {
   size_t sbytes = g->precision == PE_FP64 ? sizeof(double) : sizeof(float);
-  if (n_terms == 0) {
+  const int M = n_terms + int(der.size());
+  if (M == 0) {
     PE_HIP(hipMemsetAsync(d_W, 0, size_t(g->dof) * sbytes, st));
     return PE_OK;
   }
+  if (M > PE_MAX_TERMS)
+    return set_error(PE_E_ARG, "%d terms + %d from the boundary data exceed %d", n_terms,
+                     int(der.size()), PE_MAX_TERMS);
+  if (!d_work) return set_error(PE_E_ARG, "null workspace");
   if (work_bytes < pe_project_workspace_bytes(g))
     return set_error(PE_E_WORKSPACE, "workspace %zu B below %zu B", work_bytes,
                      pe_project_workspace_bytes(g));
   Arena ar(d_work, work_bytes);
   double *C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};
-  for (int a = 0; a < g->dim; ++a) C[a] = ar.take<double>(size_t(n_terms) * g->ax[a].np);
-  double *coef = ar.take<double>(n_terms);
-  double *Cf = ar.take<double>(2 * size_t(n_terms) * g->ax[g->dim - 1].Kh);
+  for (int a = 0; a < g->dim; ++a) C[a] = ar.take<double>(size_t(M) * g->ax[a].np);
+  double *coef = ar.take<double>(M);
+  double *Cf = ar.take<double>(2 * size_t(M) * g->ax[g->dim - 1].Kh);
   char *w0 = ar.take<char>(field_bytes(g));
   char *w1 = ar.take<char>(field_bytes(g));
   if (!coef || !Cf || !w0 || !w1)
     return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
-  PE_TRY(build_loads(g, n_terms, terms, C, st));
-  std::vector<double> amps(n_terms);
+  if (n_terms > 0) PE_TRY(build_loads(g, n_terms, terms, C, st));
+  PE_TRY(upload_derived(g, der, n_terms, C, st));
+  std::vector<double> amps(M);
   for (int m = 0; m < n_terms; ++m) amps[m] = terms[m].amp;
-  PE_HIP(hipMemcpyAsync(coef, amps.data(), sizeof(double) * n_terms, hipMemcpyHostToDevice, st));
+  for (size_t m = 0; m < der.size(); ++m) amps[n_terms + m] = der[m].time.amp;
+  PE_HIP(hipMemcpyAsync(coef, amps.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
   void *res = nullptr;
-  const bool fused = g->precision == PE_FP64 ? gen_supported(g, n_terms)
-                                              : gen_supported_split(g, n_terms);
+  const bool fused = g->precision == PE_FP64 ? gen_supported(g, M) : gen_supported_split(g, M);
   if (fused) {
-    PE_TRY(fold_table(g, C[g->dim - 1], n_terms, Cf, st));
+    PE_TRY(fold_table(g, C[g->dim - 1], M, Cf, st));
     GenSrc gs;
     gs.C0 = g->dim >= 2 ? C[0] : nullptr;
     gs.C1 = g->dim >= 3 ? C[1] : nullptr;
     gs.coef = coef;
     gs.Cf = Cf;
     gs.Cl = C[g->dim - 1];
-    gs.M = n_terms;
+    gs.M = M;
     PE_TRY(transform(g, 1, &gs, w0, w1, &res, st));
   } else {
-    PE_TRY(launch_load(g, C, n_terms, coef, w0, 1, st));
+    PE_TRY(launch_load(g, C, M, coef, w0, 1, st));
     PE_TRY(transform(g, 1, nullptr, w0, w1, &res, st));
   }
   Dims D = dims_of(g);
@@ -458,6 +462,27 @@ pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W
   PE_HIP(hipGetLastError());
   PE_HIP(hipStreamSynchronize(st));   // amps is host memory read by the copy
   return PE_OK;
+}
+
+pe_status pe_project(pe_grid g, int32_t n_terms, const pe_term *terms, void *d_W, void *d_work,
+                     size_t work_bytes, void *stream) {
+  clear_error();
+  if (!g || !d_W) return set_error(PE_E_ARG, "null argument");
+  if (n_terms < 0 || n_terms > PE_MAX_TERMS) return set_error(PE_E_ARG, "n_terms out of range");
+  if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");
+  return project_impl(g, n_terms, terms, {}, d_W, d_work, work_bytes, as_stream(stream));
+}
+
+pe_status pe_project_state(pe_grid g, int32_t n_terms, const pe_term *terms, double t, void *d_W,
+                           void *d_work, size_t work_bytes, void *stream) {
+  clear_error();
+  if (!g || !d_W) return set_error(PE_E_ARG, "null argument");
+  if (n_terms < 0 || n_terms > PE_MAX_TERMS) return set_error(PE_E_ARG, "n_terms out of range");
+  if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");
+  if (!std::isfinite(t)) return set_error(PE_E_ARG, "bad t");
+  std::vector<DerivedTerm> der;
+  boundary_terms(g, true, t, der);
+  return project_impl(g, n_terms, terms, der, d_W, d_work, work_bytes, as_stream(stream));
 }
 
 }  // extern "C"

@@ -359,7 +359,96 @@ DevTerm to_dev_term(const pe_term &t) {
   d.omega = t.time.omega;
   d.phase = t.time.phase;
   for (int i = 0; i < 4; ++i) d.p[i] = t.time.poly[i];
+  d.deriv = 0;
   return d;
+}
+
+static double space_value(const pe_space_factor &f, double x) {
+  return (f.poly[0] + x * (f.poly[1] + x * f.poly[2])) * std::sin(f.kappa * x + f.phase);
+}
+
+static double time_value(const pe_time_factor &tf, double t) {
+  const double poly = tf.poly[0] + t * (tf.poly[1] + t * (tf.poly[2] + t * tf.poly[3]));
+  return std::exp(tf.alpha * t) * std::cos(tf.omega * t + tf.phase) * poly;
+}
+
+void boundary_terms(pe_grid g, bool mass_only, double t, std::vector<DerivedTerm> &out) {
+  const int d = g->dim;
+  for (const pe_term &bt : g->src_boundary) {
+    // the 1D products of the data's nodal values on each axis
+    std::vector<double> P[PE_MAX_DIM], Qv[PE_MAX_DIM], R[PE_MAX_DIM], S[PE_MAX_DIM];
+    for (int a = 0; a < d; ++a) {
+      const Axis &ax = g->ax[a];
+      const int n = ax.n;
+      const double h = ax.h;
+      std::vector<double> xb(n + 2);
+      for (int j = 0; j < n + 2; ++j) xb[j] = space_value(bt.space[a], ax.lo + h * j);
+      P[a].resize(n);
+      Qv[a].resize(n);
+      R[a].resize(n);
+      S[a].resize(n);
+      for (int i = 0; i < n; ++i) {
+        const double xl = xb[i], xc = xb[i + 1], xr = xb[i + 2];
+        const double xli = i > 0 ? xl : 0.0, xri = i < n - 1 ? xr : 0.0;
+        P[a][i] = (h / 6.0) * xl + (4.0 * h / 6.0) * xc + (h / 6.0) * xr;
+        Qv[a][i] = (h / 6.0) * xli + (4.0 * h / 6.0) * xc + (h / 6.0) * xri;
+        R[a][i] = (2.0 * xc - xl - xr) / h;
+        S[a][i] = (2.0 * xc - xli - xri) / h;
+      }
+    }
+    auto add = [&](double amp, bool deriv, const std::vector<double> *const *tabs) {
+      DerivedTerm dt;
+      dt.time = to_dev_term(bt);
+      dt.time.amp = amp;
+      dt.time.deriv = deriv ? 1 : 0;
+      if (mass_only) {   // constant in time: the factor at t folded into amp
+        dt.time.amp = amp * time_value(bt.time, t);
+        dt.time.alpha = dt.time.omega = 0.0;
+        dt.time.phase = 0.0;
+        dt.time.p[0] = 1.0;
+        dt.time.p[1] = dt.time.p[2] = dt.time.p[3] = 0.0;
+      }
+      for (int a = 0; a < d; ++a) dt.table[a] = *tabs[a];
+      out.push_back(std::move(dt));
+    };
+    const std::vector<double> *tp[PE_MAX_DIM], *tq[PE_MAX_DIM];
+    for (int a = 0; a < d; ++a) {
+      tp[a] = &P[a];
+      tq[a] = &Qv[a];
+    }
+    // -M_IB g_B' (or -M_IB g_B(t) for the initial value)
+    add(-bt.amp, !mass_only, tp);
+    add(bt.amp, !mass_only, tq);
+    if (mass_only) continue;
+    // -D A_IB g_B
+    for (int a = 0; a < d; ++a) {
+      const std::vector<double> *tr[PE_MAX_DIM], *ts[PE_MAX_DIM];
+      for (int b = 0; b < d; ++b) {
+        tr[b] = b == a ? &R[b] : &P[b];
+        ts[b] = b == a ? &S[b] : &Qv[b];
+      }
+      add(-g->D * bt.amp, false, tr);
+      add(g->D * bt.amp, false, ts);
+    }
+  }
+}
+
+// The 1D tables of explicit-vector terms into rows row0.. of the per-axis
+// tables (stride np_a, zero beyond n_a).
+pe_status upload_derived(pe_grid g, const std::vector<DerivedTerm> &der, int row0, double **dst,
+                         hipStream_t st) {
+  for (int a = 0; a < g->dim; ++a) {
+    const Axis &ax = g->ax[a];
+    std::vector<double> rows(size_t(ax.np) * der.size(), 0.0);
+    for (size_t m = 0; m < der.size(); ++m)
+      for (int i = 0; i < ax.n; ++i) rows[m * ax.np + i] = der[m].table[a][i];
+    if (!rows.empty()) {
+      PE_HIP(hipMemcpyAsync(dst[a] + size_t(row0) * ax.np, rows.data(), sizeof(double) * rows.size(),
+                            hipMemcpyHostToDevice, st));
+      PE_HIP(hipStreamSynchronize(st));   // rows is host memory read by the copy
+    }
+  }
+  return PE_OK;
 }
 
 }  // namespace pe
@@ -516,13 +605,9 @@ pe_status pe_set_transform(pe_grid g, int32_t kind) {
   return PE_OK;
 }
 
-pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream) {
-  clear_error();
-  if (!g) return set_error(PE_E_ARG, "null grid");
-  if (n_terms < 0 || n_terms > PE_MAX_TERMS)
-    return set_error(PE_E_ARG, "n_terms must be 0..%d", PE_MAX_TERMS);
-  if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");
-  hipStream_t st = as_stream(stream);
+// The internal term list: the forcing (loads by the grid's Gauss rule)
+// followed by the derived terms of the Dirichlet data (explicit tables).
+static pe_status rebuild_terms(pe_grid g, hipStream_t st) {
   for (int a = 0; a < PE_MAX_DIM; ++a) {
     dev_free(g->d_C[a]);
     g->d_C[a] = nullptr;
@@ -533,15 +618,24 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
   g->d_terms = nullptr;
   dev_free(g->d_Cf);
   g->d_Cf = nullptr;
-  g->n_terms = n_terms;
+  std::vector<DerivedTerm> der;
+  boundary_terms(g, false, 0.0, der);
+  const int mf = int(g->src_forcing.size());
+  const int n_terms = mf + int(der.size());
+  g->n_terms = 0;
+  if (n_terms > PE_MAX_TERMS)
+    return set_error(PE_E_ARG, "%d forcing terms + %d from the boundary data exceed %d", mf,
+                     int(der.size()), PE_MAX_TERMS);
   if (n_terms == 0) return PE_OK;
-  for (int m = 0; m < n_terms; ++m) g->h_terms[m] = to_dev_term(terms[m]);
+  for (int m = 0; m < mf; ++m) g->h_terms[m] = to_dev_term(g->src_forcing[m]);
+  for (size_t m = 0; m < der.size(); ++m) g->h_terms[mf + m] = der[m].time;
   PE_HIP(hipMalloc(&g->d_terms, sizeof(DevTerm) * n_terms));
   PE_HIP(hipMemcpyAsync(g->d_terms, g->h_terms, sizeof(DevTerm) * n_terms, hipMemcpyHostToDevice,
                         st));
   for (int a = 0; a < g->dim; ++a)
     PE_HIP(hipMalloc(&g->d_C[a], sizeof(double) * size_t(n_terms) * g->ax[a].np));
-  PE_TRY(build_loads(g, n_terms, terms, g->d_C, st));
+  if (mf > 0) PE_TRY(build_loads(g, mf, g->src_forcing.data(), g->d_C, st));
+  PE_TRY(upload_derived(g, der, mf, g->d_C, st));
   const Axis &last = g->ax[g->dim - 1];
   PE_HIP(hipMalloc(&g->d_Cf, sizeof(double) * 2 * size_t(n_terms) * last.Kh));
   PE_TRY(fold_table(g, g->d_C[g->dim - 1], n_terms, g->d_Cf, st));
@@ -554,7 +648,35 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
     PE_HIP(hipGetLastError());
   }
   PE_HIP(hipStreamSynchronize(st));
+  g->n_terms = n_terms;
   return PE_OK;
+}
+
+pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream) {
+  clear_error();
+  if (!g) return set_error(PE_E_ARG, "null grid");
+  if (n_terms < 0 || n_terms > PE_MAX_TERMS)
+    return set_error(PE_E_ARG, "n_terms must be 0..%d", PE_MAX_TERMS);
+  if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");
+  if (n_terms + (2 + 2 * g->dim) * int(g->src_boundary.size()) > PE_MAX_TERMS)
+    return set_error(PE_E_ARG, "%d forcing terms + the boundary data's terms exceed %d", n_terms,
+                     PE_MAX_TERMS);
+  g->src_forcing.assign(terms, terms + n_terms);
+  return rebuild_terms(g, as_stream(stream));
+}
+
+pe_status pe_set_boundary(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream) {
+  clear_error();
+  if (!g) return set_error(PE_E_ARG, "null grid");
+  if (n_terms < 0 || n_terms > PE_MAX_TERMS)
+    return set_error(PE_E_ARG, "n_terms must be 0..%d", PE_MAX_TERMS);
+  if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");
+  const int per = 2 + 2 * g->dim;
+  if (int(g->src_forcing.size()) + per * n_terms > PE_MAX_TERMS)
+    return set_error(PE_E_ARG, "%d forcing terms + %d x %d from the boundary data exceed %d",
+                     int(g->src_forcing.size()), n_terms, per, PE_MAX_TERMS);
+  g->src_boundary.assign(terms, terms + n_terms);
+  return rebuild_terms(g, as_stream(stream));
 }
 
 pe_status pe_phi_tables(pe_grid g, double h, int32_t s, const double *c, double *d_E, double *d_B,

@@ -77,13 +77,41 @@ struct DevTerm {                 // a forcing term as the kernels read it
   double amp;
   double alpha, omega, phase;
   double p[4];
+  int deriv;                     // 1: the term carries tau'(t) instead of tau(t)
 };
 
-// amp tau(t): the time factor of a forcing term with its amplitude.
+// amp tau(t) (or amp tau'(t)): the time factor of a forcing term with its
+// amplitude; tau = e^{alpha t} cos(omega t + phase) P(t), P cubic.
 __device__ inline double term_time(const DevTerm &tm, double t) {
   const double poly = tm.p[0] + t * (tm.p[1] + t * (tm.p[2] + t * tm.p[3]));
-  return tm.amp * exp(tm.alpha * t) * cos(tm.omega * t + tm.phase) * poly;
+  if (!tm.deriv) return tm.amp * exp(tm.alpha * t) * cos(tm.omega * t + tm.phase) * poly;
+  const double arg = tm.omega * t + tm.phase;
+  const double dpoly = tm.p[1] + t * (2.0 * tm.p[2] + 3.0 * t * tm.p[3]);
+  return tm.amp * exp(tm.alpha * t) *
+         ((tm.alpha * cos(arg) - tm.omega * sin(arg)) * poly + cos(arg) * dpoly);
 }
+
+// Non-homogeneous Dirichlet data g (Sections 3 and 4 note the extension):
+// with g_h the Q1 interpolant of g on the boundary nodes, the interior load
+// gains -(M_IB g_B' + D A_IB g_B).  For a separable data term
+// amp tau(t) prod_a X_a, with xb_a the values of X_a at the n_a + 2 nodes of
+// axis a and (interior rows i, boundary entries kept / dropped)
+//   p_a = (Mbar xb_a)_I, q_a = M_II (xb_a)_I, r_a = (Abar xb_a)_I, s_a = A_II (xb_a)_I,
+// that load is the sum of 2 + 2d separable terms with explicit 1D tables:
+//   -amp tau' (x)p + amp tau' (x)q
+//   - D amp tau sum_a (x)_{b!=a} p_b x r_a + D amp tau sum_a (x)_{b!=a} q_b x s_a.
+struct DerivedTerm {
+  DevTerm time;                          // amplitude and time factor (tau or tau')
+  std::vector<double> table[PE_MAX_DIM]; // [n_a] 1D load per axis
+};
+constexpr int PE_BOUNDARY_EXPANSION_MAX = 2 + 2 * PE_MAX_DIM;   // terms per data term
+// the derived terms of the grid's data: all of them (mass_only = false), or
+// only the mass coupling at time t with the time factor folded into the
+// amplitude (mass_only = true: the initial-value correction -M_IB g_B(t))
+void boundary_terms(pe_grid g, bool mass_only, double t, std::vector<DerivedTerm> &out);
+// their tables into rows row0.. of per-axis tables [rows][np_a] (device)
+pe_status upload_derived(pe_grid g, const std::vector<DerivedTerm> &der, int row0, double **dst,
+                         hipStream_t st);
 
 }  // namespace pe
 
@@ -99,6 +127,9 @@ struct pe_grid_s {
   int n_terms = 0;
   pe::DevTerm h_terms[PE_MAX_TERMS];
   pe::DevTerm *d_terms = nullptr;        // [n_terms]
+  // the descriptors as given: forcing terms and Dirichlet data terms (the
+  // internal list is the forcing followed by the data's derived terms)
+  std::vector<pe_term> src_forcing, src_boundary;
   double *d_C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][np_a] 1D loads
   double *d_Cf = nullptr;        // [2][n_terms][Kh_last] folded last-axis loads
   // spec_a[m][k] = sig_a(k) (S_a^T C_a[m])_k: spectral 1D loads of each term

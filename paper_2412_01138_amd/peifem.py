@@ -32,8 +32,9 @@ PE_TRANSFORM_DENSE = 0
 PE_TRANSFORM_FFT = 1
 
 EXPORTS = [
-    "pe_init_grid", "pe_free_grid", "pe_set_transform", "pe_set_forcing", "pe_phi_tables",
-    "pe_project_workspace_bytes", "pe_project", "pe_fine_workspace_bytes",
+    "pe_init_grid", "pe_free_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+    "pe_phi_tables", "pe_project_workspace_bytes", "pe_project", "pe_project_state",
+    "pe_fine_workspace_bytes",
     "pe_fine_propagate", "pe_coarse_workspace_bytes", "pe_coarse_sweep",
     "pe_solve_workspace_bytes", "pe_parareal_solve", "pe_grid_dof",
     "pe_grid_precision", "pe_last_error", "pe_set_timing", "pe_get_timing",
@@ -108,6 +109,8 @@ def load_library():
     L.pe_free_grid.restype = None
     L.pe_set_transform.argtypes = [vp, i32]
     L.pe_set_forcing.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
+    L.pe_set_boundary.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
+    L.pe_project_state.argtypes = [vp, i32, ctypes.POINTER(Term), dbl, vp, vp, sz, vp]
     L.pe_phi_tables.argtypes = [vp, dbl, i32, dp, vp, vp, vp]
     L.pe_project_workspace_bytes.argtypes = [vp]
     L.pe_project_workspace_bytes.restype = sz
@@ -150,7 +153,8 @@ def load_library():
                                         vp, sz, vp]
     L.pe_last_error.argtypes = []
     L.pe_last_error.restype = ctypes.c_char_p
-    for name in ("pe_init_grid", "pe_set_transform", "pe_set_forcing", "pe_phi_tables", "pe_project",
+    for name in ("pe_init_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+                 "pe_project_state", "pe_phi_tables", "pe_project",
                  "pe_fine_propagate", "pe_coarse_sweep", "pe_parareal_solve", "pe_set_timing",
                  "pe_get_timing", "pe_mlp_create", "pe_mlp_get_params", "pe_mlp_set_params",
                  "pe_mlp_forward", "pe_mlp_train_step", "pe_learned_samples", "pe_learned_rows",
@@ -241,6 +245,8 @@ class Grid:
         g = cls(prob.n, prob.lo, prob.hi, prob.D, prob.precision, quad_q, device, stream,
                 transform)
         g.set_forcing(prob.forcing)
+        if getattr(prob, "boundary", None):
+            g.set_boundary(prob.boundary)
         return g
 
     def set_transform(self, kind: str):
@@ -286,6 +292,22 @@ class Grid:
     def set_forcing(self, terms):
         arr, m = to_c_terms(terms)
         _check(self.L.pe_set_forcing(self.h, m, arr, _stream(self.stream)))
+
+    def set_boundary(self, terms):
+        """Dirichlet data g (separable terms); [] for homogeneous data."""
+        arr, m = to_c_terms(terms)
+        _check(self.L.pe_set_boundary(self.h, m, arr, _stream(self.stream)))
+
+    def project_state(self, terms, t: float):
+        """Interior state whose boundary values are the Dirichlet data at t and
+        which is otherwise the L2 projection of `terms`."""
+        arr, m = to_c_terms(terms)
+        W = self.empty_states(1)[0]
+        nb = self.L.pe_project_workspace_bytes(self.h)
+        work = self.workspace(nb)
+        _check(self.L.pe_project_state(self.h, m, arr, float(t), _ptr(W), _ptr(work), nb,
+                                       _stream(self.stream)))
+        return W
 
     def phi_tables(self, h: float, c: Sequence[float]):
         import torch
@@ -464,7 +486,10 @@ def solve_problem(prob, K_max: Optional[int] = None, tol: Optional[float] = None
                   transform: str = "dense"):
     """Grid + forcing + P_h u0 + Algorithm 1 for a workloads.Problem."""
     g = Grid.from_problem(prob, device=device, transform=transform)
-    U0 = g.project(prob.u0) if prob.u0 else None
+    if getattr(prob, "boundary", None):
+        U0 = g.project_state(prob.u0, prob.t0)
+    else:
+        U0 = g.project(prob.u0) if prob.u0 else None
     P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
                        prob.K_max if K_max is None else K_max, prob.tol if tol is None else tol, corr,
                        mlp)
