@@ -248,6 +248,45 @@ def fft_transform(prob, U_dense, repeats: int):
     return out
 
 
+def dirichlet_data(prob, repeats: int):
+    """The bench solve with non-homogeneous Dirichlet data (two time-dependent
+    separable data terms, pe_set_boundary): wall time per solve and fine-pass
+    rate, beside the homogeneous solve."""
+    import torch
+    import workloads as wl
+    from paper_2412_01138_amd import peifem
+
+    P = wl.poly_factor
+    data = [wl.Term(0.7, wl.TimeFactor(omega=2.0, phase=0.3),
+                    (P(1.0, 0.5, -0.2), wl.SpaceFactor(kappa=1.3, phase=0.4))),
+            wl.Term(-0.4, wl.TimeFactor(alpha=-0.5, poly=(1.0, 0.3, 0.0, 0.0)),
+                    (wl.SpaceFactor(kappa=2.1, phase=0.2), P(0.3, 1.0)))]
+    pb = prob.with_(boundary=data)
+    g = peifem.Grid.from_problem(pb)
+    U0 = g.project_state(pb.u0, pb.t0)
+    P_ = g.solve_params(pb.t0, pb.T, pb.N, pb.J, pb.c_coarse, pb.c_fine, pb.K_max, pb.tol)
+    work = g.workspace(g.solve_workspace_bytes(P_))
+    U = g.empty_states(pb.N + 1)
+    g.parareal_solve(P_, U0=U0, U=U, work=work)
+    torch.cuda.synchronize()
+    reports = []
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        _, rep = g.parareal_solve(P_, U0=U0, U=U, work=work)
+        reports.append(rep)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / repeats
+    iters = reports[-1].iterations
+    fine_updates = pb.dof * pb.N * pb.J * pb.q
+    fine_ms = sum(r.ms_fine for r in reports) / len(reports) / max(iters, 1)
+    out = {"data_terms": len(data), "forcing_terms_total": len(pb.forcing) + len(data) * 6,
+           "ms_per_solve": ms, "iterations": iters, "converged": bool(reports[-1].converged),
+           "fine_updates_per_s": iters * fine_updates / (ms / 1e3), "ms_fine_per_pass": fine_ms}
+    del work, U, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +431,8 @@ def main():
         torch.cuda.synchronize()
     if not args.no_fft:
         out["fft_transform"] = fft_transform(prob, U, max(args.steps, 3))
+    if not args.no_fft:
+        out["dirichlet_data"] = dirichlet_data(prob, max(args.steps, 3))
     if not args.no_learned:
         out["learned_vs_plain_G"] = learned_vs_plain(args.learned_forcings, args.learned_steps)
     if not args.no_3d:

@@ -32,7 +32,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int KB = 16;
 constexpr int NT = 256;
-constexpr int GEN_MAX_TERMS = 16;
+constexpr int GEN_MAX_TERMS = 32;
 constexpr int GEN_MAX_CF = 4096;   // doubles of one folded half table kept in LDS
 
 template <int BM, int BN>
@@ -1139,8 +1139,10 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
             PE_TRY(launch_last2<8>(a, st));
           else if (gen->M <= 12)
             PE_TRY(launch_last2<12>(a, st));
-          else
+          else if (gen->M <= 16)
             PE_TRY(launch_last2<16>(a, st));
+          else
+            PE_TRY(launch_last2<32>(a, st));
         } else {
           PE_TRY(launch_last2<0>(a, st));
         }
@@ -1152,8 +1154,10 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
           PE_TRY(launch_last<8>(a, st));
         else if (gen->M <= 12)
           PE_TRY(launch_last<12>(a, st));
-        else
+        else if (gen->M <= 16)
           PE_TRY(launch_last<16>(a, st));
+        else
+          PE_TRY(launch_last<32>(a, st));
       } else {
         PE_TRY(launch_last<0>(a, st));
       }

@@ -123,3 +123,22 @@ def test_boundary_term_limits():
     # the grid keeps its data: the projection still matches the oracle
     W = g.project_state(prob.u0, prob.t0).cpu().numpy()
     assert rel(W, Discretization(prob).initial()) <= 1e-13
+
+
+def test_boundary_fullsize_first_slices():
+    """The 255x255 workload with Dirichlet data, at full size in the default
+    batching: the converged Parareal answer at T_1 and T_2 against the
+    oracle's sequential fine solution of the first two slices (after one
+    fine pass the Parareal iterate is the fine solution)."""
+    pe = _pe()
+    prob = wl.config(2).with_(boundary=_data(2))
+    print(f"boundary full size: {prob.name}, dof {prob.dof}", flush=True)
+    g, U, rep = pe.solve_problem(prob)
+    assert rep.converged
+    d = Discretization(prob)
+    tab = d.tables(prob.dt, prob.c_fine)
+    W, kept = sequential(d, d.initial(), prob.t0, tab, 2 * prob.J, keep_every=prob.J)
+    got = U[:3].cpu().numpy()
+    err = rel(got, np.stack(kept))
+    print(f"  iterations {rep.iterations}, relative L2 error on slices 0..2: {err:.3e}")
+    assert err <= 1e-11

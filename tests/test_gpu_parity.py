@@ -123,7 +123,7 @@ def test_fine_propagate_many_terms(dim, n):
     """More forcing terms than the fused quadrature path takes: the load
     vectors are written by the separate quadrature kernel instead."""
     pe = _peifem()
-    prob, d, Uin = _fine_case(dim, n, 2, 3, 3, seed=7, n_modes=20)
+    prob, d, Uin = _fine_case(dim, n, 2, 3, 3, seed=7, n_modes=40)
     g = pe.Grid.from_problem(prob)
     E, B = g.phi_tables(prob.dt, prob.c_fine)
     out = g.fine_propagate(_dev(Uin), prob.t0, prob.dT, prob.J, prob.c_fine, E, B).cpu().numpy()
