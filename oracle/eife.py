@@ -18,7 +18,7 @@ import numpy as np
 from . import phi
 from .boundary import FullGrid
 from .fem import Grid, gauss_legendre_01
-from .forcing import load_field, eval_terms, space_factor, time_factor
+from .forcing import load_field, load_moving, eval_terms, space_factor, time_factor
 
 
 @dataclass
@@ -50,6 +50,8 @@ class Discretization:
     def spectral_forcing(self, t: float) -> np.ndarray:
         """Coefficients of P_h f(t): Q^T F(t) (with the boundary coupling)."""
         F = load_field(self.grid, self.prob.forcing, t, self.q)
+        if getattr(self.prob, "moving", None):
+            F = F + load_moving(self.grid, self.prob.moving, t, self.q)
         if self.full is not None:
             F = F + self.full.load_correction(t)
         return self.grid.to_spectral(F)

@@ -74,6 +74,46 @@ def load_1d(sf, n: int, lo: float, hi: float, q: int) -> np.ndarray:
     return C
 
 
+def hat_center(hat, t: float) -> float:
+    return hat.c0 + hat.c1 * math.sin(hat.omega * t + hat.phase)
+
+
+def hat_load_1d(hat, t: float, n: int, lo: float, hi: float, q: int) -> np.ndarray:
+    """C_j = int max(1 - |x - c(t)| / w, 0) phi_j(x) dx by the q-point Gauss
+    rule on the two elements touching node j (the rule of every other load,
+    reading R2; the hat's kinks fall inside elements and are not treated
+    specially)."""
+    h = (hi - lo) / (n + 1)
+    xg, wg = gauss_legendre_01(q)
+    c = hat_center(hat, t)
+    e = np.arange(n + 1)[:, None]
+    x = lo + h * (e + xg[None, :])
+    X = np.maximum(1.0 - np.abs(x - c) / hat.width, 0.0)
+    left = h * np.sum(wg * X * (1.0 - xg), axis=1)
+    right = h * np.sum(wg * X * xg, axis=1)
+    C = np.zeros(n)
+    C += left[1:]
+    C += right[:-1]
+    return C
+
+
+def load_moving(grid: Grid, hats, t: float, q: int = 3) -> np.ndarray:
+    """Nodal load of moving hat sources: per source, the hat's 1D load along
+    its axis times the other axes' factor loads, times amp tau(t)."""
+    F = np.zeros(grid.n)
+    for hat in hats:
+        v = hat.amp * time_factor(hat.time, t)
+        prod = np.ones(())
+        for a, ax in enumerate(grid.axes):
+            if a == hat.axis:
+                vec = hat_load_1d(hat, t, ax.n, ax.lo, ax.hi, q)
+            else:
+                vec = load_1d(hat.space[a], ax.n, ax.lo, ax.hi, q)
+            prod = np.multiply.outer(prod, vec)
+        F = F + v * prod
+    return F
+
+
 def load_field(grid: Grid, terms, t: float, q: int = 3, use_time: bool = True) -> np.ndarray:
     """Nodal load vector F(t) of a separable function, shape grid.n."""
     F = np.zeros(grid.n)

@@ -60,6 +60,22 @@ class Term:
     space: Tuple[SpaceFactor, ...]
 
 
+@dataclass(frozen=True)
+class MovingHat:
+    """A moving hat source amp tau(t) max(1 - |x_axis - c(t)| / width, 0)
+    prod_{b != axis} X_b(x_b), c(t) = c0 + c1 sin(omega t + phase) (the
+    oscillating source of the paper's Example 5.4).  space[axis] is unused."""
+    amp: float
+    axis: int
+    width: float
+    c0: float
+    c1: float = 0.0
+    omega: float = 0.0
+    phase: float = 0.0
+    time: TimeFactor = TimeFactor()
+    space: Tuple[SpaceFactor, ...] = ()
+
+
 def sine_factor(k: int, lo: float, hi: float) -> SpaceFactor:
     """sin(k*pi*(x - lo)/(hi - lo)): the k-th Dirichlet sine on [lo, hi]."""
     kappa = k * PI / (hi - lo)
@@ -95,6 +111,8 @@ class Problem:
     # Dirichlet data u = g on the boundary (separable terms with time
     # factors); empty: homogeneous data
     boundary: List[Term] = field(default_factory=list)
+    # moving hat sources added to the forcing (not separable in t and x)
+    moving: List[MovingHat] = field(default_factory=list)
 
     @property
     def q(self) -> int:
@@ -245,6 +263,22 @@ def example_5_2(nx: int, ny: int, N: int, M: int, s_fine: int, s_coarse: Optiona
                    0.0, 0.6, f, [Term(1.0, TimeFactor(), (sx, sy))], N, M,
                    uniform_nodes(s_fine), uniform_nodes(sc), "fp64", 64, 0.0,
                    exact=[Term(1.0, decay, (sx, sy))])
+
+
+def example_5_4(alpha: float, freq: float, n_elems: int = 1024, N: int = 4, M: int = 16,
+                s_fine: int = 2, s_coarse: Optional[int] = None) -> Problem:
+    """1D oscillating source on [0, 1], T = 1: u_t = alpha u_xx + g, u0 =
+    4x(1 - x), homogeneous Dirichlet data, g a hat of half-width w = 0.05 and
+    height 100 sqrt(alpha) centred at c(t) = 0.5 + (0.5 - w) sin(2 pi f t);
+    N x M = 4 x 16, N_x = 1024 elements, iterated 4 times (the paper shows
+    figures only)."""
+    sc = s_fine if s_coarse is None else s_coarse
+    w = 0.05
+    hat = MovingHat(100.0 * math.sqrt(alpha), 0, w, 0.5, 0.5 - w, 2.0 * PI * freq, 0.0,
+                    TimeFactor(), (SpaceFactor(),))
+    return Problem(f"ex5.4-a{alpha:g}-f{freq:g}", 1, (n_elems - 1,), (0.0,), (1.0,), alpha, 0.0,
+                   1.0, [], [Term(1.0, TimeFactor(), (poly_factor(0.0, 4.0, -4.0),))], N, M,
+                   uniform_nodes(s_fine), uniform_nodes(sc), "fp64", 4, 0.0, moving=[hat])
 
 
 def example_5_3(nx: int, N: int, M: int, s_fine: int, s_coarse: Optional[int] = None) -> Problem:
