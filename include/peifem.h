@@ -82,6 +82,22 @@ typedef struct {
   pe_space_factor space[PE_MAX_DIM];
 } pe_term;
 
+/* A moving hat source (the oscillating source of the paper's Example 5.4,
+ * not separable in t and x):
+ *     amp tau(t) max(1 - |x_axis - c(t)| / width, 0) prod_{b != axis} X_b(x_b),
+ *     c(t) = c0 + c1 sin(omega t + phase),
+ * tau and X_b as in pe_term (space[axis] is ignored). */
+typedef struct {
+  double amp;
+  int32_t axis;
+  double width;
+  double c0, c1, omega, phase;
+  pe_time_factor time;
+  pe_space_factor space[PE_MAX_DIM];
+} pe_moving_hat;
+
+#define PE_MAX_MOVING 16
+
 /* --------------------------------------------------------------------- */
 
 /* Build a grid: n[a] interior Q1 nodes on [lo[a], hi[a]] (n[a] + 1 elements
@@ -143,6 +159,18 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
  * plus (2 + 2d) n_terms exceed PE_MAX_TERMS or for null terms (the grid keeps
  * its previous data).  Synchronises `stream`. */
 pe_status pe_set_boundary(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream);
+
+/* Moving hat sources (0..PE_MAX_MOVING; host array) added to the forcing of
+ * every call that evaluates it (pe_fine_propagate, pe_coarse_sweep's r_n,
+ * pe_parareal_solve).  Their load is the grid's q-point Gauss rule on every
+ * element, like every other load (the hat's kinks fall inside elements and
+ * are not treated apart); the load field is written by a quadrature kernel
+ * and transformed by the non-generating passes.  The learned calls reject a
+ * grid with moving sources (their inputs are the separable forcing's).
+ * Errors: PE_E_ARG (count, axis outside the grid, width <= 0, non-finite
+ * parameters; the grid keeps its previous sources), PE_E_HIP.  Synchronises
+ * `stream`. */
+pe_status pe_set_moving_sources(pe_grid g, int32_t n, const pe_moving_hat *src, void *stream);
 
 /* Exponential Runge-Kutta tables for step h > 0 and s (1..PE_MAX_STAGES)
  * distinct nodes c[0..s-1] in [0, 1] (host):

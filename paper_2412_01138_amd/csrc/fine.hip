@@ -88,6 +88,67 @@ __global__ void k_load_fields(Dims D, const double *__restrict__ C0, const doubl
   }
 }
 
+// Moving hat sources (Example 5.4) added to the load fields of a batch: for
+// field f at time t_f and node j,
+//   sum_s amp_s tau_s(t_f) H_s(t_f)[j_axis] prod_{b != axis} Chat_b[s][j_b],
+// H_s(t)[j] the q-point Gauss rule of max(1 - |x - c_s(t)| / w_s, 0) phi_j(x)
+// on the two elements of node j (as the 1D loads of the separable terms).
+struct HatGeom {
+  double lo[PE_MAX_DIM], h[PE_MAX_DIM];
+};
+
+__device__ inline double hat_load(const DevHat &hs, double t, int j, double lo, double h,
+                                  const GaussRule &rule) {
+  const double c = hs.c0 + hs.c1 * sin(hs.omega * t + hs.phase);
+  double acc = 0.0;
+  for (int gq = 0; gq < rule.q; ++gq) {
+    const double xi = rule.x[gq];
+    const double xl = lo + h * (double(j) + xi);
+    const double xr = lo + h * (double(j + 1) + xi);
+    const double Xl = fmax(1.0 - fabs(xl - c) / hs.width, 0.0);
+    const double Xr = fmax(1.0 - fabs(xr - c) / hs.width, 0.0);
+    acc += rule.w[gq] * (Xl * xi + Xr * (1.0 - xi));
+  }
+  return acc * h;
+}
+
+template <typename TG>
+__global__ void k_add_hats(Dims D, FieldBatch b, HatGeom geo, GaussRule rule,
+                           const DevHat *__restrict__ hats, int nh, const double *__restrict__ C0,
+                           const double *__restrict__ C1, const double *__restrict__ C2,
+                           TG *__restrict__ out, int64_t dofp, int64_t total) {
+  const double *C[3] = {C0, C1, C2};
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t f = idx / dofp;
+    int64_t r = idx - f * dofp;
+    int j[3] = {0, 0, 0};
+    for (int a = D.d - 1; a >= 0; --a) {
+      j[a] = int(r % D.np[a]);
+      r /= D.np[a];
+    }
+    bool inside = true;
+    for (int a = 0; a < D.d; ++a) inside = inside && (j[a] < D.n[a]);
+    if (!inside) continue;
+    const int64_t per_slice = int64_t(b.jc) * b.s;
+    const int n = b.n0 + int(f / per_slice);
+    const int rem = int(f - (f / per_slice) * per_slice);
+    const int js = b.j0 + rem / b.s;
+    const int i = rem - (rem / b.s) * b.s;
+    const double t = ((b.t0 + double(n) * b.dT) + double(js) * b.dt) + b.c[i] * b.dt;
+    double v = 0.0;
+    for (int s = 0; s < nh; ++s) {
+      const DevHat &hs = hats[s];
+      double prod = term_time(hs.time, t);
+      for (int a = 0; a < D.d; ++a)
+        prod *= a == hs.axis ? hat_load(hs, t, j[a], geo.lo[a], geo.h[a], rule)
+                             : C[a][int64_t(s) * D.np[a] + j[a]];
+      v += prod;
+    }
+    out[idx] = TG(double(out[idx]) + v);
+  }
+}
+
 // The fused diagonal update of eq. (2.6) over the jc steps of a batch, for
 // every slice and every (unpadded) coefficient k:
 //     V <- E_k V + sum_i B_ik sigma_k G[f(n, j, i)][p(k)]
@@ -235,8 +296,11 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
   int64_t nc = count * g->n_terms;
   k_time_coefs<<<blocks_for(nc), 256, 0, st>>>(b, g->d_terms, g->n_terms, coef, count);
   PE_HIP(hipGetLastError());
-  const bool fused = g->precision == PE_FP64 ? gen_supported(g, g->n_terms)
-                                              : gen_supported_split(g, g->n_terms);
+  // moving sources are not separable in t and x: their loads go into
+  // written fields, which the non-generating passes transform
+  const bool hats = g->n_hats > 0;
+  const bool fused = !hats && (g->precision == PE_FP64 ? gen_supported(g, g->n_terms)
+                                                       : gen_supported_split(g, g->n_terms));
   if (fused) {
     // quadrature fused into the first transform pass
     GenSrc gs;
@@ -249,6 +313,25 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
     return transform(g, count, &gs, work0, work1, result, st, stop_axis);
   }
   PE_TRY(launch_load(g, g->d_C, g->n_terms, coef, work0, count, st));
+  if (hats) {
+    Dims D = dims_of(g);
+    HatGeom geo{};
+    for (int a = 0; a < g->dim; ++a) {
+      geo.lo[a] = g->ax[a].lo;
+      geo.h[a] = g->ax[a].h;
+    }
+    const GaussRule rule = gauss_rule(g->quad_q);
+    const int64_t total = count * g->dofp;
+    if (g->precision == PE_FP64)
+      k_add_hats<double><<<blocks_for(total), 256, 0, st>>>(
+          D, b, geo, rule, g->d_hats, g->n_hats, g->d_Chat[0], g->d_Chat[1], g->d_Chat[2],
+          static_cast<double *>(work0), g->dofp, total);
+    else
+      k_add_hats<float><<<blocks_for(total), 256, 0, st>>>(
+          D, b, geo, rule, g->d_hats, g->n_hats, g->d_Chat[0], g->d_Chat[1], g->d_Chat[2],
+          static_cast<float *>(work0), g->dofp, total);
+    PE_HIP(hipGetLastError());
+  }
   return transform(g, count, nullptr, work0, work1, result, st, stop_axis);
 }
 
@@ -265,7 +348,7 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
   const bool fp64 = g->precision == PE_FP64;
   const size_t sbytes = fp64 ? sizeof(double) : sizeof(float);
   Dims D = dims_of(g);
-  if (g->n_terms == 0) {
+  if (g->n_terms == 0 && g->n_hats == 0) {
     // no forcing: pure decay, J steps at once
     int64_t tot = int64_t(N) * dof;
     if (fp64)

@@ -155,11 +155,6 @@ __global__ void k_fold_table(const double *C, int np, int n, int H, int Kh, int 
   Cf[(size_t(n_terms) + m) * Kh + p] = v;
 }
 
-struct GaussRule {
-  int q;
-  double x[8], w[8];   // nodes / weights on [0, 1]
-};
-
 // C[m][j] = int X_m(x) phi_j(x) dx, j = 0..np-1 (zero for j >= n), by the
 // q-point Gauss rule on the two elements around interior node j (global
 // node j + 1): element [x_j, x_{j+1}] carries the hat as xi, element
@@ -247,7 +242,7 @@ __global__ void k_phi_tables(int dim, int n0, int n1, int n2, const double *lam0
 // ------------------------------------------------------------ host helpers
 
 // Gauss-Legendre nodes/weights on [0, 1] by Newton's method on P_q.
-static GaussRule gauss_rule(int q) {
+GaussRule gauss_rule(int q) {
   GaussRule r{};
   r.q = q;
   for (int i = 0; i < q; ++i) {
@@ -313,9 +308,11 @@ static void free_grid_tables(pe_grid g) {
     dev_free(g->ax[a].d_tw);
     dev_free(g->d_C[a]);
     dev_free(g->d_spec[a]);
+    dev_free(g->d_Chat[a]);
   }
   dev_free(g->d_terms);
   dev_free(g->d_Cf);
+  dev_free(g->d_hats);
 }
 
 pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst, hipStream_t st) {
@@ -663,6 +660,55 @@ pe_status pe_set_forcing(pe_grid g, int32_t n_terms, const pe_term *terms, void 
                      PE_MAX_TERMS);
   g->src_forcing.assign(terms, terms + n_terms);
   return rebuild_terms(g, as_stream(stream));
+}
+
+pe_status pe_set_moving_sources(pe_grid g, int32_t n, const pe_moving_hat *src, void *stream) {
+  clear_error();
+  if (!g) return set_error(PE_E_ARG, "null grid");
+  if (n < 0 || n > PE_MAX_MOVING) return set_error(PE_E_ARG, "n must be 0..%d", PE_MAX_MOVING);
+  if (n > 0 && !src) return set_error(PE_E_ARG, "null sources");
+  for (int i = 0; i < n; ++i) {
+    const pe_moving_hat &h = src[i];
+    if (h.axis < 0 || h.axis >= g->dim) return set_error(PE_E_ARG, "source %d: bad axis", i);
+    if (!(h.width > 0) || !std::isfinite(h.width) || !std::isfinite(h.amp) ||
+        !std::isfinite(h.c0) || !std::isfinite(h.c1) || !std::isfinite(h.omega) ||
+        !std::isfinite(h.phase))
+      return set_error(PE_E_ARG, "source %d: bad parameters", i);
+  }
+  hipStream_t st = as_stream(stream);
+  for (int a = 0; a < PE_MAX_DIM; ++a) {
+    dev_free(g->d_Chat[a]);
+    g->d_Chat[a] = nullptr;
+  }
+  dev_free(g->d_hats);
+  g->d_hats = nullptr;
+  g->n_hats = 0;
+  g->src_moving.assign(src, src + n);
+  if (n == 0) return PE_OK;
+  std::vector<DevHat> dh(n);
+  std::vector<pe_term> factors(n);
+  for (int i = 0; i < n; ++i) {
+    const pe_moving_hat &h = src[i];
+    pe_term tm{};
+    tm.amp = h.amp;
+    tm.time = h.time;
+    for (int a = 0; a < PE_MAX_DIM; ++a) tm.space[a] = h.space[a];
+    factors[i] = tm;
+    dh[i].time = to_dev_term(tm);
+    dh[i].width = h.width;
+    dh[i].c0 = h.c0;
+    dh[i].c1 = h.c1;
+    dh[i].omega = h.omega;
+    dh[i].phase = h.phase;
+    dh[i].axis = h.axis;
+  }
+  PE_HIP(hipMalloc(&g->d_hats, sizeof(DevHat) * n));
+  PE_HIP(hipMemcpyAsync(g->d_hats, dh.data(), sizeof(DevHat) * n, hipMemcpyHostToDevice, st));
+  for (int a = 0; a < g->dim; ++a)
+    PE_HIP(hipMalloc(&g->d_Chat[a], sizeof(double) * size_t(n) * g->ax[a].np));
+  PE_TRY(build_loads(g, n, factors.data(), g->d_Chat, st));   // synchronises
+  g->n_hats = n;
+  return PE_OK;
 }
 
 pe_status pe_set_boundary(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream) {

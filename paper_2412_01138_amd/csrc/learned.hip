@@ -273,6 +273,7 @@ pe_status pe_learned_samples(pe_grid g, int32_t n_slices, double t0, double dT, 
   clear_error();
   if (!g || !d_samples) return set_error(PE_E_ARG, "null argument");
   if (n_slices < 1 || !(dT > 0)) return set_error(PE_E_ARG, "bad n_slices / dT");
+  if (g->n_hats > 0) return set_error(PE_E_ARG, "the learned inputs do not cover moving sources");
   hipStream_t st = as_stream(stream);
   const size_t sb = g->precision == PE_FP64 ? sizeof(double) : sizeof(float);
   if (g->n_terms == 0) {
@@ -336,6 +337,7 @@ pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double t0, double dT, con
     return set_error(PE_E_ARG, "null argument");
   if (n_slices < 1 || !(dT > 0) || max_rows < 0 || !(rel_thresh >= 0) || !std::isfinite(t0))
     return set_error(PE_E_ARG, "bad arguments");
+  if (g->n_hats > 0) return set_error(PE_E_ARG, "the learned inputs do not cover moving sources");
   if (work_bytes < pe_learned_rows_workspace_bytes(g, n_slices))
     return set_error(PE_E_WORKSPACE, "workspace too small");
   hipStream_t st = as_stream(stream);

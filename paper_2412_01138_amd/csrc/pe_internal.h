@@ -67,6 +67,13 @@ struct Axis {
   double *d_tw = nullptr;        // [N][2]
 };
 
+// q-point Gauss-Legendre rule on [0, 1]
+struct GaussRule {
+  int q;
+  double x[8], w[8];
+};
+GaussRule gauss_rule(int q);
+
 struct PendingTiming {
   hipEvent_t start, stop;
   int cls;
@@ -90,6 +97,13 @@ __device__ inline double term_time(const DevTerm &tm, double t) {
   return tm.amp * exp(tm.alpha * t) *
          ((tm.alpha * cos(arg) - tm.omega * sin(arg)) * poly + cos(arg) * dpoly);
 }
+
+// a moving hat source as the kernels read it
+struct DevHat {
+  DevTerm time;                  // amp tau(t)
+  double width, c0, c1, omega, phase;
+  int axis;
+};
 
 // Non-homogeneous Dirichlet data g (Sections 3 and 4 note the extension):
 // with g_h the Q1 interpolant of g on the boundary nodes, the interior load
@@ -130,6 +144,12 @@ struct pe_grid_s {
   // the descriptors as given: forcing terms and Dirichlet data terms (the
   // internal list is the forcing followed by the data's derived terms)
   std::vector<pe_term> src_forcing, src_boundary;
+  // moving hat sources: descriptors, device copies, the other axes' factor
+  // loads [n_hats][np_a]
+  std::vector<pe_moving_hat> src_moving;
+  int n_hats = 0;
+  pe::DevHat *d_hats = nullptr;
+  double *d_Chat[PE_MAX_DIM] = {nullptr, nullptr, nullptr};
   double *d_C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][np_a] 1D loads
   double *d_Cf = nullptr;        // [2][n_terms][Kh_last] folded last-axis loads
   // spec_a[m][k] = sig_a(k) (S_a^T C_a[m])_k: spectral 1D loads of each term

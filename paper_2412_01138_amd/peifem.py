@@ -33,6 +33,7 @@ PE_TRANSFORM_FFT = 1
 
 EXPORTS = [
     "pe_init_grid", "pe_free_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+    "pe_set_moving_sources",
     "pe_phi_tables", "pe_project_workspace_bytes", "pe_project", "pe_project_state",
     "pe_fine_workspace_bytes",
     "pe_fine_propagate", "pe_coarse_workspace_bytes", "pe_coarse_sweep",
@@ -67,6 +68,13 @@ class TimeFactor(ctypes.Structure):
 
 class Term(ctypes.Structure):
     _fields_ = [("amp", ctypes.c_double), ("time", TimeFactor),
+                ("space", SpaceFactor * PE_MAX_DIM)]
+
+
+class MovingHat(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("axis", ctypes.c_int32), ("width", ctypes.c_double),
+                ("c0", ctypes.c_double), ("c1", ctypes.c_double), ("omega", ctypes.c_double),
+                ("phase", ctypes.c_double), ("time", TimeFactor),
                 ("space", SpaceFactor * PE_MAX_DIM)]
 
 
@@ -110,6 +118,7 @@ def load_library():
     L.pe_set_transform.argtypes = [vp, i32]
     L.pe_set_forcing.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
     L.pe_set_boundary.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
+    L.pe_set_moving_sources.argtypes = [vp, i32, ctypes.POINTER(MovingHat), vp]
     L.pe_project_state.argtypes = [vp, i32, ctypes.POINTER(Term), dbl, vp, vp, sz, vp]
     L.pe_phi_tables.argtypes = [vp, dbl, i32, dp, vp, vp, vp]
     L.pe_project_workspace_bytes.argtypes = [vp]
@@ -154,6 +163,7 @@ def load_library():
     L.pe_last_error.argtypes = []
     L.pe_last_error.restype = ctypes.c_char_p
     for name in ("pe_init_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+                 "pe_set_moving_sources",
                  "pe_project_state", "pe_phi_tables", "pe_project",
                  "pe_fine_propagate", "pe_coarse_sweep", "pe_parareal_solve", "pe_set_timing",
                  "pe_get_timing", "pe_mlp_create", "pe_mlp_get_params", "pe_mlp_set_params",
@@ -247,6 +257,8 @@ class Grid:
         g.set_forcing(prob.forcing)
         if getattr(prob, "boundary", None):
             g.set_boundary(prob.boundary)
+        if getattr(prob, "moving", None):
+            g.set_moving_sources(prob.moving)
         return g
 
     def set_transform(self, kind: str):
@@ -292,6 +304,25 @@ class Grid:
     def set_forcing(self, terms):
         arr, m = to_c_terms(terms)
         _check(self.L.pe_set_forcing(self.h, m, arr, _stream(self.stream)))
+
+    def set_moving_sources(self, hats):
+        """Moving hat sources (objects with the workloads.MovingHat fields)."""
+        hats = list(hats)
+        arr = (MovingHat * max(1, len(hats)))()
+        for i, h in enumerate(hats):
+            arr[i].amp, arr[i].axis, arr[i].width = h.amp, h.axis, h.width
+            arr[i].c0, arr[i].c1, arr[i].omega, arr[i].phase = h.c0, h.c1, h.omega, h.phase
+            tf = h.time
+            arr[i].time.alpha, arr[i].time.omega, arr[i].time.phase = tf.alpha, tf.omega, tf.phase
+            for j in range(4):
+                arr[i].time.poly[j] = tf.poly[j]
+            for a in range(PE_MAX_DIM):
+                sf = h.space[a] if a < len(h.space) else None
+                arr[i].space[a].kappa = sf.kappa if sf else 0.0
+                arr[i].space[a].phase = sf.phase if sf else math.pi / 2
+                for j in range(3):
+                    arr[i].space[a].poly[j] = sf.poly[j] if sf else (1.0 if j == 0 else 0.0)
+        _check(self.L.pe_set_moving_sources(self.h, len(hats), arr, _stream(self.stream)))
 
     def set_boundary(self, terms):
         """Dirichlet data g (separable terms); [] for homogeneous data."""
