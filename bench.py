@@ -287,6 +287,38 @@ def dirichlet_data(prob, repeats: int):
     return out
 
 
+def example_5_4_runs(repeats: int = 3):
+    """The paper's Example 5.4 (1D oscillating hat source, N_x = 1024, N x M =
+    4 x 16, 4 Parareal iterations) for its three settings: wall time per solve
+    (median of `repeats`) and the final jump."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2412_01138_amd import peifem
+
+    out = {}
+    for alpha, freq, sc, sf in ((0.01, 1.0, 2, 2), (0.01, 10.0, 2, 3), (0.1, 10.0, 3, 3)):
+        prob = wl.example_5_4(alpha, freq, s_fine=sf, s_coarse=sc)
+        g = peifem.Grid.from_problem(prob)
+        U0 = g.project(prob.u0)
+        P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine, 4, 0.0)
+        work = g.workspace(g.solve_workspace_bytes(P))
+        U = g.empty_states(prob.N + 1)
+        g.parareal_solve(P, U0=U0, U=U, work=work)
+        times = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = g.parareal_solve(P, U0=U0, U=U, work=work)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        out[f"PEIFE-linear{sc}{sf}, alpha={alpha:g}, f={freq:g}"] = {
+            "ms_per_solve": float(np.median(times)), "iterations": rep.iterations,
+            "jumps": [rep.jumps[i] for i in range(rep.iterations)]}
+        del work, U, g
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -433,6 +465,7 @@ def main():
         out["fft_transform"] = fft_transform(prob, U, max(args.steps, 3))
     if not args.no_fft:
         out["dirichlet_data"] = dirichlet_data(prob, max(args.steps, 3))
+        out["example_5_4"] = example_5_4_runs()
     if not args.no_learned:
         out["learned_vs_plain_G"] = learned_vs_plain(args.learned_forcings, args.learned_steps)
     if not args.no_3d:
