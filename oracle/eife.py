@@ -34,7 +34,10 @@ class Discretization:
 
     def __init__(self, prob, q: int = 3):
         self.prob = prob
-        self.grid = Grid(prob.n, prob.lo, prob.hi)
+        self.grid = Grid(prob.n, prob.lo, prob.hi, getattr(prob, "periodic", None))
+        if any(self.grid.periodic):
+            assert not getattr(prob, "boundary", None) and not getattr(prob, "moving", None), \
+                "Dirichlet data and moving sources are for non-periodic axes"
         self.D = float(prob.D)
         self.q = q
         self.lam = self.grid.eigenvalues()

@@ -55,6 +55,25 @@ def axis_matrices(n: int, lo: float, hi: float):
     return M, A
 
 
+def periodic_axis_matrices(n: int, lo: float, hi: float):
+    """Mass and stiffness of the n hats of a periodic axis (node j at
+    lo + j h, h = (hi - lo)/n; element e joins nodes e and e + 1 mod n),
+    assembled element by element."""
+    h = (hi - lo) / n
+    xg, wg = gauss_legendre_01(2)
+    shape = [1.0 - xg, xg]
+    dshape = [-1.0 / h, 1.0 / h]
+    M = np.zeros((n, n))
+    A = np.zeros((n, n))
+    for e in range(n):
+        gl = (e, (e + 1) % n)
+        for a in range(2):
+            for b in range(2):
+                M[gl[a], gl[b]] += h * float(np.sum(wg * shape[a] * shape[b]))
+                A[gl[a], gl[b]] += h * dshape[a] * dshape[b]
+    return M, A
+
+
 @dataclass
 class AxisBasis:
     n: int
@@ -66,10 +85,11 @@ class AxisBasis:
     Q: np.ndarray       # M-orthonormal eigenvectors (columns), Q^T M Q = I
     lam: np.ndarray     # generalized eigenvalues: A q = lam M q
     mu: np.ndarray      # mass eigenvalues of the orthonormal eigenvectors
+    periodic: bool = False
 
 
 @lru_cache(maxsize=16)
-def axis_basis(n: int, lo: float, hi: float) -> AxisBasis:
+def axis_basis(n: int, lo: float, hi: float, periodic: bool = False) -> AxisBasis:
     """Diagonalise the commuting pair (M_a, A_a) with dense LAPACK.
 
     eigh(A) gives orthonormal eigenvectors V (A has distinct eigenvalues, so V
@@ -80,25 +100,39 @@ def axis_basis(n: int, lo: float, hi: float) -> AxisBasis:
     (The generalized solver eigh(A, M) is avoided: it is markedly less
     accurate for the smallest eigenvalue at n ~ 500.)
     """
-    M, A = axis_matrices(n, lo, hi)
-    _, V = scipy.linalg.eigh(A)
-    V = V * np.sign(V[0, :])
+    if periodic:
+        # circulant pair: A has double eigenvalues (the cos/sin pairs), where
+        # any orthonormal basis of the eigenspace serves (M is a polynomial
+        # in A, so it is diagonal there too); results are compared through
+        # basis-free quantities (nodal values, norms)
+        M, A = periodic_axis_matrices(n, lo, hi)
+        _, V = scipy.linalg.eigh(A)
+        V = V * np.sign(V[np.argmax(np.abs(V), axis=0), np.arange(n)])
+        h = (hi - lo) / n
+    else:
+        M, A = axis_matrices(n, lo, hi)
+        _, V = scipy.linalg.eigh(A)
+        V = V * np.sign(V[0, :])
+        h = (hi - lo) / (n + 1)
     mu = np.sum(V * (M @ V), axis=0)
     lam = np.sum(V * (A @ V), axis=0) / mu
     Q = V / np.sqrt(mu)
-    h = (hi - lo) / (n + 1)
-    return AxisBasis(n, lo, hi, h, M, A, Q, lam, mu)
+    return AxisBasis(n, lo, hi, h, M, A, Q, lam, mu, periodic)
 
 
 class Grid:
-    """Tensor-product Q1 grid on a box with homogeneous Dirichlet data."""
+    """Tensor-product Q1 grid on a box: per axis homogeneous Dirichlet data
+    (default) or periodicity (n nodes per period)."""
 
-    def __init__(self, n, lo, hi):
+    def __init__(self, n, lo, hi, periodic=None):
         self.n = tuple(int(v) for v in n)
         self.lo = tuple(float(v) for v in lo)
         self.hi = tuple(float(v) for v in hi)
         self.dim = len(self.n)
-        self.axes = [axis_basis(a, l, r) for a, l, r in zip(self.n, self.lo, self.hi)]
+        per = tuple(bool(p) for p in periodic) if periodic else (False,) * self.dim
+        self.periodic = per + (False,) * (self.dim - len(per))
+        self.axes = [axis_basis(a, l, r, p) for a, l, r, p in
+                     zip(self.n, self.lo, self.hi, self.periodic)]
 
     @property
     def shape(self):
@@ -115,6 +149,8 @@ class Grid:
 
     def nodes(self, a: int) -> np.ndarray:
         ax = self.axes[a]
+        if ax.periodic:
+            return ax.lo + ax.h * np.arange(ax.n)
         return ax.lo + ax.h * np.arange(1, ax.n + 1)
 
     # mode products ------------------------------------------------------

@@ -54,13 +54,26 @@ def eval_terms(terms, t, grid_points: Sequence[np.ndarray], use_time=True) -> np
 
 
 @lru_cache(maxsize=4096)
-def load_1d(sf, n: int, lo: float, hi: float, q: int) -> np.ndarray:
+def load_1d(sf, n: int, lo: float, hi: float, q: int, periodic: bool = False) -> np.ndarray:
     """C_j = int X(x) phi_j(x) dx over the two elements touching node j.
 
     Element e = [x_e, x_{e+1}] (e = 0..n) carries the local hats 1 - xi (node
     e) and xi (node e + 1); interior node j (1..n) collects the right half of
     element j - 1 and the left half of element j.  The elements are looped
-    over as one vectorised array."""
+    over as one vectorised array.  Periodic axis (n nodes per period, node j
+    at lo + j h, element e = [x_e, x_{e+1}], e = 0..n-1, node n = node 0):
+    node j collects the right half of element j - 1 (mod n) and the left half
+    of element j."""
+    if periodic:
+        h = (hi - lo) / n
+        xg, wg = gauss_legendre_01(q)
+        e = np.arange(n)[:, None]
+        X = space_factor(sf, lo + h * (e + xg[None, :]))
+        left = h * np.sum(wg * X * (1.0 - xg), axis=1)        # to node e
+        right = h * np.sum(wg * X * xg, axis=1)               # to node e + 1
+        C = left + np.roll(right, 1)
+        C.setflags(write=False)
+        return C
     h = (hi - lo) / (n + 1)
     xg, wg = gauss_legendre_01(q)
     e = np.arange(n + 1)[:, None]
@@ -122,7 +135,7 @@ def load_field(grid: Grid, terms, t: float, q: int = 3, use_time: bool = True) -
         prod = np.ones(())
         for a, sf in enumerate(term.space):
             ax = grid.axes[a]
-            prod = np.multiply.outer(prod, load_1d(sf, ax.n, ax.lo, ax.hi, q))
+            prod = np.multiply.outer(prod, load_1d(sf, ax.n, ax.lo, ax.hi, q, ax.periodic))
         F = F + v * prod
     return F
 

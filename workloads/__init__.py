@@ -113,6 +113,9 @@ class Problem:
     boundary: List[Term] = field(default_factory=list)
     # moving hat sources added to the forcing (not separable in t and x)
     moving: List[MovingHat] = field(default_factory=list)
+    # per axis: periodic (n nodes per period) instead of Dirichlet; empty:
+    # all Dirichlet
+    periodic: Tuple[bool, ...] = ()
 
     @property
     def q(self) -> int:
