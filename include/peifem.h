@@ -115,6 +115,24 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
                        const double *hi, double D, int32_t precision, int32_t quad_q,
                        void *stream);
 
+/* As pe_init_grid, with periodic[a] != 0 making axis a periodic (Section 1
+ * and the closing remark of Section 2 carry the method over to periodic
+ * boundary conditions): n[a] nodes per period, node j at lo + j h, h =
+ * (hi - lo)/n; the circulant Q1 pair has lambda_a(k) = (6/h^2)(1 - cos t_k)/
+ * (2 + cos t_k) with t_k = 2 pi k / n (a zero mode included, which the phi
+ * tables take at z = 0) and the orthonormal cos/sin basis; a periodic axis of
+ * a state holds its modes in the order: position 0 the constant, 2k - 1 cos k,
+ * 2k sin k (k = 1..n/2 - 1), n - 1 the alternating mode (k = n/2).  Loads
+ * use the grid's Gauss rule on the n elements of the period, node 0 taking
+ * the last one.  Grids with a periodic axis use the FFT transform (FP64; a
+ * periodic n in {64, 128, 256, 512, 1024}, the other axes n + 1 in
+ * {64, .., 512}) with the separate update; Dirichlet data, moving sources on
+ * a periodic axis and the learned calls are not available on them.
+ * Errors: as pe_init_grid, plus PE_E_ARG for these limits. */
+pe_status pe_init_grid_periodic(pe_grid *out, int32_t dim, const int32_t *n, const double *lo,
+                                const double *hi, double D, int32_t precision, int32_t quad_q,
+                                const int32_t *periodic, void *stream);
+
 /* Release a grid and its device tables (NULL is ignored). */
 void pe_free_grid(pe_grid g);
 

@@ -489,6 +489,58 @@ __global__ void k_fft_tables(FftFinalArgs a, int L, const double *__restrict__ s
   }
 }
 
+// One periodic axis (N = n nodes per period) of a batch of fields.  Two real
+// lines x, x' ride in one complex FFT of z = x + i x' (no extension); with
+// Z = DFT(z), X_k = (Z_k + conj Z_{N-k}) / 2 and X'_k = (Z_k - conj Z_{N-k}) / 2i,
+// and the orthonormal cos/sin coefficients of a line are Re X_0 / sqrt(N)
+// (position 0), sqrt(2/N) Re X_k (cos k, position 2k - 1), -sqrt(2/N) Im X_k
+// (sin k, position 2k) and Re X_{N/2} / sqrt(N) (position N - 1).
+template <int N, bool CONTIG>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_pass_periodic(FftPassArgs a) {
+  using Sh = Shape<N>;
+  constexpr int LINES = Sh::LINES;
+  constexpr int PER_THREAD = LINES * N / FFT_THREADS;
+  __shared__ c2 Zs[Sh::P * Sh::FS];
+  double *Zd = reinterpret_cast<double *>(Zs);
+  const int t = threadIdx.x;
+  const int64_t l0 = int64_t(blockIdx.x) * LINES;
+  auto line_base = [&](int64_t ln) -> int64_t {
+    if (CONTIG) return ln * N;
+    const int64_t o = ln / a.inner;
+    return o * N * a.inner + (ln - o * a.inner);
+  };
+#pragma unroll
+  for (int k = 0; k < PER_THREAD; ++k) {
+    const int e = t + k * FFT_THREADS;
+    const int l = CONTIG ? e / N : e % LINES;
+    const int j = CONTIG ? e % N : e / LINES;
+    const int64_t ln = l0 + l;
+    const double x = ln < a.nlines ? a.in[line_base(ln) + int64_t(j) * a.inner] : 0.0;
+    Zd[2 * ((l % Sh::P) * Sh::FS + pidx(j)) + l / Sh::P] = x;
+  }
+  __syncthreads();
+  c2 v[8];
+  fft_run<N, 1, false>(Zs + (t / Sh::TF) * Sh::FS, a.tw, t % Sh::TF, v);
+  __syncthreads();
+  const double s0 = 1.0 / sqrt(double(N)), s1 = sqrt(2.0 / double(N));
+#pragma unroll
+  for (int k = 0; k < PER_THREAD; ++k) {
+    const int e = t + k * FFT_THREADS;
+    const int l = CONTIG ? e / N : e % LINES;
+    const int q = CONTIG ? e % N : e / LINES;
+    const int64_t ln = l0 + l;
+    if (ln >= a.nlines) continue;
+    const int p = l % Sh::P, part = l / Sh::P;
+    const int kk = q == 0 ? 0 : (q == N - 1 ? N / 2 : (q + 1) / 2);
+    const c2 Zk = Zs[p * Sh::FS + pidx(kk)];
+    const c2 Zm = Zs[p * Sh::FS + pidx((N - kk) % N)];
+    const double re = part ? 0.5 * (Zk.y + Zm.y) : 0.5 * (Zk.x + Zm.x);
+    const double im = part ? -0.5 * (Zk.x - Zm.x) : 0.5 * (Zk.y - Zm.y);
+    const double y = (q == 0 || q == N - 1) ? re * s0 : ((q & 1) ? re * s1 : -im * s1);
+    a.out[line_base(ln) + int64_t(q) * a.inner] = y;
+  }
+}
+
 // ------------------------------------------------------------------ host
 
 bool fft_axis_ok(int n) {
@@ -496,8 +548,11 @@ bool fft_axis_ok(int n) {
   return L == 64 || L == 128 || L == 256 || L == 512;
 }
 
+bool fft_periodic_ok(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+
 bool fft_gen_supported(pe_grid g, int n_terms) {
-  return n_terms >= 1 && n_terms <= FFT_GEN_MAX_TERMS;
+  // the generating pass builds the odd extension of Dirichlet lines
+  return n_terms >= 1 && n_terms <= FFT_GEN_MAX_TERMS && !g->ax[g->dim - 1].periodic;
 }
 
 __global__ void k_fft_twiddles(int N, c2 *tw) {
@@ -512,7 +567,7 @@ pe_status fft_prepare(pe_grid g) {
   for (int a = 0; a < g->dim; ++a) {
     Axis &ax = g->ax[a];
     if (ax.d_tw) continue;
-    const int N = 2 * (ax.n + 1);
+    const int N = ax.periodic ? ax.n : 2 * (ax.n + 1);
     PE_HIP(hipMalloc(&ax.d_tw, sizeof(c2) * size_t(N)));
     k_fft_twiddles<<<(N + 255) / 256, 256>>>(N, reinterpret_cast<c2 *>(ax.d_tw));
     PE_HIP(hipGetLastError());
@@ -538,13 +593,22 @@ static void launch_pass(const FftPassArgs &a, bool gen, bool contig, hipStream_t
   }
 }
 
+template <int N>
+static void launch_pass_periodic(const FftPassArgs &a, bool contig, hipStream_t st) {
+  const unsigned blocks = unsigned((a.nlines + Shape<N>::LINES - 1) / Shape<N>::LINES);
+  if (contig)
+    k_fft_pass_periodic<N, true><<<blocks, FFT_THREADS, 0, st>>>(a);
+  else
+    k_fft_pass_periodic<N, false><<<blocks, FFT_THREADS, 0, st>>>(a);
+}
+
 pe_status dst_fields_fft(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
                          double **result, hipStream_t st, int stop_axis) {
   double *in = buf0, *out = buf1;
   const int d = g->dim;
   for (int ax_i = d - 1; ax_i >= stop_axis; --ax_i) {
     const Axis &ax = g->ax[ax_i];
-    const int N = 2 * (ax.n + 1);
+    const int N = ax.periodic ? ax.n : 2 * (ax.n + 1);
     FftPassArgs a{};
     int64_t inner = 1;
     for (int b = ax_i + 1; b < d; ++b) inner *= g->ax[b].np;
@@ -574,6 +638,20 @@ pe_status dst_fields_fft(pe_grid g, int64_t count, const GenSrc *gen, double *bu
     TimedScope ts(g, ax_i == d - 1 ? PE_K_DST_LAST : PE_K_DST_MID, flops,
                   gen_pass ? fb : 2.0 * fb, st);
     const bool contig = inner == 1;
+    if (ax.periodic) {
+      if (gen_pass) return set_error(PE_E_ARG, "internal: no generating pass on a periodic axis");
+      switch (N) {
+        case 64: launch_pass_periodic<64>(a, contig, st); break;
+        case 128: launch_pass_periodic<128>(a, contig, st); break;
+        case 256: launch_pass_periodic<256>(a, contig, st); break;
+        case 512: launch_pass_periodic<512>(a, contig, st); break;
+        case 1024: launch_pass_periodic<1024>(a, contig, st); break;
+        default: return set_error(PE_E_ARG, "internal: periodic FFT length %d", N);
+      }
+      PE_HIP(hipGetLastError());
+      std::swap(in, out);
+      continue;
+    }
     switch (N) {
       case 128: launch_pass<128>(a, gen_pass, contig, st); break;
       case 256: launch_pass<256>(a, gen_pass, contig, st); break;
@@ -611,6 +689,8 @@ static FftFinalArgs final_args(pe_grid g, int s) {
 }
 
 bool fft_final_supported(pe_grid g) {
+  for (int a = 0; a < g->dim; ++a)
+    if (g->ax[a].periodic) return false;   // the fused kernel reads folded Dirichlet modes
   return g->dim >= 2 && g->dofp < (int64_t(1) << 31) && g->dof < (int64_t(1) << 31);
 }
 

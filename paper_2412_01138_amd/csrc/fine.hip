@@ -40,6 +40,7 @@ struct Dims {
   int n[PE_MAX_DIM];
   int np[PE_MAX_DIM];
   int Kh[PE_MAX_DIM];
+  int per[PE_MAX_DIM];   // periodic axis: the transform writes modes in their own order
 };
 
 static Dims dims_of(pe_grid g) {
@@ -49,8 +50,14 @@ static Dims dims_of(pe_grid g) {
     D.n[a] = a < g->dim ? g->ax[a].n : 1;
     D.np[a] = a < g->dim ? g->ax[a].np : 1;
     D.Kh[a] = a < g->dim ? g->ax[a].Kh : 1;
+    D.per[a] = a < g->dim && g->ax[a].periodic ? 1 : 0;
   }
   return D;
+}
+
+// position of mode k of axis a in a transformed field
+__device__ inline int mode_pos(const Dims &D, int a, int k) {
+  return D.per[a] ? k : fold_pos(k, D.Kh[a]);
 }
 
 // Load vectors of `count` fields on the padded grid (pads = 0):
@@ -174,7 +181,7 @@ __global__ void k_update(Dims D, const double *__restrict__ sig0, const double *
       r /= D.n[a];
     }
     int64_t p = 0;   // position of mode k in the folded mode order of every axis
-    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + fold_pos(kk[a], D.Kh[a]);
+    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + mode_pos(D, a, kk[a]);
     double sig = sig0[kk[0]];
     if (D.d > 1) sig *= sig1[kk[1]];
     if (D.d > 2) sig *= sig2[kk[2]];
@@ -230,7 +237,7 @@ __global__ void k_scale_compact(Dims D, const double *sig0, const double *sig1, 
       r /= D.n[a];
     }
     int64_t p = 0;
-    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + fold_pos(kk[a], D.Kh[a]);
+    for (int a = 0; a < D.d; ++a) p = p * D.np[a] + mode_pos(D, a, kk[a]);
     double sig = sig0[kk[0]];
     if (D.d > 1) sig *= sig1[kk[1]];
     if (D.d > 2) sig *= sig2[kk[2]];

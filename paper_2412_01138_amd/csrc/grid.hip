@@ -55,6 +55,20 @@ __global__ void k_axis_eig(int n, double h, double *lam, double *sig) {
   sig[k] = 1.0 / sqrt(mu);
 }
 
+// Periodic axis (n nodes per period): the circulant pair has the same
+// eigenvalue formula at t_k = 2 pi k / n; position p holds mode k(p) of the
+// cos/sin order (p = 0: k = 0; p = 2k - 1 and 2k: k; p = n - 1: k = n/2).
+__global__ void k_axis_eig_periodic(int n, double h, double *lam, double *sig) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int k = p == 0 ? 0 : (p == n - 1 ? n / 2 : (p + 1) / 2);
+  const double s = sinpi(double(k) / double(n));          // sin(t_k / 2)
+  const double c = cospi(2.0 * double(k) / double(n));    // cos(t_k)
+  const double mu = h / 3.0 * (2.0 + c);
+  lam[p] = 12.0 / (h * h) * s * s / (2.0 + c);
+  sig[p] = 1.0 / sqrt(mu);
+}
+
 // Odd (h = 0) and even (h = 1) halves of the orthonormal DST-I matrix:
 // Sh[h][i][p] = S[2i+1+h][p+1] (1-based S), restricted to the folded inputs
 // that exist (p < H, plus the middle node p = H for the odd half when n is
@@ -163,18 +177,22 @@ struct SpaceParams {
   double kappa, phase, q0, q1, q2;
 };
 
+// (periodic axis: node j at lo + j h collects element j - 1 (mod n, so node
+// 0 takes the last element of the period) and element j)
 __global__ void k_load_1d(int n, int np, double lo, double h, GaussRule rule,
-                          const SpaceParams *sp, int n_terms, double *C) {
+                          const SpaceParams *sp, int n_terms, double *C, int periodic) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   int m = blockIdx.y;
   if (j >= np || m >= n_terms) return;
   double acc = 0.0;
   if (j < n) {
     SpaceParams p = sp[m];
+    const int el = periodic ? (j > 0 ? j - 1 : n - 1) : j;    // left element's first node
+    const int er = periodic ? j : j + 1;                       // right element's first node
     for (int g = 0; g < rule.q; ++g) {
       double xi = rule.x[g];
-      double xl = lo + h * (double(j) + xi);        // left element
-      double xr = lo + h * (double(j + 1) + xi);    // right element
+      double xl = lo + h * (double(el) + xi);       // left element
+      double xr = lo + h * (double(er) + xi);       // right element
       double Xl = (p.q0 + xl * (p.q1 + xl * p.q2)) * sin(p.kappa * xl + p.phase);
       double Xr = (p.q0 + xr * (p.q1 + xr * p.q2)) * sin(p.kappa * xr + p.phase);
       acc += rule.w[g] * (Xl * xi + Xr * (1.0 - xi));
@@ -331,7 +349,8 @@ pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst
     const Axis &ax = g->ax[a];
     dim3 grid((ax.np + 127) / 128, n_terms);
     if (n_terms > 0)
-      k_load_1d<<<grid, 128, 0, st>>>(ax.n, ax.np, ax.lo, ax.h, rule, d_sp, n_terms, dst[a]);
+      k_load_1d<<<grid, 128, 0, st>>>(ax.n, ax.np, ax.lo, ax.h, rule, d_sp, n_terms, dst[a],
+                                      ax.periodic ? 1 : 0);
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) { dev_free(d_sp); PE_HIP(e); }
   }
@@ -497,10 +516,9 @@ pe_status pe_get_timing(pe_grid g, pe_kernel_stat *out) {
 }
 int32_t pe_grid_precision(pe_grid g) { return g ? g->precision : -1; }
 
-pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double *lo,
-                       const double *hi, double D, int32_t precision, int32_t quad_q,
-                       void *stream) {
-  clear_error();
+static pe_status init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double *lo,
+                           const double *hi, double D, int32_t precision, int32_t quad_q,
+                           const int32_t *periodic, void *stream) {
   if (!out || !n || !lo || !hi) return set_error(PE_E_ARG, "null argument");
   *out = nullptr;
   if (dim < 1 || dim > PE_MAX_DIM) return set_error(PE_E_ARG, "dim must be 1..3 (got %d)", dim);
@@ -508,9 +526,23 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
   if (precision != PE_FP64 && precision != PE_SPLIT_BF16)
     return set_error(PE_E_ARG, "unknown precision %d", precision);
   if (quad_q < 1 || quad_q > 8) return set_error(PE_E_ARG, "quad_q must be 1..8");
+  bool any_periodic = false;
   for (int a = 0; a < dim; ++a) {
     if (n[a] < 1 || n[a] > 8191) return set_error(PE_E_ARG, "n[%d] must be 1..8191", a);
     if (!(hi[a] > lo[a])) return set_error(PE_E_ARG, "hi[%d] must exceed lo[%d]", a, a);
+    if (periodic && periodic[a]) {
+      any_periodic = true;
+      if (!fft_periodic_ok(n[a]))
+        return set_error(PE_E_ARG, "periodic axis %d: n must be 64, 128, 256, 512 or 1024", a);
+    }
+  }
+  if (any_periodic) {
+    // periodic axes run on the FFT transform: FP64, and every other axis
+    // must suit it too
+    if (precision != PE_FP64) return set_error(PE_E_ARG, "periodic axes need an FP64 grid");
+    for (int a = 0; a < dim; ++a)
+      if (!periodic[a] && !fft_axis_ok(n[a]))
+        return set_error(PE_E_ARG, "axis %d: with periodic axes n + 1 must be 64..512 (a power of 2)", a);
   }
   hipStream_t st = as_stream(stream);
   pe_grid g = new pe_grid_s();
@@ -528,11 +560,25 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
   for (int a = 0; a < dim; ++a) {
     Axis &ax = g->ax[a];
     ax.n = n[a];
+    ax.lo = lo[a];
+    ax.hi = hi[a];
+    if (periodic && periodic[a]) {
+      ax.periodic = true;
+      ax.Kh = ax.H = n[a] / 2;
+      ax.np = n[a];
+      ax.h = (hi[a] - lo[a]) / n[a];
+      g->dof *= ax.n;
+      g->dofp *= ax.np;
+      hipError_t e = hipMalloc(&ax.d_lam, sizeof(double) * ax.n);
+      if (e == hipSuccess) e = hipMalloc(&ax.d_sig, sizeof(double) * ax.n);
+      if (e != hipSuccess)
+        return fail(set_error(PE_E_HIP, "grid table allocation failed: %s", hipGetErrorString(e)));
+      k_axis_eig_periodic<<<(ax.n + 127) / 128, 128, 0, st>>>(ax.n, ax.h, ax.d_lam, ax.d_sig);
+      continue;
+    }
     ax.Kh = half_pad(n[a]);
     ax.H = n[a] / 2;
     ax.np = 2 * ax.Kh;
-    ax.lo = lo[a];
-    ax.hi = hi[a];
     ax.h = (hi[a] - lo[a]) / (n[a] + 1);
     g->dof *= ax.n;
     g->dofp *= ax.np;
@@ -573,8 +619,28 @@ pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess)
     return fail(set_error(PE_E_HIP, "grid set-up kernels failed: %s", hipGetErrorString(e)));
+  if (any_periodic) {
+    pe_status ps = fft_prepare(g);
+    if (ps != PE_OK) return fail(ps);
+    g->transform = PE_TRANSFORM_FFT;
+  }
   *out = g;
   return PE_OK;
+}
+
+pe_status pe_init_grid(pe_grid *out, int32_t dim, const int32_t *n, const double *lo,
+                       const double *hi, double D, int32_t precision, int32_t quad_q,
+                       void *stream) {
+  clear_error();
+  return init_grid(out, dim, n, lo, hi, D, precision, quad_q, nullptr, stream);
+}
+
+pe_status pe_init_grid_periodic(pe_grid *out, int32_t dim, const int32_t *n, const double *lo,
+                                const double *hi, double D, int32_t precision, int32_t quad_q,
+                                const int32_t *periodic, void *stream) {
+  clear_error();
+  if (!periodic) return set_error(PE_E_ARG, "null periodic flags");
+  return init_grid(out, dim, n, lo, hi, D, precision, quad_q, periodic, stream);
 }
 
 void pe_free_grid(pe_grid g) {
@@ -587,10 +653,14 @@ void pe_free_grid(pe_grid g) {
 pe_status pe_set_transform(pe_grid g, int32_t kind) {
   clear_error();
   if (!g) return set_error(PE_E_ARG, "null grid");
+  bool any_periodic = false;
+  for (int a = 0; a < g->dim; ++a) any_periodic = any_periodic || g->ax[a].periodic;
   if (kind == PE_TRANSFORM_DENSE) {
+    if (any_periodic) return set_error(PE_E_ARG, "periodic axes need the FFT transform");
     g->transform = kind;
     return PE_OK;
   }
+  if (kind == PE_TRANSFORM_FFT && any_periodic) return PE_OK;
   if (kind != PE_TRANSFORM_FFT) return set_error(PE_E_ARG, "unknown transform %d", kind);
   if (g->precision != PE_FP64) return set_error(PE_E_ARG, "the FFT transform needs an FP64 grid");
   for (int a = 0; a < g->dim; ++a)
@@ -670,6 +740,7 @@ pe_status pe_set_moving_sources(pe_grid g, int32_t n, const pe_moving_hat *src, 
   for (int i = 0; i < n; ++i) {
     const pe_moving_hat &h = src[i];
     if (h.axis < 0 || h.axis >= g->dim) return set_error(PE_E_ARG, "source %d: bad axis", i);
+    if (g->ax[h.axis].periodic) return set_error(PE_E_ARG, "source %d: periodic axis", i);
     if (!(h.width > 0) || !std::isfinite(h.width) || !std::isfinite(h.amp) ||
         !std::isfinite(h.c0) || !std::isfinite(h.c1) || !std::isfinite(h.omega) ||
         !std::isfinite(h.phase))
@@ -714,6 +785,9 @@ pe_status pe_set_moving_sources(pe_grid g, int32_t n, const pe_moving_hat *src, 
 pe_status pe_set_boundary(pe_grid g, int32_t n_terms, const pe_term *terms, void *stream) {
   clear_error();
   if (!g) return set_error(PE_E_ARG, "null grid");
+  for (int a = 0; a < g->dim; ++a)
+    if (g->ax[a].periodic && n_terms > 0)
+      return set_error(PE_E_ARG, "Dirichlet data on a grid with periodic axes");
   if (n_terms < 0 || n_terms > PE_MAX_TERMS)
     return set_error(PE_E_ARG, "n_terms must be 0..%d", PE_MAX_TERMS);
   if (n_terms > 0 && !terms) return set_error(PE_E_ARG, "null terms");

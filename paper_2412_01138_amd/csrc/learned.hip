@@ -274,6 +274,7 @@ pe_status pe_learned_samples(pe_grid g, int32_t n_slices, double t0, double dT, 
   if (!g || !d_samples) return set_error(PE_E_ARG, "null argument");
   if (n_slices < 1 || !(dT > 0)) return set_error(PE_E_ARG, "bad n_slices / dT");
   if (g->n_hats > 0) return set_error(PE_E_ARG, "the learned inputs do not cover moving sources");
+  if (has_periodic(g)) return set_error(PE_E_ARG, "the learned inputs are built for Dirichlet axes");
   hipStream_t st = as_stream(stream);
   const size_t sb = g->precision == PE_FP64 ? sizeof(double) : sizeof(float);
   if (g->n_terms == 0) {
@@ -338,6 +339,7 @@ pe_status pe_learned_rows(pe_grid g, int32_t n_slices, double t0, double dT, con
   if (n_slices < 1 || !(dT > 0) || max_rows < 0 || !(rel_thresh >= 0) || !std::isfinite(t0))
     return set_error(PE_E_ARG, "bad arguments");
   if (g->n_hats > 0) return set_error(PE_E_ARG, "the learned inputs do not cover moving sources");
+  if (has_periodic(g)) return set_error(PE_E_ARG, "the learned inputs are built for Dirichlet axes");
   if (work_bytes < pe_learned_rows_workspace_bytes(g, n_slices))
     return set_error(PE_E_WORKSPACE, "workspace too small");
   hipStream_t st = as_stream(stream);

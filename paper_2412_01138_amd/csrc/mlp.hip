@@ -695,6 +695,7 @@ pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double t0
   if (n_slices < 1 || !(dT > 0) || !std::isfinite(t0))
     return set_error(PE_E_ARG, "bad n_slices / t0 / dT");
   if (g->n_hats > 0) return set_error(PE_E_ARG, "the learned inputs do not cover moving sources");
+  if (has_periodic(g)) return set_error(PE_E_ARG, "the learned inputs are built for Dirichlet axes");
   hipStream_t st = as_stream(stream);
   const bool fp64 = g->precision == PE_FP64;
   const size_t sb = fp64 ? sizeof(double) : sizeof(float);

@@ -42,6 +42,10 @@ __device__ inline int64_t xcd_remap(int64_t bid, int64_t nblocks) {
 
 struct Axis {
   int n = 0, np = 0, Kh = 0, H = 0;
+  // periodic axis: n nodes per period (node j at lo + j h, h = (hi - lo)/n),
+  // np = n, modes in cos/sin order (position 0: the constant, 2k - 1: cos k,
+  // 2k: sin k, n - 1: the alternating mode k = n/2); no DST tables
+  bool periodic = false;
   double lo = 0, hi = 0, h = 0;
   double *d_lam = nullptr;       // [n]   generalized eigenvalues lambda_a(k)
   double *d_sig = nullptr;       // [n]   1/sqrt(mu_a(k)), mu_a the mass eigenvalues
@@ -286,6 +290,7 @@ pe_status build_loads(pe_grid g, int n_terms, const pe_term *terms, double **dst
 // dst_fields_f64 (gen->Cl the plain last-axis table); the fused axis-0 pass
 // + update takes (1 + s) DOF_padded doubles of tables from fft_tables.
 bool fft_axis_ok(int n);
+bool fft_periodic_ok(int n);
 bool fft_gen_supported(pe_grid g, int n_terms);
 pe_status fft_prepare(pe_grid g);
 pe_status dst_fields_fft(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
@@ -295,6 +300,12 @@ pe_status fft_tables(pe_grid g, int s, const double *E, const double *B, double 
                      hipStream_t st);
 pe_status fft_final_update(pe_grid g, const FieldBatch &b, const double *X, const double *Tf,
                            const double *Uin, double *Uout, hipStream_t st);
+
+inline bool has_periodic(pe_grid g) {
+  for (int a = 0; a < g->dim; ++a)
+    if (g->ax[a].periodic) return true;
+  return false;
+}
 
 // bytes of one padded stage field
 size_t field_bytes(pe_grid g);

@@ -32,7 +32,7 @@ PE_TRANSFORM_DENSE = 0
 PE_TRANSFORM_FFT = 1
 
 EXPORTS = [
-    "pe_init_grid", "pe_free_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+    "pe_init_grid", "pe_init_grid_periodic", "pe_free_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
     "pe_set_moving_sources",
     "pe_phi_tables", "pe_project_workspace_bytes", "pe_project", "pe_project_state",
     "pe_fine_workspace_bytes",
@@ -113,6 +113,8 @@ def load_library():
     vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     dp = ctypes.POINTER(ctypes.c_double)
     L.pe_init_grid.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), dp, dp, dbl, i32, i32, vp]
+    L.pe_init_grid_periodic.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), dp, dp, dbl, i32,
+                                        i32, ctypes.POINTER(i32), vp]
     L.pe_free_grid.argtypes = [vp]
     L.pe_free_grid.restype = None
     L.pe_set_transform.argtypes = [vp, i32]
@@ -162,7 +164,7 @@ def load_library():
                                         vp, sz, vp]
     L.pe_last_error.argtypes = []
     L.pe_last_error.restype = ctypes.c_char_p
-    for name in ("pe_init_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+    for name in ("pe_init_grid", "pe_init_grid_periodic", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
                  "pe_set_moving_sources",
                  "pe_project_state", "pe_phi_tables", "pe_project",
                  "pe_fine_propagate", "pe_coarse_sweep", "pe_parareal_solve", "pe_set_timing",
@@ -227,7 +229,7 @@ class Grid:
 
     def __init__(self, n: Sequence[int], lo: Sequence[float], hi: Sequence[float], D: float,
                  precision: str = "fp64", quad_q: int = 3, device: str = "cuda:0", stream=None,
-                 transform: str = "dense"):
+                 transform: str = "dense", periodic: Optional[Sequence[bool]] = None):
         import torch
         self.L = load_library()
         self.device = torch.device(device)
@@ -239,21 +241,28 @@ class Grid:
         self.stream = stream
         handle = ctypes.c_void_p()
         nn = (ctypes.c_int32 * len(self.n))(*self.n)
+        self.periodic = tuple(bool(p) for p in periodic) if periodic else (False,) * self.dim
         with torch.cuda.device(self.device):
-            _check(self.L.pe_init_grid(ctypes.byref(handle), self.dim, nn, _dbl_array(lo),
-                                       _dbl_array(hi), float(D), prec, int(quad_q),
-                                       _stream(stream)))
+            if any(self.periodic):
+                per = (ctypes.c_int32 * self.dim)(*[int(p) for p in self.periodic])
+                _check(self.L.pe_init_grid_periodic(ctypes.byref(handle), self.dim, nn,
+                                                    _dbl_array(lo), _dbl_array(hi), float(D), prec,
+                                                    int(quad_q), per, _stream(stream)))
+            else:
+                _check(self.L.pe_init_grid(ctypes.byref(handle), self.dim, nn, _dbl_array(lo),
+                                           _dbl_array(hi), float(D), prec, int(quad_q),
+                                           _stream(stream)))
         self.h = handle
         self.dof = int(self.L.pe_grid_dof(self.h))
-        self.transform = "dense"
-        if transform != "dense":
+        self.transform = "fft" if any(self.periodic) else "dense"
+        if transform != "dense" and transform != self.transform:
             self.set_transform(transform)
 
     @classmethod
     def from_problem(cls, prob, quad_q: int = 3, device: str = "cuda:0", stream=None,
                      transform: str = "dense") -> "Grid":
         g = cls(prob.n, prob.lo, prob.hi, prob.D, prob.precision, quad_q, device, stream,
-                transform)
+                transform, getattr(prob, "periodic", None) or None)
         g.set_forcing(prob.forcing)
         if getattr(prob, "boundary", None):
             g.set_boundary(prob.boundary)
