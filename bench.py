@@ -287,6 +287,43 @@ def dirichlet_data(prob, repeats: int):
     return out
 
 
+def periodic_solve(prob, repeats: int):
+    """Workload 2's forcing and slicing on a 256 x 256 grid periodic in both
+    axes (pe_init_grid_periodic; FFT transform, separate update): wall time
+    per solve and fine-pass rate."""
+    import torch
+    from paper_2412_01138_amd import peifem
+
+    pb = prob.with_(n=(256, 256), periodic=(True, True))
+    g = peifem.Grid.from_problem(pb)
+    P = g.solve_params(pb.t0, pb.T, pb.N, pb.J, pb.c_coarse, pb.c_fine, pb.K_max, pb.tol)
+    work = g.workspace(g.solve_workspace_bytes(P))
+    U = g.empty_states(pb.N + 1)
+    g.parareal_solve(P, U=U, work=work)
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    reports = []
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        _, rep = g.parareal_solve(P, U=U, work=work)
+        reports.append(rep)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / repeats
+    stats = g.get_timing()
+    g.set_timing(False)
+    iters = reports[-1].iterations
+    fine_updates = pb.dof * pb.N * pb.J * pb.q
+    fine_ms = sum(r.ms_fine for r in reports) / len(reports) / max(iters, 1)
+    out = {"grid": list(pb.n), "periodic": list(pb.periodic), "ms_per_solve": ms,
+           "iterations": iters, "converged": bool(reports[-1].converged),
+           "fine_updates_per_s": iters * fine_updates / (ms / 1e3), "ms_fine_per_pass": fine_ms,
+           "kernels_ms_per_launch": {k: v["ms"] / v["launches"] for k, v in stats.items()
+                                     if v["launches"]}}
+    del work, U, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def example_5_4_runs(repeats: int = 3):
     """The paper's Example 5.4 (1D oscillating hat source, N_x = 1024, N x M =
     4 x 16, 4 Parareal iterations) for its three settings: wall time per solve
@@ -466,6 +503,7 @@ def main():
     if not args.no_fft:
         out["dirichlet_data"] = dirichlet_data(prob, max(args.steps, 3))
         out["example_5_4"] = example_5_4_runs()
+        out["periodic"] = periodic_solve(prob, max(args.steps, 3))
     if not args.no_learned:
         out["learned_vs_plain_G"] = learned_vs_plain(args.learned_forcings, args.learned_steps)
     if not args.no_3d:

@@ -63,35 +63,47 @@ __device__ inline int mode_pos(const Dims &D, int a, int k) {
 // Load vectors of `count` fields on the padded grid (pads = 0):
 //   F_f[j] = sum_m coef[f][m] prod_a C_a[m][j_a]
 // (the tensor Gauss rule applied to a separable term factorises into 1D
-// rules, so C_a are the per-axis element-quadrature loads).
+// rules, so C_a are the per-axis element-quadrature loads).  Block = one row
+// (all axes but the last fixed) at a time: the row's factors
+// coef[f][m] prod_{a<d-1} C_a[m][j_a] are formed once in LDS, then each
+// thread sums them against the last-axis table for its nodes (the product
+// order of a per-node evaluation, so the values are the same).
 template <typename TG>
-__global__ void k_load_fields(Dims D, const double *__restrict__ C0, const double *__restrict__ C1,
-                              const double *__restrict__ C2, int n_terms,
-                              const double *__restrict__ coef, TG *__restrict__ out, int64_t dofp,
-                              int64_t total) {
-  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
-       idx += int64_t(gridDim.x) * blockDim.x) {
-  int64_t f = idx / dofp;
-  int64_t p = idx - f * dofp;
-  int j[3] = {0, 0, 0};
-  int64_t r = p;
-  for (int a = D.d - 1; a >= 0; --a) {
-    j[a] = int(r % D.np[a]);
-    r /= D.np[a];
-  }
-  bool inside = true;
-  for (int a = 0; a < D.d; ++a) inside = inside && (j[a] < D.n[a]);
-  double v = 0.0;
-  if (inside) {
-    const double *cf = coef + f * n_terms;
-    for (int m = 0; m < n_terms; ++m) {
-      double prod = cf[m] * C0[int64_t(m) * D.np[0] + j[0]];
-      if (D.d > 1) prod *= C1[int64_t(m) * D.np[1] + j[1]];
-      if (D.d > 2) prod *= C2[int64_t(m) * D.np[2] + j[2]];
-      v += prod;
+__global__ __launch_bounds__(256) void k_load_fields(Dims D, const double *__restrict__ C0,
+                                                     const double *__restrict__ C1,
+                                                     const double *__restrict__ C2, int n_terms,
+                                                     const double *__restrict__ coef,
+                                                     TG *__restrict__ out, int64_t rows_total,
+                                                     int64_t rows_per_field) {
+  __shared__ double pre[PE_MAX_TERMS];
+  const int last = D.d - 1;
+  const int npl = D.np[last], nl = D.n[last];
+  const double *Cl = last == 0 ? C0 : (last == 1 ? C1 : C2);
+  for (int64_t row = blockIdx.x; row < rows_total; row += gridDim.x) {
+    const int64_t f = row / rows_per_field;
+    int64_t r = row - f * rows_per_field;
+    int j[2] = {0, 0};
+    bool inside = true;
+    for (int a = last - 1; a >= 0; --a) {
+      j[a] = int(r % D.np[a]);
+      r /= D.np[a];
+      inside = inside && j[a] < D.n[a];
     }
-  }
-  out[idx] = TG(v);
+    __syncthreads();   // the previous row's factors are read
+    for (int m = threadIdx.x; m < n_terms; m += blockDim.x) {
+      double v = coef[f * n_terms + m];
+      if (last >= 1) v *= C0[int64_t(m) * D.np[0] + j[0]];
+      if (last >= 2) v *= C1[int64_t(m) * D.np[1] + j[1]];
+      pre[m] = inside ? v : 0.0;
+    }
+    __syncthreads();
+    TG *o = out + row * npl;
+    for (int jl = threadIdx.x; jl < npl; jl += blockDim.x) {
+      double x = 0.0;
+      if (jl < nl)
+        for (int m = 0; m < n_terms; ++m) x += pre[m] * Cl[int64_t(m) * npl + jl];
+      o[jl] = TG(x);
+    }
   }
 }
 
@@ -255,15 +267,17 @@ static inline unsigned blocks_for(int64_t n, int bs = 256) {
 static pe_status launch_load(pe_grid g, double *const *C, int n_terms, const double *coef,
                              void *out, int64_t count, hipStream_t st) {
   Dims D = dims_of(g);
-  int64_t total = count * g->dofp;
   const double sb = g->precision == PE_FP64 ? 8.0 : 4.0;
   TimedScope ts(g, PE_K_LOAD, 0.0, double(count) * double(g->dof) * sb, st);
+  const int64_t per_field = g->dofp / g->ax[g->dim - 1].np;
+  const int64_t rows = count * per_field;
+  const unsigned blocks = unsigned(std::min<int64_t>(std::max<int64_t>(rows, 1), 65536));
   if (g->precision == PE_FP64)
-    k_load_fields<double><<<blocks_for(total), 256, 0, st>>>(
-        D, C[0], C[1], C[2], n_terms, coef, static_cast<double *>(out), g->dofp, total);
+    k_load_fields<double><<<blocks, 256, 0, st>>>(D, C[0], C[1], C[2], n_terms, coef,
+                                                   static_cast<double *>(out), rows, per_field);
   else
-    k_load_fields<float><<<blocks_for(total), 256, 0, st>>>(
-        D, C[0], C[1], C[2], n_terms, coef, static_cast<float *>(out), g->dofp, total);
+    k_load_fields<float><<<blocks, 256, 0, st>>>(D, C[0], C[1], C[2], n_terms, coef,
+                                                  static_cast<float *>(out), rows, per_field);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }

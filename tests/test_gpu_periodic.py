@@ -184,3 +184,25 @@ def test_periodic_argument_errors():
         g.set_boundary([wl.Term(1.0, wl.TimeFactor(), (wl.poly_factor(1.0), wl.poly_factor(1.0)))])
     with pytest.raises(pe.PeifemError):
         g.learned_samples(prob.N, prob.t0, prob.dT)
+
+
+def test_periodic_fullsize_first_slices():
+    """Workload 2's forcing and slicing on a 256 x 256 fully periodic grid,
+    at full size in the default batching: the converged answer at T_1 and
+    T_2 against the oracle's sequential fine solution of the first two
+    slices (nodal values)."""
+    import workloads as wl_
+    from oracle.eife import sequential
+    pe = _pe()
+    prob = wl_.config(2).with_(n=(256, 256), periodic=(True, True))
+    print(f"periodic full size: dof {prob.dof}", flush=True)
+    g, U, rep = pe.solve_problem(prob)
+    assert rep.converged
+    d = Discretization(prob)
+    Ql, _ = _bases(prob, d)
+    W, kept = sequential(d, d.initial(), prob.t0, d.tables(prob.dt, prob.c_fine), 2 * prob.J,
+                         keep_every=prob.J)
+    got = _apply(Ql, U[:3].cpu().numpy())
+    err = rel(got, d.grid.to_nodal(np.stack(kept)))
+    print(f"  iterations {rep.iterations}, relative L2 error (nodal) on slices 0..2: {err:.3e}")
+    assert err <= oracle_bar(prob.n, prob.periodic)
