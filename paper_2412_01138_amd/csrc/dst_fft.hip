@@ -421,13 +421,21 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_final(FftFinalArgs a) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) put_node<N>(Zd, l, t / LINES + k * (FFT_THREADS / LINES), S[k]);
     __syncthreads();
+    // the field's tables, issued before the next strip's loads (loads
+    // complete in issue order: the update then waits for its tables only)
+    const int i = e % a.s;
+    const double *Ti = Tl + (1 + i) * 8 * FFT_THREADS;
+    double tb[8], te[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      tb[k] = Ti[k * FFT_THREADS];
+      te[k] = i == 0 ? Tl[k * FFT_THREADS] : 1.0;
+    }
     if (e + 1 < nf) load(e + 1);   // in flight during the transform
     c2 v[8];
     fft_run<N, 1, true>(Zs + p * Sh::FS, a.tw, u, v);
     // eq. (2.6): W = E W at a step's first stage, then W += (b_i sigma) y;
     // the tables carry sigma and the 1/sqrt(2L)
-    const int i = e % a.s;
-    const double *Ti = Tl + (1 + i) * 8 * FFT_THREADS;
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       int vi, fi;
@@ -437,8 +445,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_final(FftFinalArgs a) {
         const int k = 2 * sl + h;
         const double y = h ? v[vi].x : -v[vi].y;
         double w = W[k];
-        if (i == 0) w = Tl[k * FFT_THREADS] * w;
-        W[k] = w + Ti[k * FFT_THREADS] * y;
+        if (i == 0) w = te[k] * w;
+        W[k] = w + tb[k] * y;
       }
     }
     __syncthreads();   // every wave is done with LDS before the next strip lands

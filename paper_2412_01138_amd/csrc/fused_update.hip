@@ -215,12 +215,12 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   for (int e0 = 0; e0 < nf; e0 += FPB) {
     const int stage = (e0 / FPB) & 1;
     const int nxt = e0 + FPB;
-#pragma unroll
-    for (int f = 0; f < FPB; ++f)
-      if (nxt + f < nf) load(S[f], nxt + f, 0);
     // tables of the group (16-byte loads, contiguous across the wave): the
     // decay once per group (it does not depend on the stage), a weight set
-    // per field; ahead of the products where the registers allow it
+    // per field; ahead of the products where the registers allow it, and
+    // issued before the next strip's loads: memory loads complete in issue
+    // order, so the update's wait for its tables then leaves the strip in
+    // flight
     int ist[FPB];
     bool need_e = false;
 #pragma unroll
@@ -235,6 +235,9 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
       if (need_e) load2(Tl, ew);
     };
     if (!LATE_TABLES) tables();
+#pragma unroll
+    for (int f = 0; f < FPB; ++f)
+      if (nxt + f < nf) load(S[f], nxt + f, 0);
     d4 c0[FPB], c1[FPB];
 #pragma unroll
     for (int f = 0; f < FPB; ++f) c0[f] = c1[f] = d4{0.0, 0.0, 0.0, 0.0};
