@@ -33,7 +33,6 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int KB = 16;
 constexpr int NT = 256;
 constexpr int GEN_MAX_TERMS = 32;
-constexpr int GEN_MAX_CF = 4096;   // doubles of one folded half table kept in LDS
 
 template <int BM, int BN>
 struct Cfg {
@@ -115,7 +114,6 @@ __global__ __launch_bounds__(NT) void k_pass_last(LastArgs a) {
   constexpr bool GEN = GM > 0;
   using C = Cfg<BM, BN>;
   __shared__ Smem<BM, BN> sm;
-  extern __shared__ double cf_lds[];   // GEN: folded last-axis table of this half, [M][Kh]
 
   int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int tn = int(bid % a.tiles_n);
@@ -143,14 +141,6 @@ __global__ __launch_bounds__(NT) void k_pass_last(LastArgs a) {
   double rfa[RT][GK];
   if constexpr (GEN) {
     const int M = a.gen.M;
-    const int ncf = M * a.Kh;
-    const double *cf_src = a.gen.Cf + int64_t(h) * ncf;
-    double stage[GEN_MAX_CF / NT];
-#pragma unroll
-    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
-      int e = t + q * NT;
-      stage[q] = cf_src[e < ncf ? e : ncf - 1];
-    }
     const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
     const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
 #pragma unroll
@@ -176,13 +166,10 @@ __global__ __launch_bounds__(NT) void k_pass_last(LastArgs a) {
         rfa[rt][kk] = (m < M && ok) ? v : 0.0;
       }
     }
-#pragma unroll
-    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
-      int e = t + q * NT;
-      if (e < ncf) cf_lds[e] = stage[q];
-    }
-    __syncthreads();
   }
+  // GEN: the folded last-axis table of this half, [M][Kh], read through the
+  // cache (a copy in LDS would cost the second block per CU)
+  const double *cf_half = GEN ? a.gen.Cf + int64_t(h) * a.gen.M * a.Kh : nullptr;
 
   // prefetch registers: raw loads only; the arithmetic happens in store()
   double ra_a[GEN ? 1 : C::CPT], ra_b[GEN ? 1 : C::CPT], rb[C::B_PER];
@@ -211,7 +198,7 @@ __global__ __launch_bounds__(NT) void k_pass_last(LastArgs a) {
 #pragma unroll
       for (int kk = 0; kk < GK; ++kk) {
         const int term = lk + 4 * kk;
-        cfb[kk] = cf_lds[(term < Mm1 ? term : Mm1) * a.Kh + k0 + lr];
+        cfb[kk] = cf_half[(term < Mm1 ? term : Mm1) * a.Kh + k0 + lr];
       }
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
@@ -522,7 +509,6 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   constexpr bool GEN = GM > 0;
   using C = Cfg<BM, BN>;
   __shared__ Smem2<BM, BN> sm;
-  extern __shared__ double cf_lds[];   // GEN: folded last-axis table of this half, [M][Kh]
 
   const int Q = a.Kh / 2;
   int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -546,14 +532,6 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   double rfa[RT][GK];
   if constexpr (GEN) {
     const int M = a.gen.M;
-    const int ncf = M * a.Kh;
-    const double *cf_src = a.gen.Cf + int64_t(h) * ncf;
-    double stage[GEN_MAX_CF / NT];
-#pragma unroll
-    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
-      int e = t + q * NT;
-      stage[q] = cf_src[e < ncf ? e : ncf - 1];
-    }
     const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
     const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
 #pragma unroll
@@ -579,13 +557,10 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
         rfa[rt][kk] = (m < M && ok) ? v : 0.0;
       }
     }
-#pragma unroll
-    for (int q = 0; q < GEN_MAX_CF / NT; ++q) {
-      int e = t + q * NT;
-      if (e < ncf) cf_lds[e] = stage[q];
-    }
-    __syncthreads();
   }
+  // GEN: the folded last-axis table of this half, [M][Kh], read through the
+  // cache (a copy in LDS would leave room for one block per CU only)
+  const double *cf_half = GEN ? a.gen.Cf + int64_t(h) * a.gen.M * a.Kh : nullptr;
 
   // raw prefetch: input rows at p = 2 jj + g and their mirrors (p <= H)
   double ra_a[GEN ? 1 : 2][GEN ? 1 : C::CPT], ra_b[GEN ? 1 : 2][GEN ? 1 : C::CPT];
@@ -622,7 +597,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
 #pragma unroll
         for (int kk = 0; kk < GK; ++kk) {
           const int term = lk + 4 * kk;
-          cfb[kk] = cf_lds[(term < Mm1 ? term : Mm1) * a.Kh + 2 * (k0 + lr) + g];
+          cfb[kk] = cf_half[(term < Mm1 ? term : Mm1) * a.Kh + 2 * (k0 + lr) + g];
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
@@ -986,7 +961,7 @@ static pe_status launch_last(LastArgs a, hipStream_t st) {
   int bn = pick(a.Kh);
   a.tiles_m = int((a.R + bm - 1) / bm);
   a.tiles_n = (a.Kh + bn - 1) / bn;
-  size_t dyn = GM > 0 ? sizeof(double) * size_t(a.gen.M) * a.Kh : 0;
+  const size_t dyn = 0;
 #define PE_LAST(BMv, BNv) \
   if (bm == BMv && bn == BNv) return launch_last_t<BMv, BNv, GM>(a, dyn, st);
   PE_LAST(128, 128) PE_LAST(128, 64) PE_LAST(128, 32)
@@ -1063,8 +1038,7 @@ static pe_status launch_last2(LastArgs a, hipStream_t st) {
   }
   a.tiles_m = int((a.R + BM - 1) / BM);
   a.tiles_n = (a.Kh / 2 + BN - 1) / BN;
-  size_t dyn = GM > 0 ? sizeof(double) * size_t(a.gen.M) * a.Kh : 0;
-  return launch_last2_t<BM, BN, GM>(a, dyn, st);
+  return launch_last2_t<BM, BN, GM>(a, 0, st);
 }
 
 static pe_status launch_mid2(Mid2Args a, hipStream_t st) {
@@ -1087,8 +1061,7 @@ static pe_status launch_mid2(Mid2Args a, hipStream_t st) {
 
 bool gen_supported(pe_grid g, int n_terms) {
   if (g->transform == PE_TRANSFORM_FFT) return fft_gen_supported(g, n_terms);
-  const Axis &last = g->ax[g->dim - 1];
-  return n_terms >= 1 && n_terms <= GEN_MAX_TERMS && int64_t(n_terms) * last.Kh <= GEN_MAX_CF;
+  return n_terms >= 1 && n_terms <= GEN_MAX_TERMS;
 }
 
 pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *buf0, double *buf1,
