@@ -18,9 +18,10 @@
 //     sum_m rf[r][m] Cf[h][m][p],  rf = coef[f][m] prod_{a<d-1} C_a[m][j_a],
 // a product with k = the (at most 32) forcing terms, done on the same bf16
 // MFMA as the transform with hi/lo splits of both factors (three products,
-// fp32 accumulation): A = Cf^T of this half (bf16 hi/lo, [p][m] in LDS),
-// B = the wave's row factors (registers), C = the tile transposed, so a lane
-// holds four consecutive p of one row.
+// fp32 accumulation): A = Cf^T of this half (bf16 hi/lo, [p][m], built once
+// per table by k_split_gen_table and read through the cache, so the block's
+// LDS holds only its tiles), B = the wave's row factors (registers), C = the
+// tile transposed, so a lane holds four consecutive p of one row.
 //
 // Block: 256 threads = 4 waves (2 x 2), tile BM (modes) x 128 (rows r),
 // k-step 32, single LDS buffer with register prefetch.
@@ -40,7 +41,6 @@ constexpr int SBN = 128;         // block tile along r
 constexpr int SLD = SKB + 8;     // LDS row length in bf16 (16-byte pad: conflict-free b128 reads)
 constexpr int SNT = 256;
 constexpr int SGEN_MAX_TERMS = 32;   // one 32-deep MFMA k-step over the terms
-constexpr int SGEN_LD = 40;          // LDS row length (bf16) of the transposed table
 
 typedef float f8 __attribute__((ext_vector_type(8)));
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));   // dword-aligned loads
@@ -80,15 +80,14 @@ struct alignas(16) SSmem {
 };
 
 template <int BM, bool GEN>
-__global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
+// (GEN: at most 168 registers, three waves per SIMD)
+__global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(GEN ? 3 : 1))) void k_split_pass(SplitArgs a) {
   constexpr int TM = BM / 32;                 // MFMA tiles per wave along the modes
   constexpr int TN = 4;                       // ... along r (64 per wave)
   constexpr int ACH = BM * (SKB / 8) / SNT;   // 16-byte A chunks per thread per array (2, 1, ..)
   constexpr int EB = 16;                      // p values of one B row per thread
   static_assert(ACH >= 1 || BM == 32, "A chunk mapping");
   __shared__ SSmem<BM> sm;
-  // GEN: Cf^T of this half as bf16 hi / lo, [Kh][SGEN_LD] each
-  extern __shared__ __align__(16) uint16_t cft[];
 
   int64_t bid = blockIdx.x;
   {
@@ -122,16 +121,6 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
   bf16x8 rfh[GEN ? 2 : 1], rfl[GEN ? 2 : 1];
   if constexpr (GEN) {
     const int M = a.gen.M;
-    const double *cf_src = a.gen.Cf + int64_t(h) * M * a.Kh;
-    uint16_t *cth = cft, *ctl = cft + a.Kh * SGEN_LD;
-    for (int e = t; e < a.Kh * SGEN_MAX_TERMS; e += SNT) {
-      const int p = e / SGEN_MAX_TERMS, m = e % SGEN_MAX_TERMS;
-      const float v = m < M ? float(cf_src[int64_t(m) * a.Kh + p]) : 0.0f;
-      const __bf16 hv = static_cast<__bf16>(v);
-      const __bf16 lv = static_cast<__bf16>(v - static_cast<float>(hv));
-      cth[p * SGEN_LD + m] = __builtin_bit_cast(uint16_t, hv);
-      ctl[p * SGEN_LD + m] = __builtin_bit_cast(uint16_t, lv);
-    }
     const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
     const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
 #pragma unroll
@@ -157,8 +146,10 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
       }
       split8(v, rfh[rt], rfl[rt]);
     }
-    __syncthreads();
   }
+  // GEN: Cf^T as 16-byte pieces, [hi / lo][h][p][m / 8]
+  const bf16x8 *cft = GEN ? reinterpret_cast<const bf16x8 *>(a.gen.Cft) : nullptr;
+  const int64_t cft_lo = int64_t(2) * a.Kh * (SGEN_MAX_TERMS / 8);
 
   const float *xrow = GEN ? nullptr : a.X + (f * a.R + grc) * a.np;
   u16x8 pah[AU], pal[AU];
@@ -219,12 +210,19 @@ __global__ __launch_bounds__(SNT) void k_split_pass(SplitArgs a) {
     }
     if constexpr (GEN) {
       // B tile rows 32 wave .. + 32, p = k0 .. k0 + 32: C^T = Cf^T rf^T
-      const uint16_t *cth = cft, *ctl = cft + a.Kh * SGEN_LD;
+      // (the A fragments are read here, not prefetched with the next step's
+      // tiles: sixteen more live registers would cost a wave per SIMD)
+      bf16x8 gth[2], gtl[2];
 #pragma unroll
       for (int pt = 0; pt < 2; ++pt) {
-        const int pr = (k0 + 16 * pt + lr) * SGEN_LD + 8 * lk;
-        const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(cth + pr);
-        const bf16x8 al = *reinterpret_cast<const bf16x8 *>(ctl + pr);
+        // this half's rows p = k0 + 16 pt + lr, terms m = 8 lk .. 8 lk + 7
+        const int64_t o = (int64_t(h) * a.Kh + k0 + 16 * pt + lr) * (SGEN_MAX_TERMS / 8) + lk;
+        gth[pt] = cft[o];
+        gtl[pt] = cft[cft_lo + o];
+      }
+#pragma unroll
+      for (int pt = 0; pt < 2; ++pt) {
+        const bf16x8 ah = gth[pt], al = gtl[pt];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
           f4 c = f4{0.f, 0.f, 0.f, 0.f};
@@ -346,14 +344,13 @@ static pe_status launch_split_t(SplitArgs a, int64_t count, hipStream_t st) {
   const int64_t per_f = int64_t(a.tiles_m) * a.tiles_n * 2;
   if (per_f > SMAX_BLOCKS) return set_error(PE_E_ARG, "internal: split grid too large");
   const int64_t max_f = std::max<int64_t>(1, SMAX_BLOCKS / per_f);
-  size_t dyn = GEN ? 2 * sizeof(uint16_t) * size_t(a.Kh) * SGEN_LD : 0;
   for (int64_t f0 = 0; f0 < count; f0 += max_f) {
     const int64_t nf = std::min(max_f, count - f0);
     SplitArgs b = a;
     if (!GEN) b.X = a.X + f0 * a.R * a.np;
     b.Y = a.Y + f0 * a.R * a.np;
     if (GEN) b.gen.coef = a.gen.coef + f0 * a.gen.M;
-    k_split_pass<BM, GEN><<<dim3(unsigned(nf * per_f)), SNT, dyn, st>>>(b);
+    k_split_pass<BM, GEN><<<dim3(unsigned(nf * per_f)), SNT, 0, st>>>(b);
     PE_HIP(hipGetLastError());
   }
   return PE_OK;
@@ -370,9 +367,33 @@ static pe_status launch_split(SplitArgs a, int64_t count, hipStream_t st) {
 }
 
 bool gen_supported_split(pe_grid g, int n_terms) {
-  const Axis &last = g->ax[g->dim - 1];
-  // the transposed hi/lo table of one half must fit in LDS next to the tiles
-  return n_terms >= 1 && n_terms <= SGEN_MAX_TERMS && last.Kh <= 256;
+  return n_terms >= 1 && n_terms <= SGEN_MAX_TERMS;
+}
+
+// Cft[s][h][p][m] (s = 0: bf16 hi, 1: lo) of Cf[h][m][p], zero for m >= M
+__global__ void k_split_gen_table(const double *Cf, int M, int Kh, uint16_t *Cft) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * Kh * SGEN_MAX_TERMS) return;
+  const int m = i % SGEN_MAX_TERMS, p = (i / SGEN_MAX_TERMS) % Kh, h = i / (SGEN_MAX_TERMS * Kh);
+  const float v = m < M ? float(Cf[(int64_t(h) * M + m) * Kh + p]) : 0.0f;
+  const __bf16 hv = static_cast<__bf16>(v);
+  const __bf16 lv = static_cast<__bf16>(v - static_cast<float>(hv));
+  Cft[i] = __builtin_bit_cast(uint16_t, hv);
+  Cft[2 * Kh * SGEN_MAX_TERMS + i] = __builtin_bit_cast(uint16_t, lv);
+}
+
+size_t split_gen_table_bytes(pe_grid g) {
+  return 2 * 2 * size_t(g->ax[g->dim - 1].Kh) * SGEN_MAX_TERMS * sizeof(uint16_t);
+}
+
+pe_status split_gen_table(pe_grid g, const double *Cf, int M, uint16_t *Cft, hipStream_t st) {
+  if (M < 1 || M > SGEN_MAX_TERMS)
+    return set_error(PE_E_ARG, "internal: %d terms for the split generating table", M);
+  const int Kh = g->ax[g->dim - 1].Kh;
+  const int total = 2 * Kh * SGEN_MAX_TERMS;
+  k_split_gen_table<<<(total + 255) / 256, 256, 0, st>>>(Cf, M, Kh, Cft);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
 }
 
 pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,
@@ -406,6 +427,7 @@ pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *
     a.np0 = g->ax[0].np;
     a.np1 = d >= 2 ? g->ax[1].np : 1;
     if (q == 0 && gen) {
+      if (!gen->Cft) return set_error(PE_E_ARG, "internal: split generating pass without its table");
       a.gen = *gen;
       PE_TRY(launch_split<true>(a, count, st));
     } else {

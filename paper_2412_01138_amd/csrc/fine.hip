@@ -302,6 +302,7 @@ static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *wo
       gf.C1 = gen->C1;
       gf.coef = gen->coef;
       gf.Cf = gen->Cf;
+      gf.Cft = gen->Cft;
       gf.M = gen->M;
     }
     PE_TRY(dst_fields_split(g, count, gen ? &gf : nullptr, static_cast<float *>(work0),
@@ -329,6 +330,7 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
     gs.C1 = g->dim >= 3 ? g->d_C[1] : nullptr;
     gs.coef = coef;
     gs.Cf = g->d_Cf;
+    gs.Cft = g->d_Cft;
     gs.Cl = g->d_C[g->dim - 1];
     gs.M = g->n_terms;
     return transform(g, count, &gs, work0, work1, result, st, stop_axis);
@@ -498,10 +500,11 @@ pe_status pe_fine_propagate(pe_grid g, int32_t n_slices, double t0, double dT, i
 
 size_t pe_project_workspace_bytes(pe_grid g) {
   if (!g) return 0;
-  size_t b = 8 * 256 + 2 * field_bytes(g);
+  size_t b = 10 * 256 + 2 * field_bytes(g);
   for (int a = 0; a < g->dim; ++a) b += sizeof(double) * PE_MAX_TERMS * g->ax[a].np;
   b += sizeof(double) * PE_MAX_TERMS + sizeof(DevTerm) * PE_MAX_TERMS;
   b += sizeof(double) * 2 * PE_MAX_TERMS * g->ax[g->dim - 1].Kh;
+  if (g->precision != PE_FP64) b += split_gen_table_bytes(g);
   return b;
 }
 
@@ -528,9 +531,10 @@ static pe_status project_impl(pe_grid g, int32_t n_terms, const pe_term *terms,
   for (int a = 0; a < g->dim; ++a) C[a] = ar.take<double>(size_t(M) * g->ax[a].np);
   double *coef = ar.take<double>(M);
   double *Cf = ar.take<double>(2 * size_t(M) * g->ax[g->dim - 1].Kh);
+  uint16_t *Cft = g->precision != PE_FP64 ? ar.take<uint16_t>(split_gen_table_bytes(g) / 2) : nullptr;
   char *w0 = ar.take<char>(field_bytes(g));
   char *w1 = ar.take<char>(field_bytes(g));
-  if (!coef || !Cf || !w0 || !w1)
+  if (!coef || !Cf || !w0 || !w1 || (g->precision != PE_FP64 && !Cft))
     return set_error(PE_E_WORKSPACE, "internal: workspace split failed");
   if (n_terms > 0) PE_TRY(build_loads(g, n_terms, terms, C, st));
   PE_TRY(upload_derived(g, der, n_terms, C, st));
@@ -542,11 +546,13 @@ static pe_status project_impl(pe_grid g, int32_t n_terms, const pe_term *terms,
   const bool fused = g->precision == PE_FP64 ? gen_supported(g, M) : gen_supported_split(g, M);
   if (fused) {
     PE_TRY(fold_table(g, C[g->dim - 1], M, Cf, st));
+    if (Cft) PE_TRY(split_gen_table(g, Cf, M, Cft, st));
     GenSrc gs;
     gs.C0 = g->dim >= 2 ? C[0] : nullptr;
     gs.C1 = g->dim >= 3 ? C[1] : nullptr;
     gs.coef = coef;
     gs.Cf = Cf;
+    gs.Cft = Cft;
     gs.Cl = C[g->dim - 1];
     gs.M = M;
     PE_TRY(transform(g, 1, &gs, w0, w1, &res, st));

@@ -330,6 +330,7 @@ static void free_grid_tables(pe_grid g) {
   }
   dev_free(g->d_terms);
   dev_free(g->d_Cf);
+  dev_free(g->d_Cft);
   dev_free(g->d_hats);
 }
 
@@ -685,6 +686,8 @@ static pe_status rebuild_terms(pe_grid g, hipStream_t st) {
   g->d_terms = nullptr;
   dev_free(g->d_Cf);
   g->d_Cf = nullptr;
+  dev_free(g->d_Cft);
+  g->d_Cft = nullptr;
   std::vector<DerivedTerm> der;
   boundary_terms(g, false, 0.0, der);
   const int mf = int(g->src_forcing.size());
@@ -706,6 +709,10 @@ static pe_status rebuild_terms(pe_grid g, hipStream_t st) {
   const Axis &last = g->ax[g->dim - 1];
   PE_HIP(hipMalloc(&g->d_Cf, sizeof(double) * 2 * size_t(n_terms) * last.Kh));
   PE_TRY(fold_table(g, g->d_C[g->dim - 1], n_terms, g->d_Cf, st));
+  if (g->precision != PE_FP64 && gen_supported_split(g, n_terms)) {
+    PE_HIP(hipMalloc(&g->d_Cft, split_gen_table_bytes(g)));
+    PE_TRY(split_gen_table(g, g->d_Cf, n_terms, g->d_Cft, st));
+  }
   for (int a = 0; a < g->dim; ++a) {
     const Axis &ax = g->ax[a];
     PE_HIP(hipMalloc(&g->d_spec[a], sizeof(double) * size_t(n_terms) * ax.n));

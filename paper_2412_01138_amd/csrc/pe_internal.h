@@ -156,6 +156,7 @@ struct pe_grid_s {
   double *d_Chat[PE_MAX_DIM] = {nullptr, nullptr, nullptr};
   double *d_C[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][np_a] 1D loads
   double *d_Cf = nullptr;        // [2][n_terms][Kh_last] folded last-axis loads
+  uint16_t *d_Cft = nullptr;     // split-bf16 grids: d_Cf as the generating pass reads it
   // spec_a[m][k] = sig_a(k) (S_a^T C_a[m])_k: spectral 1D loads of each term
   double *d_spec[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][n_a]
   // kernel timing (benchmark instrumentation)
@@ -254,6 +255,7 @@ struct GenSrc {
   const double *coef = nullptr;   // [count][M]
   const double *Cf = nullptr;     // [2][M][Kh_last]
   const double *Cl = nullptr;     // [M][np_last] (the FFT transform's generation)
+  const uint16_t *Cft = nullptr;  // split-bf16 grids: Cf^T as bf16 hi / lo (split_gen_table)
   int M = 0;
 };
 
@@ -272,8 +274,13 @@ struct GenSrcF {
   const double *C1 = nullptr;     // [M][np_1]  (d == 3)
   const double *coef = nullptr;   // [count][M]
   const double *Cf = nullptr;     // [2][M][Kh_last]
+  const uint16_t *Cft = nullptr;  // [2 hi/lo][2 halves][Kh_last][32] bf16 bits of Cf^T
   int M = 0;
 };
+// Cft of a split-bf16 grid from Cf ([2][M][Kh_last], M <= 32); terms
+// m >= M are zero.  split_gen_table_bytes is its size.
+size_t split_gen_table_bytes(pe_grid g);
+pe_status split_gen_table(pe_grid g, const double *Cf, int M, uint16_t *Cft, hipStream_t st);
 // (stop_axis = 1 leaves out the last pass, the one that contracts axis 0:
 // the batch is then [count][R][np_0] with the other axes transformed)
 pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,

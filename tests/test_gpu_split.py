@@ -57,6 +57,8 @@ def test_split_project(dim, n):
     (3, (100, 20, 9), 2, 2, 3, 4),
     (2, (200, 33), 1, 2, 4, 5),
     (3, (255, 9, 12), 1, 2, 3, 4),
+    # a last axis with Kh = 320 (the generating pass at any length)
+    (2, (20, 600), 2, 2, 3, 5),
 ])
 def test_split_fine_propagate(dim, n, N, J, s, modes):
     pe = _peifem()
