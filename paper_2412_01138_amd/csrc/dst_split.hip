@@ -94,9 +94,13 @@ __global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(GEN ? 3 : 1
     const int64_t nb = gridDim.x;
     if (nb % 8 == 0) bid = (bid % 8) * (nb / 8) + bid / 8;   // one field's tiles on one XCD
   }
-  // the two halves of a tile read the same rows: run them back to back
-  const int h = int(bid % 2);
-  bid /= 2;
+  // the two halves of a tile read the same rows: run them back to back (a
+  // generating block runs both, sharing its row factors)
+  int h = 0;
+  if (!GEN) {
+    h = int(bid % 2);
+    bid /= 2;
+  }
   const int tn = int(bid % a.tiles_n);
   bid /= a.tiles_n;
   const int tm = int(bid % a.tiles_m);
@@ -265,74 +269,78 @@ __global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(GEN ? 3 : 1
     }
   };
 
-  f4 acc[TM][TN];
+  for (int hh = 0; hh < (GEN ? 2 : 1); ++hh) {
+    if (GEN) h = hh;
+    f4 acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  const int nk = a.Kh / SKB;
-  load(0);
-  for (int kt = 0; kt < nk; ++kt) {
-    store(kt * SKB);
-    __syncthreads();
-    if (kt + 1 < nk) load((kt + 1) * SKB);
-    bf16x8 ah[TM], al[TM];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int row = wm * (BM / 2) + i * 16 + lr;
-      ah[i] = *reinterpret_cast<const bf16x8 *>(&sm.Ahi[row][lk * 8]);
-      al[i] = *reinterpret_cast<const bf16x8 *>(&sm.Alo[row][lk * 8]);
-    }
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = wn * 64 + j * 16 + lr;
-      const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sm.Bhi[col][lk * 8]);
-      const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sm.Blo[col][lk * 8]);
+    const int nk = a.Kh / SKB;
+    load(0);
+    for (int kt = 0; kt < nk; ++kt) {
+      store(kt * SKB);
+      __syncthreads();
+      if (kt + 1 < nk) load((kt + 1) * SKB);
+      bf16x8 ah[TM], al[TM];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        const int row = wm * (BM / 2) + i * 16 + lr;
+        ah[i] = *reinterpret_cast<const bf16x8 *>(&sm.Ahi[row][lk * 8]);
+        al[i] = *reinterpret_cast<const bf16x8 *>(&sm.Alo[row][lk * 8]);
       }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = wn * 64 + j * 16 + lr;
+        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sm.Bhi[col][lk * 8]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sm.Blo[col][lk * 8]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
 
-  // Output through a per-wave LDS scratch (the tile buffers are free after
-  // the last barrier): each 16-row group of the wave's 64 columns is written
-  // in MFMA layout, read back as rows and stored as float4 runs (256 B of
-  // one output row per 16 lanes instead of 64 B pieces of four rows).
-  float *Y = a.Y + f * int64_t(a.np) * a.R;
-  constexpr int SCR = 68;   // scratch row stride (floats)
-  static_assert(sizeof(SSmem<BM>) >= 4 * 16 * SCR * sizeof(float), "scratch fits");
-  float *scr = reinterpret_cast<float *>(&sm) + wave * (16 * SCR);
-  const bool vec_ok = (a.R & 3) == 0;
+    // Output through a per-wave LDS scratch (the tile buffers are free after
+    // the last barrier): each 16-row group of the wave's 64 columns is written
+    // in MFMA layout, read back as rows and stored as float4 runs (256 B of
+    // one output row per 16 lanes instead of 64 B pieces of four rows).
+    float *Y = a.Y + f * int64_t(a.np) * a.R;
+    constexpr int SCR = 68;   // scratch row stride (floats)
+    static_assert(sizeof(SSmem<BM>) >= 4 * 16 * SCR * sizeof(float), "scratch fits");
+    float *scr = reinterpret_cast<float *>(&sm) + wave * (16 * SCR);
+    const bool vec_ok = (a.R & 3) == 0;
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
+    for (int i = 0; i < TM; ++i) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) scr[(4 * lk + r) * SCR + j * 16 + lr] = acc[i][j][r];
-    wave_sync();
+        for (int r = 0; r < 4; ++r) scr[(4 * lk + r) * SCR + j * 16 + lr] = acc[i][j][r];
+      wave_sync();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int rr = (lane >> 4) + 4 * q, c4 = (lane & 15) * 4;
-      const int row = m0 + wm * (BM / 2) + i * 16 + rr;
-      const int64_t col = n0 + wn * 64 + c4;
-      if (row >= a.Kh || col >= a.R) continue;
-      const f4 v = *reinterpret_cast<const f4 *>(&scr[rr * SCR + c4]);
-      float *dst = Y + int64_t(h * a.Kh + row) * a.R + col;
-      if (vec_ok) {
-        // R % 4 == 0: col + 3 < R; streaming store (read once by the next pass)
-        __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(dst));
-      } else {
+      for (int q = 0; q < 4; ++q) {
+        const int rr = (lane >> 4) + 4 * q, c4 = (lane & 15) * 4;
+        const int row = m0 + wm * (BM / 2) + i * 16 + rr;
+        const int64_t col = n0 + wn * 64 + c4;
+        if (row >= a.Kh || col >= a.R) continue;
+        const f4 v = *reinterpret_cast<const f4 *>(&scr[rr * SCR + c4]);
+        float *dst = Y + int64_t(h * a.Kh + row) * a.R + col;
+        if (vec_ok) {
+          // R % 4 == 0: col + 3 < R; streaming store (read once by the next pass)
+          __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(dst));
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (col + e < a.R) dst[e] = v[e];
+          for (int e = 0; e < 4; ++e)
+            if (col + e < a.R) dst[e] = v[e];
+        }
       }
+      wave_sync();
     }
-    wave_sync();
+    if (GEN && hh == 0) __syncthreads();   // the scratch is the next half's tile buffer
   }
 }
 
@@ -341,7 +349,7 @@ constexpr int64_t SMAX_BLOCKS = (int64_t(1) << 24) - 1;
 
 template <int BM, bool GEN>
 static pe_status launch_split_t(SplitArgs a, int64_t count, hipStream_t st) {
-  const int64_t per_f = int64_t(a.tiles_m) * a.tiles_n * 2;
+  const int64_t per_f = int64_t(a.tiles_m) * a.tiles_n * (GEN ? 1 : 2);
   if (per_f > SMAX_BLOCKS) return set_error(PE_E_ARG, "internal: split grid too large");
   const int64_t max_f = std::max<int64_t>(1, SMAX_BLOCKS / per_f);
   for (int64_t f0 = 0; f0 < count; f0 += max_f) {
