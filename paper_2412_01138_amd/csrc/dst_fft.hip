@@ -504,29 +504,19 @@ __global__ void k_fft_tables(FftFinalArgs a, int L, const double *__restrict__ s
 // (position 0), sqrt(2/N) Re X_k (cos k, position 2k - 1), -sqrt(2/N) Im X_k
 // (sin k, position 2k) and Re X_{N/2} / sqrt(N) (position N - 1).
 template <int N, bool CONTIG>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_pass_periodic(FftPassArgs a) {
+__device__ __forceinline__ int64_t periodic_line_base(const FftPassArgs &a, int64_t ln) {
+  if (CONTIG) return ln * N;
+  const int64_t o = ln / a.inner;
+  return o * N * a.inner + (ln - o * a.inner);
+}
+
+// The block's lines in Zs (line l: FFT l % P, real part for l < P): FFT
+// and the cos/sin coefficients out.
+template <int N, bool CONTIG>
+__device__ __forceinline__ void periodic_fft_out(c2 *Zs, const FftPassArgs &a, int64_t l0, int t) {
   using Sh = Shape<N>;
   constexpr int LINES = Sh::LINES;
   constexpr int PER_THREAD = LINES * N / FFT_THREADS;
-  __shared__ c2 Zs[Sh::P * Sh::FS];
-  double *Zd = reinterpret_cast<double *>(Zs);
-  const int t = threadIdx.x;
-  const int64_t l0 = int64_t(blockIdx.x) * LINES;
-  auto line_base = [&](int64_t ln) -> int64_t {
-    if (CONTIG) return ln * N;
-    const int64_t o = ln / a.inner;
-    return o * N * a.inner + (ln - o * a.inner);
-  };
-#pragma unroll
-  for (int k = 0; k < PER_THREAD; ++k) {
-    const int e = t + k * FFT_THREADS;
-    const int l = CONTIG ? e / N : e % LINES;
-    const int j = CONTIG ? e % N : e / LINES;
-    const int64_t ln = l0 + l;
-    const double x = ln < a.nlines ? a.in[line_base(ln) + int64_t(j) * a.inner] : 0.0;
-    Zd[2 * ((l % Sh::P) * Sh::FS + pidx(j)) + l / Sh::P] = x;
-  }
-  __syncthreads();
   c2 v[8];
   fft_run<N, 1, false>(Zs + (t / Sh::TF) * Sh::FS, a.tw, t % Sh::TF, v);
   __syncthreads();
@@ -545,8 +535,97 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_pass_periodic(FftPassArgs a
     const double re = part ? 0.5 * (Zk.y + Zm.y) : 0.5 * (Zk.x + Zm.x);
     const double im = part ? -0.5 * (Zk.x - Zm.x) : 0.5 * (Zk.y - Zm.y);
     const double y = (q == 0 || q == N - 1) ? re * s0 : ((q & 1) ? re * s1 : -im * s1);
-    a.out[line_base(ln) + int64_t(q) * a.inner] = y;
+    a.out[periodic_line_base<N, CONTIG>(a, ln) + int64_t(q) * a.inner] = y;
   }
+}
+
+template <int N, bool CONTIG>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_pass_periodic(FftPassArgs a) {
+  using Sh = Shape<N>;
+  constexpr int LINES = Sh::LINES;
+  constexpr int PER_THREAD = LINES * N / FFT_THREADS;
+  __shared__ c2 Zs[Sh::P * Sh::FS];
+  double *Zd = reinterpret_cast<double *>(Zs);
+  const int t = threadIdx.x;
+  const int64_t l0 = int64_t(blockIdx.x) * LINES;
+#pragma unroll
+  for (int k = 0; k < PER_THREAD; ++k) {
+    const int e = t + k * FFT_THREADS;
+    const int l = CONTIG ? e / N : e % LINES;
+    const int j = CONTIG ? e % N : e / LINES;
+    const int64_t ln = l0 + l;
+    const double x =
+        ln < a.nlines ? a.in[periodic_line_base<N, CONTIG>(a, ln) + int64_t(j) * a.inner] : 0.0;
+    Zd[2 * ((l % Sh::P) * Sh::FS + pidx(j)) + l / Sh::P] = x;
+  }
+  __syncthreads();
+  periodic_fft_out<N, CONTIG>(Zs, a, l0, t);
+}
+
+// Generating pass on a periodic last axis (contiguous lines): the load value
+// of node j of line (f, r) is sum_m coef[f][m] pre_r[m] Cl[m][j], as in
+// k_fft_gen, formed in registers and then transformed as in
+// k_fft_pass_periodic.  The factor table pre[l][m] borrows the FFT buffer
+// (it is dead once the values are formed).  MT: the terms rounded up.
+template <int N, int MT>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_gen_periodic(FftPassArgs a) {
+  using Sh = Shape<N>;
+  constexpr int LINES = Sh::LINES;
+  constexpr int PER_THREAD = LINES * N / FFT_THREADS;
+  // node positions of a thread: t mod N when N divides the block, else
+  // t + FFT_THREADS jd (element k has jd = k mod JD, line k / JD)
+  constexpr int JD = N > FFT_THREADS ? N / FFT_THREADS : 1;
+  static_assert(N % FFT_THREADS == 0 || FFT_THREADS % N == 0, "node mapping");
+  static_assert(LINES * MT <= 2 * Sh::P * Sh::FS, "the factors fit the FFT buffer");
+  __shared__ c2 Zs[Sh::P * Sh::FS];
+  double *Zd = reinterpret_cast<double *>(Zs);
+  double *pre = Zd;
+  const int t = threadIdx.x;
+  const int64_t l0 = int64_t(blockIdx.x) * LINES;
+  for (int e = t; e < LINES * a.M; e += FFT_THREADS) {
+    const int l = e / a.M, m = e - l * a.M;
+    const int64_t ln = l0 + l;
+    double v = 0.0;
+    if (ln < a.nlines) {
+      const int64_t f = ln / a.rows;
+      const int64_t r = ln - f * a.rows;
+      v = a.coef[f * a.M + m];
+      if (a.d == 2) v *= a.C0[int64_t(m) * a.np0 + r];
+      if (a.d == 3) {
+        v *= a.C0[int64_t(m) * a.np0 + r / a.np1];
+        v *= a.C1[int64_t(m) * a.np1 + r % a.np1];
+      }
+    }
+    pre[l * MT + m] = v;
+  }
+  __syncthreads();
+  double x[PER_THREAD];
+#pragma unroll
+  for (int jd = 0; jd < JD; ++jd) {
+    const int j = JD > 1 ? t + jd * FFT_THREADS : t % N;
+    double cl[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) cl[m] = m < a.M ? a.Cl[int64_t(m) * N + j] : 0.0;
+#pragma unroll
+    for (int k = jd; k < PER_THREAD; k += JD) {
+      const int l = (t + k * FFT_THREADS) / N;
+      const double *pl = pre + l * MT;
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        if (m < a.M) s += pl[m] * cl[m];
+      x[k] = s;
+    }
+  }
+  __syncthreads();   // the factors are dead: the buffer takes the lines
+#pragma unroll
+  for (int k = 0; k < PER_THREAD; ++k) {
+    const int e = t + k * FFT_THREADS;
+    const int l = e / N, j = e % N;
+    Zd[2 * ((l % Sh::P) * Sh::FS + pidx(j)) + l / Sh::P] = x[k];
+  }
+  __syncthreads();
+  periodic_fft_out<N, true>(Zs, a, l0, t);
 }
 
 // ------------------------------------------------------------------ host
@@ -559,8 +638,8 @@ bool fft_axis_ok(int n) {
 bool fft_periodic_ok(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
 
 bool fft_gen_supported(pe_grid g, int n_terms) {
-  // the generating pass builds the odd extension of Dirichlet lines
-  return n_terms >= 1 && n_terms <= FFT_GEN_MAX_TERMS && !g->ax[g->dim - 1].periodic;
+  (void)g;
+  return n_terms >= 1 && n_terms <= FFT_GEN_MAX_TERMS;
 }
 
 __global__ void k_fft_twiddles(int N, c2 *tw) {
@@ -602,9 +681,17 @@ static void launch_pass(const FftPassArgs &a, bool gen, bool contig, hipStream_t
 }
 
 template <int N>
-static void launch_pass_periodic(const FftPassArgs &a, bool contig, hipStream_t st) {
+static void launch_pass_periodic(const FftPassArgs &a, bool gen, bool contig, hipStream_t st) {
   const unsigned blocks = unsigned((a.nlines + Shape<N>::LINES - 1) / Shape<N>::LINES);
-  if (contig)
+  if (gen) {
+    // (the generating pass runs on the last axis, whose lines are contiguous)
+    if (a.M <= 8)
+      k_fft_gen_periodic<N, 8><<<blocks, FFT_THREADS, 0, st>>>(a);
+    else if (a.M <= 16)
+      k_fft_gen_periodic<N, 16><<<blocks, FFT_THREADS, 0, st>>>(a);
+    else
+      k_fft_gen_periodic<N, FFT_GEN_MAX_TERMS><<<blocks, FFT_THREADS, 0, st>>>(a);
+  } else if (contig)
     k_fft_pass_periodic<N, true><<<blocks, FFT_THREADS, 0, st>>>(a);
   else
     k_fft_pass_periodic<N, false><<<blocks, FFT_THREADS, 0, st>>>(a);
@@ -647,13 +734,13 @@ pe_status dst_fields_fft(pe_grid g, int64_t count, const GenSrc *gen, double *bu
                   gen_pass ? fb : 2.0 * fb, st);
     const bool contig = inner == 1;
     if (ax.periodic) {
-      if (gen_pass) return set_error(PE_E_ARG, "internal: no generating pass on a periodic axis");
+      if (gen_pass && !contig) return set_error(PE_E_ARG, "internal: generating pass on strided lines");
       switch (N) {
-        case 64: launch_pass_periodic<64>(a, contig, st); break;
-        case 128: launch_pass_periodic<128>(a, contig, st); break;
-        case 256: launch_pass_periodic<256>(a, contig, st); break;
-        case 512: launch_pass_periodic<512>(a, contig, st); break;
-        case 1024: launch_pass_periodic<1024>(a, contig, st); break;
+        case 64: launch_pass_periodic<64>(a, gen_pass, contig, st); break;
+        case 128: launch_pass_periodic<128>(a, gen_pass, contig, st); break;
+        case 256: launch_pass_periodic<256>(a, gen_pass, contig, st); break;
+        case 512: launch_pass_periodic<512>(a, gen_pass, contig, st); break;
+        case 1024: launch_pass_periodic<1024>(a, gen_pass, contig, st); break;
         default: return set_error(PE_E_ARG, "internal: periodic FFT length %d", N);
       }
       PE_HIP(hipGetLastError());

@@ -23,8 +23,10 @@
 // LDS holds only its tiles), B = the wave's row factors (registers), C = the
 // tile transposed, so a lane holds four consecutive p of one row.
 //
-// Block: 256 threads = 4 waves (2 x 2), tile BM (modes) x 128 (rows r),
-// k-step 32, single LDS buffer with register prefetch.
+// Block: 256 threads = 4 waves (2 x 2), tile BM (modes) x 128 (rows r) of
+// one half (a generating block computes both halves of its tile in turn,
+// forming the row factors once), k-step 32, single LDS buffer with register
+// prefetch.
 // MFMA f32 16x16x32 bf16 lane layout: lane l supplies A[l%16][8(l/16) + e]
 // and B[8(l/16) + e][l%16] (e = 0..7) and receives C[4(l/16) + r][l%16].
 #include <algorithm>

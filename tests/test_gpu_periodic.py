@@ -84,8 +84,8 @@ def _apply(mats, X):
     return X
 
 
-def _case(dim, n, per, seed, N=2, J=3, s=3):
-    prob = wl.tiny_problem(dim, n, seed=seed, N=N, J=J, s=s, T=0.9, u0_modes=1)
+def _case(dim, n, per, seed, N=2, J=3, s=3, n_modes=3):
+    prob = wl.tiny_problem(dim, n, seed=seed, N=N, J=J, s=s, T=0.9, u0_modes=1, n_modes=n_modes)
     return prob.with_(periodic=tuple(per))
 
 
@@ -96,18 +96,22 @@ def _bases(prob, d):
     return Ql, T
 
 
-@pytest.mark.parametrize("dim,n,per", [
-    (1, (64,), (True,)),
-    (1, (1024,), (True,)),
-    (2, (128, 63), (True, False)),
-    (2, (63, 256), (False, True)),
-    (2, (128, 128), (True, True)),
-    (3, (64, 63, 128), (True, False, True)),
+# (a periodic last axis takes the generating FFT pass: loads of 8, 16 or 32
+# terms formed in registers, every FFT length)
+@pytest.mark.parametrize("dim,n,per,modes", [
+    (1, (64,), (True,), 3),
+    (1, (1024,), (True,), 3),
+    (2, (128, 63), (True, False), 3),
+    (2, (63, 256), (False, True), 3),
+    (2, (63, 512), (False, True), 12),
+    (2, (128, 128), (True, True), 20),
+    (3, (64, 63, 128), (True, False, True), 3),
+    (3, (63, 64, 64), (False, True, True), 9),
 ])
-def test_periodic_fine_propagate(dim, n, per):
+def test_periodic_fine_propagate(dim, n, per, modes):
     pe = _pe()
-    print(f"periodic fine propagate dim {dim} n {n} periodic {per}", flush=True)
-    prob = _case(dim, n, per, seed=5)
+    print(f"periodic fine propagate dim {dim} n {n} periodic {per} terms {modes}", flush=True)
+    prob = _case(dim, n, per, seed=5, n_modes=modes)
     d = Discretization(prob)
     Ql, T = _bases(prob, d)
     rng = np.random.default_rng(6)

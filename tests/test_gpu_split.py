@@ -35,7 +35,8 @@ def _dev32(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
 
 
-@pytest.mark.parametrize("dim,n", [(1, (63,)), (2, (37, 70)), (3, (9, 33, 20)), (3, (31, 63, 17))])
+@pytest.mark.parametrize("dim,n", [(1, (63,)), (2, (37, 70)), (3, (9, 33, 20)), (3, (31, 63, 17)),
+                                   (2, (20, 600))])
 def test_split_project(dim, n):
     pe = _peifem()
     prob = wl.tiny_problem(dim, n, seed=12, u0_modes=3, precision="split_bf16")
