@@ -353,6 +353,7 @@ struct FftFinalArgs {
   int64_t inner, dof;
   int nslices, strips, jc, s;
   int n1, Kh1, n2, Kh2, np2, d;
+  int per1, per2;         // inner axes periodic (position = mode, no fold)
 };
 
 // state index of (mode m, padded column c) or -1 at pads (DOF < 2^31 here)
@@ -360,11 +361,12 @@ __device__ __forceinline__ int fft_state_index(const FftFinalArgs &a, int L, int
   if (m < 0 || m >= L - 1) return -1;
   int k1, k2 = 0;
   if (a.d == 3) {
-    k1 = unfold_pos(int(c / a.np2), a.Kh1);
-    k2 = unfold_pos(int(c % a.np2), a.Kh2);
+    const int p1 = int(c / a.np2), p2 = int(c % a.np2);
+    k1 = a.per1 ? p1 : unfold_pos(p1, a.Kh1);
+    k2 = a.per2 ? p2 : unfold_pos(p2, a.Kh2);
     if (k2 >= a.n2) return -1;
   } else {
-    k1 = unfold_pos(int(c), a.Kh1);
+    k1 = a.per1 ? int(c) : unfold_pos(int(c), a.Kh1);
   }
   if (k1 >= a.n1) return -1;
   return (m * a.n1 + k1) * (a.d == 3 ? a.n2 : 1) + k2;
@@ -628,6 +630,122 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_gen_periodic(FftPassArgs a)
   periodic_fft_out<N, true>(Zs, a, l0, t);
 }
 
+// Axis-0 periodic pass fused with the update.  Block = (slice nl, strip of
+// LINES columns); thread t owns column l = t mod LINES and the PT = 16
+// consecutive positions q0 + k, q0 = 16 (t / LINES), of it on axis 0 (so its
+// loads, LDS offsets and tables are fixed offsets from one base each), loads
+// those nodes of every field (adjacent columns across threads), and after
+// the block's FFTs reads its coefficients as k_fft_pass_periodic does and
+// updates its states (eq. 2.6; the tables carry sigma and the cos/sin
+// scale).
+constexpr int FFTP_PT = 16;
+
+template <int N>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_final_periodic(FftFinalArgs a) {
+  using Sh = Shape<N>;
+  constexpr int LINES = Sh::LINES;
+  constexpr int PT = FFTP_PT;
+  static_assert(LINES * N == PT * FFT_THREADS, "16 positions per thread");
+  __shared__ c2 Zs[Sh::P * Sh::FS];
+  double *Zd = reinterpret_cast<double *>(Zs);
+  const int t = threadIdx.x;
+  const int nl = int(blockIdx.x % a.nslices);
+  const int strip = int(blockIdx.x / a.nslices);
+  const int nf = a.jc * a.s;
+  const int l = t % LINES, lp = l % Sh::P, part = l / Sh::P;
+  const int q0 = PT * (t / LINES);
+  const int64_t col = int64_t(strip) * LINES + l;
+  const int inner = int(a.inner);
+
+  double W[PT];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int ki = fft_state_index(a, N + 1, q0 + k, col);
+    W[k] = (a.Uin && ki >= 0) ? a.Uin[int64_t(nl) * a.dof + ki] : 0.0;
+  }
+  const double *Xs = a.X + int64_t(nl) * nf * N * a.inner + int64_t(q0) * inner + col;
+  const double *Tl = a.Tf + (int64_t(strip) * (1 + a.s) * FFT_THREADS + t) * PT;
+  c2 *Zl = Zs + lp * Sh::FS;
+  double S[PT];
+  auto load = [&](int e) {
+    const double *Xf = Xs + int64_t(e) * N * inner;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) S[k] = Xf[k * inner];
+  };
+  load(0);
+  for (int e = 0; e < nf; ++e) {
+#pragma unroll
+    for (int k = 0; k < PT; ++k) reinterpret_cast<double *>(Zl + pidx(q0 + k))[part] = S[k];
+    __syncthreads();
+    if (e + 1 < nf) load(e + 1);   // in flight during the transform
+    c2 v[8];
+    fft_run<N, 1, false>(Zs + (t / Sh::TF) * Sh::FS, a.tw, t % Sh::TF, v);
+    __syncthreads();
+    const int i = e % a.s;
+    const double *Te = Tl, *Ti = Tl + int64_t(1 + i) * FFT_THREADS * PT;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int q = q0 + k;
+      const int kk = q == 0 ? 0 : (q == N - 1 ? N / 2 : (q + 1) / 2);
+      const c2 Zk = Zl[pidx(kk)];
+      const c2 Zm = Zl[pidx((N - kk) % N)];
+      const double re = part ? Zk.y + Zm.y : Zk.x + Zm.x;
+      const double im = part ? Zm.x - Zk.x : Zk.y - Zm.y;
+      const double y = (q == 0 || q == N - 1 || (q & 1)) ? re : -im;
+      double w = W[k];
+      if (i == 0) w = Te[k] * w;
+      W[k] = w + Ti[k] * y;
+    }
+    __syncthreads();   // every wave is done with LDS before the next strip lands
+  }
+  double *Uo = a.Uout + int64_t(nl) * a.dof;
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int ki = fft_state_index(a, N + 1, q0 + k, col);
+    if (ki >= 0) Uo[ki] = W[k];
+  }
+}
+
+// Tables of k_fft_final_periodic: Tf[strip][tbl][t][k], tbl 0 = E, tbl 1 + i
+// = b_i sigma times the coefficient scale of position q (1/(2 sqrt N) for
+// the constant and alternating modes, 1/sqrt(2N) for cos/sin: the kernel
+// forms twice Re X_k or -Im X_k), zero at pads.
+__global__ void k_fft_tables_periodic(FftFinalArgs a, int N, int lines, const double *__restrict__ sig0,
+                                      const double *__restrict__ sig1,
+                                      const double *__restrict__ sig2,
+                                      const double *__restrict__ E, const double *__restrict__ B,
+                                      double *Tf) {
+  const int64_t total = int64_t(a.strips) * (1 + a.s) * FFT_THREADS * FFTP_PT;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(e % FFTP_PT);
+    const int t = int((e / FFTP_PT) % FFT_THREADS);
+    const int tbl = int((e / (int64_t(FFTP_PT) * FFT_THREADS)) % (1 + a.s));
+    const int64_t strip = e / (int64_t(FFTP_PT) * FFT_THREADS * (1 + a.s));
+    const int q = FFTP_PT * (t / lines) + k;
+    const int64_t col = strip * lines + t % lines;
+    const int64_t ki = fft_state_index(a, N + 1, q, col);
+    double v = 0.0;
+    if (ki >= 0) {
+      if (tbl == 0) {
+        v = E[ki];
+      } else {
+        const int64_t rest = ki % (a.dof / N);
+        double sig = sig0[q];
+        if (a.d == 3) {
+          sig *= sig1[rest / a.n2];
+          sig *= sig2[rest % a.n2];
+        } else {
+          sig *= sig1[rest];
+        }
+        const double sc = (q == 0 || q == N - 1) ? 0.5 / sqrt(double(N)) : 1.0 / sqrt(2.0 * N);
+        v = B[int64_t(tbl - 1) * a.dof + ki] * sig * sc;
+      }
+    }
+    Tf[e] = v;
+  }
+}
+
 // ------------------------------------------------------------------ host
 
 bool fft_axis_ok(int n) {
@@ -776,27 +894,40 @@ static FftFinalArgs final_args(pe_grid g, int s) {
   } else {
     a.n2 = a.Kh2 = a.np2 = 1;
   }
+  a.per1 = g->ax[1].periodic ? 1 : 0;
+  a.per2 = g->dim == 3 && g->ax[2].periodic ? 1 : 0;
   a.s = s;
-  const int N = 2 * (x0.n + 1);
+  const int N = x0.periodic ? x0.n : 2 * (x0.n + 1);
   a.strips = int(a.inner / (2 * (FFT_POINTS / N)));
   a.tw = reinterpret_cast<const c2 *>(x0.d_tw);
   return a;
 }
 
 bool fft_final_supported(pe_grid g) {
-  for (int a = 0; a < g->dim; ++a)
-    if (g->ax[a].periodic) return false;   // the fused kernel reads folded Dirichlet modes
-  return g->dim >= 2 && g->dofp < (int64_t(1) << 31) && g->dof < (int64_t(1) << 31);
+  if (g->dim < 2 || g->dofp >= (int64_t(1) << 31) || g->dof >= (int64_t(1) << 31)) return false;
+  const Axis &x0 = g->ax[0];
+  const int N = x0.periodic ? x0.n : 2 * (x0.n + 1);
+  // a block takes 2 FFT_POINTS / N whole columns
+  return (g->dofp / x0.np) % (2 * (FFT_POINTS / N)) == 0;
 }
 
 pe_status fft_tables(pe_grid g, int s, const double *E, const double *B, double *Tf,
                      hipStream_t st) {
   FftFinalArgs a = final_args(g, s);
+  const double *sig2 = g->dim > 2 ? g->ax[2].d_sig : nullptr;
+  if (g->ax[0].periodic) {
+    const int N = g->ax[0].n, lines = 2 * (FFT_POINTS / N);
+    const int64_t n = int64_t(a.strips) * (1 + s) * FFT_THREADS * FFTP_PT;
+    const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
+    k_fft_tables_periodic<<<blocks, 256, 0, st>>>(a, N, lines, g->ax[0].d_sig, g->ax[1].d_sig,
+                                                   sig2, E, B, Tf);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+  }
   const int L = g->ax[0].n + 1;
   const int64_t n = int64_t(a.strips) * (1 + s) * 8 * FFT_THREADS;
   const unsigned blocks = unsigned(std::min<int64_t>((n + 255) / 256, 65536));
-  k_fft_tables<<<blocks, 256, 0, st>>>(a, L, g->ax[0].d_sig, g->ax[1].d_sig,
-                                        g->dim > 2 ? g->ax[2].d_sig : nullptr, E, B, Tf);
+  k_fft_tables<<<blocks, 256, 0, st>>>(a, L, g->ax[0].d_sig, g->ax[1].d_sig, sig2, E, B, Tf);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }
@@ -811,7 +942,7 @@ pe_status fft_final_update(pe_grid g, const FieldBatch &b, const double *X, cons
   a.jc = b.jc;
   a.nslices = b.nslices;
   const Axis &x0 = g->ax[0];
-  const int N = 2 * (x0.n + 1);
+  const int N = x0.periodic ? x0.n : 2 * (x0.n + 1);
   const int64_t blocks = int64_t(b.nslices) * a.strips;
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: FFT grid too large");
   const double fields = double(b.count());
@@ -819,6 +950,19 @@ pe_status fft_final_update(pe_grid g, const FieldBatch &b, const double *X, cons
   const double bytes = fields * double(g->dof) * 8.0 + 2.0 * b.nslices * double(g->dof) * 8.0 +
                        double(1 + b.s) * double(g->dof) * 8.0;
   TimedScope ts(g, PE_K_MID_UPDATE, flops, bytes, st);
+  const dim3 grid = dim3(unsigned(blocks));
+  if (x0.periodic) {
+    switch (N) {
+      case 64: k_fft_final_periodic<64><<<grid, FFT_THREADS, 0, st>>>(a); break;
+      case 128: k_fft_final_periodic<128><<<grid, FFT_THREADS, 0, st>>>(a); break;
+      case 256: k_fft_final_periodic<256><<<grid, FFT_THREADS, 0, st>>>(a); break;
+      case 512: k_fft_final_periodic<512><<<grid, FFT_THREADS, 0, st>>>(a); break;
+      case 1024: k_fft_final_periodic<1024><<<grid, FFT_THREADS, 0, st>>>(a); break;
+      default: return set_error(PE_E_ARG, "internal: periodic FFT length %d", N);
+    }
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+  }
   switch (N) {
     case 128: k_fft_final<128><<<dim3(unsigned(blocks)), FFT_THREADS, 0, st>>>(a); break;
     case 256: k_fft_final<256><<<dim3(unsigned(blocks)), FFT_THREADS, 0, st>>>(a); break;

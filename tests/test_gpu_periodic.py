@@ -126,6 +126,26 @@ def test_periodic_fine_propagate(dim, n, per, modes):
     assert rel(_apply(Ql, out), d.grid.to_nodal(ref)) <= oracle_bar(n, per)
 
 
+@pytest.mark.parametrize("dim,n,per", [(2, (128, 63), (True, False)), (2, (64, 128), (True, True)),
+                                       (2, (63, 256), (False, True)), (3, (64, 63, 128), (True, False, True))])
+def test_periodic_fused_update_matches_separate(dim, n, per):
+    """The axis-0 pass fused with the update (periodic or Dirichlet axis 0)
+    against the separate pass + update, which run when the workspace has no
+    room for the update tables: equal to rounding."""
+    pe = _pe()
+    print(f"periodic fused vs separate dim {dim} n {n} periodic {per}", flush=True)
+    prob = _case(dim, n, per, seed=13, N=2, J=3, s=3, n_modes=5)
+    rng = np.random.default_rng(14)
+    U = torch.as_tensor(rng.normal(size=(prob.N,) + prob.n), device="cuda:0")
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    fused = g.fine_propagate(U, prob.t0, prob.dT, prob.J, prob.c_fine, E, B).cpu().numpy()
+    per_field = g.fine_workspace_bytes(2) - g.fine_workspace_bytes(1)
+    work = g.workspace(3 * 256 + per_field * prob.q)
+    sep = g.fine_propagate(U, prob.t0, prob.dT, prob.J, prob.c_fine, E, B, work=work).cpu().numpy()
+    assert rel(fused, sep) <= 1e-14
+
+
 @pytest.mark.parametrize("dim,n,per", [(1, (128,), (True,)), (2, (128, 63), (True, False)),
                                        (2, (64, 128), (True, True))])
 def test_periodic_project(dim, n, per):
