@@ -96,8 +96,9 @@ def _bases(prob, d):
     return Ql, T
 
 
-# (a periodic last axis takes the generating FFT pass: loads of 8, 16 or 32
-# terms formed in registers, every FFT length)
+# (a periodic last axis takes the generating FFT pass: loads of up to 32
+# terms formed in registers, every FFT length; 40 terms take the separate
+# quadrature and the plain periodic pass)
 @pytest.mark.parametrize("dim,n,per,modes", [
     (1, (64,), (True,), 3),
     (1, (1024,), (True,), 3),
@@ -107,6 +108,7 @@ def _bases(prob, d):
     (2, (128, 128), (True, True), 20),
     (3, (64, 63, 128), (True, False, True), 3),
     (3, (63, 64, 64), (False, True, True), 9),
+    (2, (64, 128), (True, True), 40),      # more terms than the generating pass takes
 ])
 def test_periodic_fine_propagate(dim, n, per, modes):
     pe = _pe()
