@@ -567,8 +567,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_pass_periodic(FftPassArgs a
 // Generating pass on a periodic last axis (contiguous lines): the load value
 // of node j of line (f, r) is sum_m coef[f][m] pre_r[m] Cl[m][j], as in
 // k_fft_gen, formed in registers and then transformed as in
-// k_fft_pass_periodic.  The factor table pre[l][m] borrows the FFT buffer
-// (it is dead once the values are formed).  MT: the terms rounded up.
+// k_fft_pass_periodic (Cl rows have N entries: a periodic axis has np = n).
+// The factor table pre[l][m] borrows the FFT buffer (it is dead once the
+// values are formed).  MT: the terms rounded up.
 template <int N, int MT>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_gen_periodic(FftPassArgs a) {
   using Sh = Shape<N>;
