@@ -109,6 +109,7 @@ def _bases(prob, d):
     (3, (64, 63, 128), (True, False, True), 3),
     (3, (63, 64, 64), (False, True, True), 9),
     (2, (64, 128), (True, True), 40),      # more terms than the generating pass takes
+    (2, (1024, 63), (True, False), 4),     # the fused axis-0 update at the longest period
 ])
 def test_periodic_fine_propagate(dim, n, per, modes):
     pe = _pe()
@@ -129,7 +130,8 @@ def test_periodic_fine_propagate(dim, n, per, modes):
 
 
 @pytest.mark.parametrize("dim,n,per", [(2, (128, 63), (True, False)), (2, (64, 128), (True, True)),
-                                       (2, (63, 256), (False, True)), (3, (64, 63, 128), (True, False, True))])
+                                       (2, (63, 256), (False, True)), (3, (64, 63, 128), (True, False, True)),
+                                       (2, (512, 63), (True, False)), (2, (1024, 63), (True, False))])
 def test_periodic_fused_update_matches_separate(dim, n, per):
     """The axis-0 pass fused with the update (periodic or Dirichlet axis 0)
     against the separate pass + update, which run when the workspace has no
