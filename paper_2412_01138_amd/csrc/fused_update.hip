@@ -394,6 +394,8 @@ __global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
   // The kernel is bound by HBM: DEPTH register sets keep the strips of the
   // next DEPTH fields in flight (field e + 1 + DEPTH is loaded right after
   // field e + 1 is stashed), so each load has DEPTH fields of time to land.
+  // The strips are read once: streaming (nontemporal) loads leave L2 to the
+  // update tables, which every step of the slice reads again.
   const int lrow = t / CPR, lc = t % CPR, p0 = 4 * lc;
   const bool active = t < ITEMS;
   const int64_t fstride = int64_t(a.I) * (2 * KH);
@@ -405,10 +407,10 @@ __global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
   auto load = [&](Raw &R, int e) {
     if (!active || e >= nf) return;
     const float *x = Xr + e * fstride;
-    R.xa = *reinterpret_cast<const f4_t *>(x + p0);
+    R.xa = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(x + p0));
     const int mb = a.n0 - 4 - p0;   // x[n-1-p0-e], e = 0..3: one ascending run
     if (mb >= 0) {
-      const f4u_t v = *reinterpret_cast<const f4u_t *>(x + mb);
+      const f4u_t v = __builtin_nontemporal_load(reinterpret_cast<const f4u_t *>(x + mb));
       R.xb = f4_t{v.w, v.z, v.y, v.x};
     } else {
 #pragma unroll
