@@ -172,14 +172,6 @@ class Grid:
     def mass_apply(self, U: np.ndarray) -> np.ndarray:
         return self._mode_product(U, [ax.M for ax in self.axes])
 
-    def stiffness_apply(self, U: np.ndarray) -> np.ndarray:
-        """A U with A = sum_a M_1 x .. x A_a x .. x M_d (without D)."""
-        out = np.zeros_like(U)
-        for a in range(self.dim):
-            mats = [ax.A if b == a else ax.M for b, ax in enumerate(self.axes)]
-            out = out + self._mode_product(U, mats)
-        return out
-
     def dense_mass(self) -> np.ndarray:
         out = np.ones((1, 1))
         for ax in self.axes:

@@ -92,13 +92,3 @@ def tables(z: np.ndarray, c: Sequence[float]):
         B[:, k] = b
     return E[inv].reshape(z.shape), B[:, inv].reshape((s,) + z.shape)
 
-
-def phi_table(z: np.ndarray, j: int) -> np.ndarray:
-    """phi_j(-z) for an array of z (float64)."""
-    out = np.empty(np.shape(z))
-    flat = np.ravel(z)
-    res = out.reshape(-1)
-    for k, zk in enumerate(flat):
-        with mp.workdps(_dps_for(float(zk), j)):
-            res[k] = float(phi_mp(j, -mp.mpf(float(zk))))
-    return out
