@@ -15,6 +15,16 @@ iteration the relative jump ||U^{(k+1)} - U^{(k)}||_2 / ||U^{(k+1)}||_2 over
 all slice ends n = 1..N and all coefficients is recorded; the loop stops when
 it is <= tol or after K_max iterations.  The Euclidean norm of coefficients
 is the L2 norm of u_h (M-orthonormal basis).
+
+The second quantity the loop can watch is the residual of an iterate, how
+far it is from a fine trajectory:
+
+    res^{(k)} = ||U^{n+1,(k)} - F^J(U^{n,(k)})||_2 / ||U^{(k)}||_2,
+
+norms over n = 0..N-1 (slice ends 1..N) and all coefficients.  F^J(U^{(k)})
+is what the fine pass of iteration k + 1 computes, so the residual of
+iterate k becomes known during that pass: after K passes the residuals of
+iterates 0..K-1 are recorded.
 """
 from __future__ import annotations
 
@@ -30,6 +40,7 @@ from .eife import Discretization, StepTables, eife_step
 class PararealResult:
     iterates: List[np.ndarray]          # iterates[k] has shape [N+1, *grid]
     jumps: List[float]                  # jumps[k-1] = rel. jump of iterate k vs k-1
+    residuals: List[float]              # residuals[k-1] = rel. residual of iterate k-1
     iterations: int                     # number of fine passes performed
     converged: bool
     fine_outputs: List[np.ndarray] = field(default_factory=list)
@@ -67,6 +78,7 @@ def parareal(disc: Discretization, W0: np.ndarray, t0: float, N: int, J: int,
         U.append(G(U[n], n))
     iterates = [np.stack(U)]
     jumps: List[float] = []
+    residuals: List[float] = []
     fines = []
     converged = False
     k = 0
@@ -74,6 +86,11 @@ def parareal(disc: Discretization, W0: np.ndarray, t0: float, N: int, J: int,
         Fbar = [fine_prop(disc, U[n], t0 + n * dT, tabF, J) for n in range(N)]
         if keep_fine:
             fines.append(np.stack(Fbar))
+        # residual of the iterate the fine pass started from
+        cur = iterates[-1]
+        res = np.stack([cur[n + 1] - Fbar[n] for n in range(N)])
+        residuals.append(float(np.linalg.norm(res.ravel()) /
+                               max(np.linalg.norm(cur[1:].ravel()), 1e-300)))
         Unew = [W0]
         for n in range(N):
             Unew.append(G(Unew[n], n) + Fbar[n] - G(U[n], n))
@@ -88,7 +105,7 @@ def parareal(disc: Discretization, W0: np.ndarray, t0: float, N: int, J: int,
         if jump <= tol:
             converged = True
             break
-    return PararealResult(iterates, jumps, k, converged, fines)
+    return PararealResult(iterates, jumps, residuals, k, converged, fines)
 
 
 def sequential_fine(disc: Discretization, W0: np.ndarray, t0: float, N: int, J: int,

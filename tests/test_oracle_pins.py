@@ -448,6 +448,37 @@ def test_parareal_reaches_sequential_fine_at_k_equal_N():
     assert rr.iterations == 2 and rr.converged
 
 
+def test_parareal_residuals():
+    """The residual ||U^{n+1,(k)} - F^J(U^{n,(k)})|| of each iterate:
+    (i) every iterate k >= 1 is the sequential fine solve (strong form of
+    Theorem 4.4), so its residual vanishes to rounding, while the coarse
+    iterate's does not; (ii) with f = 0, G and F apply the same exact
+    exponential (e^{-dT mu} = (e^{-dt mu})^J), so even the coarse iterate has
+    no residual; (iii) when e^{-dT mu} underflows on every mode, eq. (2.8)
+    gives U^{n+1,(1)} - U^{n+1,(0)} = F^J(U^{n,(0)}) - U^{n+1,(0)}: the first
+    jump and the coarse residual are the same vector."""
+    p, d, tF, tG, W0, r = _small_parareal(3)
+    assert len(r.residuals) == 3 and r.residuals[0] > 1e-6
+    assert all(v <= 1e-14 for v in r.residuals[1:]), r.residuals
+    # (ii)
+    p0 = p.with_(forcing=[])
+    d0 = Discretization(p0)
+    r0 = parareal(d0, d0.initial(), 0.0, p0.N, p0.J, d0.tables(p0.dt, p0.c_fine),
+                  d0.tables(p0.dT, p0.c_coarse), K_max=2)
+    assert np.linalg.norm(d0.initial()) > 1e-3
+    assert all(v <= 1e-14 for v in r0.residuals), r0.residuals
+    # (iii) lambda_1 D dT = pi^2 * 10 * 0.5 ~ 49: e^{-49} ~ 5e-22
+    ps = wl.tiny_problem(1, (7,), seed=5, N=4, J=3, s=3, n_modes=3, D=10.0, T=2.0)
+    ds = Discretization(ps)
+    assert np.max(np.exp(-ps.dT * ps.D * ds.lam)) < 1e-20
+    rs = parareal(ds, ds.initial(), 0.0, ps.N, ps.J, ds.tables(ps.dt, ps.c_fine),
+                  ds.tables(ps.dT, ps.c_coarse), K_max=1)
+    U0, U1 = rs.iterates
+    jump_abs = rs.jumps[0] * np.linalg.norm(U1[1:])
+    res_abs = rs.residuals[0] * np.linalg.norm(U0[1:])
+    assert jump_abs > 1e-3 and abs(jump_abs - res_abs) <= 1e-12 * res_abs
+
+
 def test_parareal_state_independent_correction_changes_only_k0():
     p, d, tF, tG, W0, r = _small_parareal(3)
     rng = np.random.default_rng(4)
