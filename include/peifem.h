@@ -254,10 +254,12 @@ pe_status pe_fine_propagate(pe_grid g, int32_t n_slices, double t0, double dT, i
  *    d_Fout, d_r and d_corr (nullable: no learned correction) [N][DOF];
  *    d_U must not overlap any of the arrays it is computed from (PE_E_ARG
  *    when it starts at the same address as one of them).
- *  - d_norms (nullable, 2 doubles, device): d_norms[0] = sum over n = 1..N of
- *    ||d_U[n] - d_Uprev[n]||^2 (0 without d_Uprev), d_norms[1] = sum over
- *    n = 1..N of ||d_U[n]||^2, accumulated in FP64 in a fixed order (bitwise
- *    repeatable).
+ *  - d_norms (nullable, 3 doubles, device): d_norms[0] = sum over n = 1..N of
+ *    ||d_U[n] - d_Uprev[n]||^2 (the jump; 0 without d_Uprev), d_norms[1] =
+ *    sum over n = 1..N of ||d_U[n]||^2, d_norms[2] = sum over n = 0..N-1 of
+ *    ||d_Uprev[n+1] - d_Fout[n]||^2 (the residual of the previous iterate
+ *    when d_Fout[n] = F^J(d_Uprev[n]); 0 without d_Uprev), accumulated in
+ *    FP64 in a fixed order (bitwise repeatable).
  * Needs pe_coarse_workspace_bytes(g, N, p) bytes of d_work (a smaller
  * workspace still works when it holds the norm partials and p stage fields;
  * r_n is then computed a few slices at a time). */
@@ -362,7 +364,11 @@ pe_status pe_learned_correction(pe_grid g, pe_mlp m, int32_t n_slices, double t0
  * open): after iteration k the relative jump
  *     ||U^(k) - U^(k-1)|| / ||U^(k)||    (all slice ends n = 1..N, FP64)
  * is compared with tol; the loop stops when jump <= tol (converged = 1) or
- * after K_max fine passes (converged = 0, still PE_OK). */
+ * after K_max fine passes (converged = 0, still PE_OK).  Beside it the
+ * relative residual of each iterate, how far it is from a fine trajectory,
+ *     ||U^{n+1,(k)} - F^J(U^{n,(k)})|| / ||U^(k)||   (n = 0..N-1, FP64),
+ * is reported: F^J(U^(k)) is the fine pass of iteration k + 1, so after K
+ * passes the residuals of iterates 0..K-1 are known. */
 typedef struct {
   double t0;
   double T;
@@ -390,13 +396,16 @@ typedef struct {
   double ms_total;
   double ms_learned;           /* forcing samples + network (inside ms_coarse) */
   int32_t fallback;            /* 1: the network output was non-finite, plain G used */
+  double residuals[PE_MAX_ITERS]; /* residuals[k-1]: relative residual of iterate k-1,
+                                     measured during fine pass k */
 } pe_solve_report;
 
 /* d_U0: initial state (one state, nullable = zero); d_U receives the last
  * iterate [N+1][DOF].  Needs pe_solve_workspace_bytes(g, P) of d_work (with
  * P->mlp set this includes the forcing samples and the correction).
- * Synchronises `stream` once per iteration (one 16-byte read-back of the
- * jump norms).  Errors: PE_E_ARG, PE_E_WORKSPACE, PE_E_HIP, PE_E_NUMERIC
+ * Synchronises `stream` after the coarse start and once per iteration (one
+ * 24-byte read-back of the jump and residual norms).  Errors: PE_E_ARG,
+ * PE_E_WORKSPACE, PE_E_HIP, PE_E_NUMERIC
  * (non-finite jump). */
 size_t pe_solve_workspace_bytes(pe_grid g, const pe_solve_params *P);
 pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U0, void *d_U,

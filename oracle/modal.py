@@ -88,27 +88,41 @@ class ModalForcing:
         return np.array([term.amp for term in self.terms]) @ self.G
 
 
+class ModalFine:
+    """The fine propagator F^J (J steps of eq. (2.6) with step dt = dT/J and
+    the fine nodes) restricted to a set of modes."""
+
+    def __init__(self, prob, modes: np.ndarray, q: int = 3):
+        self.modes = np.asarray(modes, dtype=np.int64).reshape(-1, prob.dim)
+        self.dT = (prob.T - prob.t0) / prob.N
+        self.dt = self.dT / prob.J
+        self.J = prob.J
+        self.c = tuple(prob.c_fine)
+        lam = mode_lambdas(prob, self.modes)
+        self.E, self.B = phi.tables(self.dt * prob.D * lam, self.c)
+        self.forcing = ModalForcing(prob, self.modes, q=q)
+
+    def propagate(self, W: np.ndarray, Tn: float) -> np.ndarray:
+        """F^J(W) over the slice starting at Tn."""
+        for j in range(self.J):
+            t = Tn + j * self.dt
+            acc = self.E * W
+            for i, ci in enumerate(self.c):
+                acc = acc + self.dt * self.B[i] * self.forcing.at(t + ci * self.dt)
+            W = acc
+        return W
+
+
 def sequential_fine_modes(prob, modes: np.ndarray, q: int = 3,
                           steps: Optional[int] = None) -> np.ndarray:
     """W[n, i] at T_n = t0 + n dT (n = 0..N) of mode modes[i] under N*J fine
     steps of eq. (2.6) with the fine nodes; W[0] = P_h u0 on those modes."""
-    modes = np.asarray(modes, dtype=np.int64).reshape(-1, prob.dim)
-    lam = mode_lambdas(prob, modes)
-    dT = (prob.T - prob.t0) / prob.N
-    dt = dT / prob.J
-    c = tuple(prob.c_fine)
-    E, B = phi.tables(dt * prob.D * lam, c)
-    forcing = ModalForcing(prob, modes, q=q)
-    W = ModalForcing(prob, modes, terms=prob.u0, q=q).static() if prob.u0 else np.zeros(len(modes))
+    fine = ModalFine(prob, modes, q)
+    W = (ModalForcing(prob, fine.modes, terms=prob.u0, q=q).static() if prob.u0
+         else np.zeros(len(fine.modes)))
     out = [W]
     for n in range(prob.N if steps is None else steps):
-        Tn = prob.t0 + n * dT
-        for j in range(prob.J):
-            t = Tn + j * dt
-            acc = E * W
-            for i, ci in enumerate(c):
-                acc = acc + dt * B[i] * forcing.at(t + ci * dt)
-            W = acc
+        W = fine.propagate(W, prob.t0 + n * fine.dT)
         out.append(W)
     return np.stack(out)
 

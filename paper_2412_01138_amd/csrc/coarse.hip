@@ -7,8 +7,10 @@
 //     U^{n+1,(k+1)} = G(U^{n,(k+1)}) + Fbar^{n+1} - G(U^{n,(k)}).
 // The sweep is a first-order linear recurrence per coefficient: one thread
 // owns one coefficient and walks n = 0..N-1, reading each slice once
-// (coalesced across threads).  The squared norms of the jump and of the new
-// iterate are accumulated in FP64 with a fixed reduction order.
+// (coalesced across threads).  The squared norms of the jump, of the new
+// iterate and of the previous iterate's residual U^{n+1,(k)} - Fbar^{n+1}
+// (Fbar = F^J(U^{n,(k)}), both already read for eq. (2.8)) are accumulated
+// in FP64 with a fixed reduction order.
 #include <algorithm>
 
 #include "pe_internal.h"
@@ -27,25 +29,25 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Block-wide sum of two values in a fixed order; result valid in thread 0.
-__device__ inline void block_sum2(double &a, double &b) {
-  __shared__ double sa[SWEEP_BS / 64], sb[SWEEP_BS / 64];
-  a = wave_sum(a);
-  b = wave_sum(b);
+constexpr int NORMS = 3;   // jump, new iterate, residual of the previous iterate
+
+// Block-wide sums of NORMS values in a fixed order; results valid in thread 0.
+__device__ inline void block_sum(double (&v)[NORMS]) {
+  __shared__ double sh[NORMS][SWEEP_BS / 64];
   int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    sa[wave] = a;
-    sb[wave] = b;
+#pragma unroll
+  for (int i = 0; i < NORMS; ++i) {
+    v[i] = wave_sum(v[i]);
+    if (lane == 0) sh[i][wave] = v[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double x = 0, y = 0;
-    for (int w = 0; w < SWEEP_BS / 64; ++w) {
-      x += sa[w];
-      y += sb[w];
+#pragma unroll
+    for (int i = 0; i < NORMS; ++i) {
+      double x = 0;
+      for (int w = 0; w < SWEEP_BS / 64; ++w) x += sh[i][w];
+      v[i] = x;
     }
-    a = x;
-    b = y;
   }
 }
 
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(SWEEP_BS) void k_sweep(const double *__restrict__ E
                                                     TS *__restrict__ U, int N, int64_t dof,
                                                     double *partials) {
   int64_t k = int64_t(blockIdx.x) * SWEEP_BS + threadIdx.x;
-  double acc_jump = 0.0, acc_norm = 0.0;
+  double acc[NORMS] = {0.0, 0.0, 0.0};   // jump, norm, residual
   if (k < dof) {
     const double e = E[k];
     double u = double(U[k]);
@@ -92,10 +94,12 @@ __global__ __launch_bounds__(SWEEP_BS) void k_sweep(const double *__restrict__ E
       const double nv = double(stored);
       if (CORRECT) {
         const double dlt = nv - c.un;
-        acc_jump += dlt * dlt;
+        acc[0] += dlt * dlt;
+        const double res = c.un - c.fo;               // U^{n+1,(k)} - F^J(U^{n,(k)})
+        acc[2] += res * res;
         up = c.un;
       }
-      acc_norm += nv * nv;
+      acc[1] += nv * nv;
       u = nv;
     };
     // two slice sets, each refilled right after use, without branches in the
@@ -113,10 +117,10 @@ __global__ __launch_bounds__(SWEEP_BS) void k_sweep(const double *__restrict__ E
     if (n < N) step(n, A);
   }
   if (partials) {
-    block_sum2(acc_jump, acc_norm);
+    block_sum(acc);
     if (threadIdx.x == 0) {
-      partials[2 * blockIdx.x] = acc_jump;
-      partials[2 * blockIdx.x + 1] = acc_norm;
+#pragma unroll
+      for (int i = 0; i < NORMS; ++i) partials[NORMS * blockIdx.x + i] = acc[i];
     }
   }
 }
@@ -141,24 +145,24 @@ static void launch_sweep(int nb, hipStream_t st, const double *E, const void *r,
   }
 }
 
-// One block: out[0..1] = sums of the block partials, in a fixed order.
+// One block: out[0..NORMS-1] = sums of the block partials, in a fixed order.
 __global__ __launch_bounds__(SWEEP_BS) void k_reduce_partials(const double *partials, int nblocks,
                                                               double *out) {
-  double a = 0.0, b = 0.0;
+  double v[NORMS] = {0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < nblocks; i += SWEEP_BS) {
-    a += partials[2 * i];
-    b += partials[2 * i + 1];
+#pragma unroll
+    for (int j = 0; j < NORMS; ++j) v[j] += partials[NORMS * i + j];
   }
-  block_sum2(a, b);
+  block_sum(v);
   if (threadIdx.x == 0) {
-    out[0] = a;
-    out[1] = b;
+#pragma unroll
+    for (int j = 0; j < NORMS; ++j) out[j] = v[j];
   }
 }
 
 static size_t partial_bytes(pe_grid g) {
   int64_t nb = (g->dof + SWEEP_BS - 1) / SWEEP_BS;
-  return Arena::need(sizeof(double) * 2 * size_t(nb));
+  return Arena::need(sizeof(double) * NORMS * size_t(nb));
 }
 
 pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const void *d_corr,

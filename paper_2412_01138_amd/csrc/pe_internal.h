@@ -317,6 +317,13 @@ inline bool has_periodic(pe_grid g) {
 // bytes of one padded stage field
 size_t field_bytes(pe_grid g);
 
+// Coarse / correction sweep over N slices (see pe_coarse_sweep) with the
+// norm partials in `partials` (needed when d_norms is given).
+pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const void *d_corr,
+                const void *d_Uprev, const void *d_Fout, void *d_U, double *d_norms,
+                double *partials, hipStream_t st);
+size_t coarse_partials_bytes(pe_grid g);
+
 // Brackets the launches made during its lifetime with HIP events when the
 // grid's timing is enabled (no-op otherwise).
 struct TimedScope {

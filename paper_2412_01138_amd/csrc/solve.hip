@@ -3,9 +3,12 @@
 //   U^(0): U_0 = P_h u0, then the sequential coarse sweep;
 //   repeat: Fbar = F^J(U^(k)) on all slices (one batched fine pass, never
 //           cached between iterations), correction sweep (eq. (2.8)) with the
-//           jump norms fused in, one 16-byte read-back, stop test.
+//           jump and residual norms fused in, one 24-byte read-back, stop
+//           test.
 // The stopping rule (not fixed by the paper) is the relative jump
 // ||U^(k) - U^(k-1)|| / ||U^(k)|| over all slice ends, compared with tol.
+// The relative residual ||U^{n+1,(k)} - F^J(U^{n,(k)})|| / ||U^(k)|| of the
+// iterate a fine pass starts from is reported beside it.
 #include <algorithm>
 #include <cmath>
 
@@ -16,10 +19,6 @@ namespace pe {
 pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int J, int s,
                           const double *c, const double *d_E, const double *d_B, const void *d_Uin,
                           void *d_Uout, void *d_work, size_t work_bytes, hipStream_t st);
-pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const void *d_corr,
-                const void *d_Uprev, const void *d_Fout, void *d_U, double *d_norms,
-                double *partials, hipStream_t st);
-size_t coarse_partials_bytes(pe_grid g);
 
 static size_t fixed_bytes(pe_grid g, const pe_solve_params *P) {
   size_t sb = g->precision == PE_FP64 ? sizeof(double) : sizeof(float);
@@ -30,7 +29,7 @@ static size_t fixed_bytes(pe_grid g, const pe_solve_params *P) {
   b += Arena::need(sb * dof * (P->N + 1));                  // second iterate buffer
   b += Arena::need(sb * dof * P->N);                        // Fout
   b += Arena::need(sb * dof * P->N);                        // r
-  b += Arena::need(sizeof(double) * 2);                     // norms
+  b += Arena::need(sizeof(double) * 6);                     // norms (initial, correction)
   b += coarse_partials_bytes(g);
   if (P->mlp && !P->d_corr) {
     b += learned_coef_bytes(g, P->N);                       // sample-coefficient tables
@@ -90,7 +89,7 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
   char *Ubuf = ar.take<char>(sb * dof * (N + 1));
   char *Fout = ar.take<char>(sb * dof * N);
   char *r = ar.take<char>(sb * dof * N);
-  double *norms = ar.take<double>(2);
+  double *norms = ar.take<double>(6);   // [0..2] correction sweeps, [3..5] initial sweep
   double *partials = ar.take<double>(coarse_partials_bytes(g) / sizeof(double));
   const bool learn = P->mlp && !P->d_corr;
   const size_t coef_bytes = learn ? learned_coef_bytes(g, N) : 0;
@@ -148,9 +147,12 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
     rep->fallback = fb;
     corr = lcorr;
   }
-  PE_TRY(sweep(g, N, EG, r, corr, nullptr, nullptr, cur, nullptr, partials, st));
+  PE_TRY(sweep(g, N, EG, r, corr, nullptr, nullptr, cur, norms + 3, partials, st));
+  double h0[3] = {0, 0, 0};
+  PE_HIP(hipMemcpyAsync(h0, norms + 3, sizeof(h0), hipMemcpyDeviceToHost, st));
   PE_HIP(hipEventRecord(ev[2], st));
   PE_HIP(hipEventSynchronize(ev[2]));
+  double prev_norm2 = h0[1];   // ||U^(k)||^2 of the iterate the next fine pass starts from
 
   int k = 0;
   bool converged = false;
@@ -161,17 +163,20 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
     PE_HIP(hipEventRecord(ev[4], st));
     PE_HIP(hipMemcpyAsync(nxt, cur, sb * dof, hipMemcpyDeviceToDevice, st));   // U^{0,(k+1)} = U^0
     PE_TRY(sweep(g, N, EG, r, corr, cur, Fout, nxt, norms, partials, st));
-    double hn[2] = {0, 0};
+    double hn[3] = {0, 0, 0};
     PE_HIP(hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, st));
     PE_HIP(hipStreamSynchronize(st));
     PE_HIP(hipEventElapsedTime(&ms, ev[3], ev[4]));
     fine_ms += ms;
     ++k;
     std::swap(cur, nxt);
-    if (!std::isfinite(hn[0]) || !std::isfinite(hn[1]))
-      return set_error(PE_E_NUMERIC, "non-finite jump norm at iteration %d", k);
+    if (!std::isfinite(hn[0]) || !std::isfinite(hn[1]) || !std::isfinite(hn[2]))
+      return set_error(PE_E_NUMERIC, "non-finite jump or residual norm at iteration %d", k);
     double jump = hn[1] > 0 ? std::sqrt(hn[0]) / std::sqrt(hn[1]) : std::sqrt(hn[0]);
     rep->jumps[k - 1] = jump;
+    rep->residuals[k - 1] =
+        prev_norm2 > 0 ? std::sqrt(hn[2]) / std::sqrt(prev_norm2) : std::sqrt(hn[2]);
+    prev_norm2 = hn[1];
     if (jump <= P->tol) {
       converged = true;
       break;

@@ -96,7 +96,8 @@ class SolveReport(ctypes.Structure):
                 ("jumps", ctypes.c_double * PE_MAX_ITERS), ("ms_tables", ctypes.c_double),
                 ("ms_coarse", ctypes.c_double), ("ms_fine", ctypes.c_double),
                 ("ms_sweep", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("ms_learned", ctypes.c_double), ("fallback", ctypes.c_int32)]
+                ("ms_learned", ctypes.c_double), ("fallback", ctypes.c_int32),
+                ("residuals", ctypes.c_double * PE_MAX_ITERS)]
 
 
 _lib = None
@@ -384,6 +385,8 @@ class Grid:
     def coarse_sweep(self, U, t0: float, dT: float, c: Sequence[float], E, B, r, compute_r=True,
                      corr=None, Uprev=None, Fout=None, norms=None, work=None):
         N = U.shape[0] - 1
+        if norms is not None and norms.numel() < 3:
+            raise ValueError("norms must hold 3 doubles (jump, norm, residual)")
         if work is None:
             work = self.workspace(self.L.pe_coarse_workspace_bytes(self.h, N, len(c)))
         _check(self.L.pe_coarse_sweep(self.h, N, float(t0), float(dT), len(c), _dbl_array(c),

@@ -38,12 +38,40 @@ def test_library_has_gfx950_code_object():
     assert b"gfx950" in data
 
 
-def test_struct_sizes_match_header():
+_STRUCTS = [("pe_space_factor", "SpaceFactor"), ("pe_time_factor", "TimeFactor"),
+            ("pe_term", "Term"), ("pe_moving_hat", "MovingHat"),
+            ("pe_solve_params", "SolveParams"), ("pe_solve_report", "SolveReport"),
+            ("pe_kernel_stat", "KernelStat")]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Size and field offsets of every struct of the binding equal what a C
+    compiler makes of include/peifem.h."""
+    import shutil
+    import subprocess
     from paper_2412_01138_amd import peifem
-    assert ctypes.sizeof(peifem.SpaceFactor) == 5 * 8
-    assert ctypes.sizeof(peifem.TimeFactor) == 7 * 8
-    assert ctypes.sizeof(peifem.Term) == 8 + 7 * 8 + 3 * 5 * 8
-    assert ctypes.sizeof(peifem.SolveReport) == 8 + 64 * 8 + 6 * 8 + 8
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "peifem.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS:
+        lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for field, _ in getattr(peifem, pyname)._fields_:
+            lines.append(f'printf("{pyname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        pyname, field, val = line.split()
+        cls = getattr(peifem, pyname)
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(val), (pyname, field, got, val)
+        seen += 1
+    assert seen == sum(1 + len(getattr(peifem, p)._fields_) for _, p in _STRUCTS)
     assert peifem.PE_K_COUNT == len(peifem.KERNEL_CLASSES)
 
 

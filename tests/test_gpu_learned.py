@@ -219,6 +219,8 @@ def test_learned_correction_matches_oracle_and_keeps_the_answer(case):
                  d.tables(prob.dT, prob.c_coarse), K_max=1,
                  corrections=[got[n].reshape(prob.n) for n in range(prob.N)])
     assert abs(rep_learn.jumps[0] - r.jumps[0]) <= 1e-9 * r.jumps[0]
+    # and the same residual of its corrected coarse iterate
+    assert abs(rep_learn.residuals[0] - r.residuals[0]) <= 1e-9 * r.residuals[0]
 
 
 def test_learned_correction_falls_back_on_non_finite_network():

@@ -68,6 +68,41 @@ def test_phi_tables(dim, n, s):
         assert np.max(np.abs(B - h * tab.b)) <= (1e-13 + 4 * LAM_REL) * scale, h
 
 
+@pytest.mark.parametrize("s", [5, 6, 7, 8])
+@pytest.mark.parametrize("nodes", ["uniform", "random"])
+def test_phi_tables_many_stages(s, nodes):
+    """s = 5..8 stages.  b_i = sum_j a_ij j! phi_{j+1}(-z) sums terms much
+    larger than b_i when the Lagrange coefficients a_ij are large (up to
+    ~1e8 at s = 8), so a double evaluation carries an error of a few ulps of
+    sum_j |a_ij j! phi_{j+1}|, not of |b_i|: that sum, taken from the
+    oracle's own Lagrange coefficients and phi values, sets the bound."""
+    import mpmath as mp
+    from oracle import phi as ophi
+    pe = _peifem()
+    prob = wl.tiny_problem(2, (37, 21), seed=10 + s, s=s, D=0.37)
+    c = wl.uniform_nodes(s) if nodes == "uniform" else prob.c_fine
+    g = pe.Grid.from_problem(prob)
+    d = Discretization(prob)
+    a = ophi.lagrange_coeffs(c)
+    A = np.array([[float(abs(a[i][j]) * mp.factorial(j)) for j in range(s)] for i in range(s)])
+    LAM_REL = 3e-12
+    for h in (1e-4, 0.03, 2.5):
+        E, B = g.phi_tables(h, c)
+        tab = d.tables(h, c)
+        E = E.cpu().numpy()
+        B = B.cpu().numpy()
+        z = h * prob.D * d.lam
+        assert np.all(np.abs(E - tab.E) <= 4e-16 + LAM_REL * z * tab.E), h
+        uz, inv = np.unique(z.ravel(), return_inverse=True)
+        with mp.workdps(40):
+            ph = np.array([[float(ophi.phi_mp(j, -mp.mpf(float(v)))) for j in range(1, s + 1)]
+                           for v in uz])
+        mag = (ph @ A.T)[inv].T.reshape((s,) + z.shape)      # sum_j |a_ij j! phi_{j+1}|
+        scale = np.max(np.abs(h * tab.b))
+        bound = (1e-13 + 4 * LAM_REL) * scale + 16 * s * 2.0 ** -52 * h * mag
+        assert np.all(np.abs(B - h * tab.b) <= bound), (h, float(np.max(np.abs(B - h * tab.b) / bound)))
+
+
 @pytest.mark.parametrize("dim,n", GRIDS)
 def test_project_initial_value(dim, n):
     pe = _peifem()
@@ -106,6 +141,8 @@ def _fine_case(dim, n, N, J, s, seed=0, n_modes=4):
     (2, (63, 255), 2, 2, 4),
     (2, (255, 255), 1, 2, 2),
     (3, (9, 20, 127), 2, 2, 3),
+    # 511-node last axis: the generating pass with Kh = 256 (two fold levels)
+    (2, (31, 511), 1, 2, 4),
 ])
 def test_fine_propagate(dim, n, N, J, s):
     pe = _peifem()
@@ -116,6 +153,55 @@ def test_fine_propagate(dim, n, N, J, s):
     tab = d.tables(prob.dt, prob.c_fine)
     ref = np.stack([fine_prop(d, Uin[k], prob.t0 + k * prob.dT, tab, J) for k in range(N)])
     assert rel(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [(511, 63), (511, 511)])
+def test_fine_propagate_511_sampled(n):
+    """511-node axes (the workload-4 kernels: the generating pass with
+    Kh = 256, the fused axis-0 update with one half per block, Q = 128) on
+    a random state and a forcing that reaches every mode (sine terms plus a
+    polynomial term, whose 1D loads are dense in both parities): every
+    output coefficient at 400 random modes, plus all modes the sine terms
+    force, against the selected-mode oracle."""
+    from oracle import modal
+    pe = _peifem()
+    prob = wl.tiny_problem(2, n, seed=61, s=4, N=2, J=2, n_modes=4, T=0.9)
+    forced = modal.forced_modes(prob)                 # the sine terms' modes
+    prob.forcing.append(wl.Term(0.8, wl.TimeFactor(omega=3.0, poly=(1.0, 0.5, 0.0, 0.0)),
+                                (wl.poly_factor(0.2, 1.0, -0.7), wl.poly_factor(1.0, -0.3, 0.1))))
+    rng = np.random.default_rng(62)
+    Uin = rng.normal(size=(prob.N,) + prob.n)
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    out = g.fine_propagate(_dev(Uin), prob.t0, prob.dT, prob.J, prob.c_fine, E, B).cpu().numpy()
+    rng = np.random.default_rng(63)
+    extra = np.stack([rng.integers(0, prob.n[a], 400) for a in range(2)], axis=1)
+    modes = np.unique(np.concatenate([forced, extra]), axis=0)
+    fine = modal.ModalFine(prob, modes)
+    idx = tuple(modes.T)
+    for k in range(prob.N):
+        ref = fine.propagate(Uin[k][idx], prob.t0 + k * prob.dT)
+        got = out[k][idx]
+        assert rel(got, ref) <= 1e-12, k
+        # the forcing's share of each coefficient is resolved too
+        free = fine.E ** prob.J * Uin[k][idx]
+        assert rel(got - free, ref - free) <= 1e-11, k
+
+
+@pytest.mark.parametrize("s", [5, 6, 7, 8])
+def test_fine_propagate_many_stages(s):
+    """s = 5..8 stage rules with the paper's uniform nodes c_i = (i-1)/s
+    (the b_i carry up to ~1e4 ulps of cancellation at s = 8, see
+    test_phi_tables_many_stages: the FP64 bar 1e-11 still holds)."""
+    pe = _peifem()
+    prob, d, Uin = _fine_case(2, (63, 127), 2, 2, s, seed=50 + s)
+    prob = prob.with_(c_fine=wl.uniform_nodes(s), c_coarse=wl.uniform_nodes(s))
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    out = g.fine_propagate(_dev(Uin), prob.t0, prob.dT, prob.J, prob.c_fine, E, B).cpu().numpy()
+    tab = d.tables(prob.dt, prob.c_fine)
+    ref = np.stack([fine_prop(d, Uin[k], prob.t0 + k * prob.dT, tab, prob.J) for k in range(2)])
+    assert rel(out, ref) <= FP64_TOL
 
 
 @pytest.mark.parametrize("dim,n", [(1, (45,)), (2, (37, 70)), (3, (9, 20, 33))])
@@ -235,7 +321,7 @@ def test_coarse_sweep_plain_and_correction(dim, n):
     Fout = rng.normal(size=(N,) + prob.n)
     Unew = torch.zeros_like(U)
     Unew[0] = U[0]
-    norms = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    norms = torch.zeros(3, dtype=torch.float64, device="cuda:0")
     g.coarse_sweep(Unew, prob.t0, prob.dT, prob.c_coarse, EG, BG, r, compute_r=False,
                    corr=_dev(corr), Uprev=Uprev, Fout=_dev(Fout), norms=norms)
     up = Uprev.cpu().numpy()
@@ -250,8 +336,11 @@ def test_coarse_sweep_plain_and_correction(dim, n):
     nrm = norms.cpu().numpy()
     assert abs(nrm[0] - np.sum((refn[1:] - up[1:]) ** 2)) <= 1e-12 * nrm[0]
     assert abs(nrm[1] - np.sum(refn[1:] ** 2)) <= 1e-12 * nrm[1]
+    # residual of the previous iterate against the given fine outputs
+    res2 = np.sum((up[1:] - Fout) ** 2)
+    assert abs(nrm[2] - res2) <= 1e-12 * res2
     # the FP64 reduction order is fixed: a second run is bitwise identical
-    norms2 = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    norms2 = torch.zeros(3, dtype=torch.float64, device="cuda:0")
     Unew2 = torch.zeros_like(U)
     Unew2[0] = U[0]
     g.coarse_sweep(Unew2, prob.t0, prob.dT, prob.c_coarse, EG, BG, r, compute_r=False,
@@ -285,6 +374,17 @@ def test_parareal_solve(case):
     assert abs(rep.jumps[0] - r.jumps[0]) <= 1e-9 * r.jumps[0]
     for k in range(1, r.iterations):
         assert rep.jumps[k] <= 1e-13
+    # residuals of iterates 0..K-1: the coarse iterate's against the oracle,
+    # the later ones vanish to rounding (every iterate k >= 1 is the
+    # sequential fine solve)
+    assert abs(rep.residuals[0] - r.residuals[0]) <= 1e-12 * r.residuals[0]
+    for k in range(1, r.iterations):
+        assert rep.residuals[k] <= 1e-13 and r.residuals[k] <= 1e-13
+    assert all(rep.residuals[k] == 0.0 for k in range(r.iterations, pe.PE_MAX_ITERS))
+    # the FP64 reductions have a fixed order: a second solve is bitwise equal
+    _, U2, rep2 = pe.solve_problem(prob, K_max=prob.K_max, tol=1e-8)
+    assert list(rep2.jumps) == list(rep.jumps) and list(rep2.residuals) == list(rep.residuals)
+    assert torch.equal(U, U2)
 
 
 def test_parareal_fixed_iterations_track_every_iterate():
