@@ -270,6 +270,23 @@ pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int
                           const void *d_Fout, void *d_U, double *d_norms, void *d_work,
                           size_t work_bytes, void *stream);
 
+/* For callers that cannot allocate or pass workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the sweep
+ * of pe_coarse_sweep with r given (compute_r = 0), the same kernels and the
+ * same results bit for bit, whose norm partials live in a static device
+ * array of the library (3 MiB per GPU, held until the process ends) instead
+ * of d_work.  The call allocates nothing and takes no workspace.  Arguments
+ * as in pe_coarse_sweep.  Grids are limited to PE_NOALLOC_MAX_DOF
+ * coefficients.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, two host threads) race and may return
+ * wrong norms; calls ordered on one stream are safe (each call writes the
+ * partials it reads).  Errors: PE_E_ARG (null pointers, n_slices < 1,
+ * overlapping d_U, a grid beyond the limit), PE_E_HIP. */
+#define PE_NOALLOC_MAX_DOF (1 << 25)
+pe_status pe_coarse_sweep_noalloc(pe_grid g, int32_t n_slices, const double *d_EG,
+                                  const void *d_r, const void *d_corr, const void *d_Uprev,
+                                  const void *d_Fout, void *d_U, double *d_norms, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned coarse correction (an addition to the paper's method).
  *

@@ -12,6 +12,7 @@
 // (Fbar = F^J(U^{n,(k)}), both already read for eq. (2.8)) are accumulated
 // in FP64 with a fixed reduction order.
 #include <algorithm>
+#include <mutex>
 
 #include "pe_internal.h"
 
@@ -167,11 +168,12 @@ static size_t partial_bytes(pe_grid g) {
 
 pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const void *d_corr,
                 const void *d_Uprev, const void *d_Fout, void *d_U, double *d_norms,
-                double *partials, hipStream_t st) {
+                double *partials, hipStream_t st, bool timed) {
   int nb = int((g->dof + SWEEP_BS - 1) / SWEEP_BS);
   const double sb = g->precision == PE_FP64 ? 8.0 : 4.0;
   int arrays = 2 + (d_corr ? 1 : 0) + (d_Uprev ? 2 : 0);   // r, U write, corr, Uprev, Fout
-  TimedScope ts(g, PE_K_SWEEP, 0.0, double(N) * double(g->dof) * sb * arrays + g->dof * 8.0, st);
+  TimedScope ts(timed ? g : nullptr, PE_K_SWEEP, 0.0,
+                double(N) * double(g->dof) * sb * arrays + g->dof * 8.0, st);
   if (g->precision == PE_FP64)
     launch_sweep<double>(nb, st, d_EG, d_r, d_corr, d_Uprev, d_Fout, d_U, N, g->dof,
                          d_norms ? partials : nullptr);
@@ -187,6 +189,37 @@ pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const voi
 }
 
 size_t coarse_partials_bytes(pe_grid g) { return partial_bytes(g); }
+
+// ---------------------------------------------------------------------------
+// Norm partials for pe_coarse_sweep_noalloc: a static device array (one copy
+// per GPU, held until the process ends) instead of caller workspace.  Host
+// code must not pass the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): its device address is looked up once per device
+// and kept in scratch_ptr.
+constexpr int64_t NOALLOC_BLOCKS = (int64_t(PE_NOALLOC_MAX_DOF) + SWEEP_BS - 1) / SWEEP_BS;
+static __device__ __align__(256) double scratch[NORMS * NOALLOC_BLOCKS];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static double *scratch_ptr[MAX_DEVICES] = {};
+
+// Look up (once per device) the address of `scratch` on the current device.
+pe_status sweep_scratch_setup(double **out) {
+  int dev = -1;
+  PE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES)
+    return set_error(PE_E_UNSUPPORTED, "device %d: the static sweep scratch covers devices 0..%d",
+                     dev, MAX_DEVICES - 1);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    PE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(PE_E_HIP, "hipGetSymbolAddress returned a null address");
+    scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  if (out) *out = scratch_ptr[dev];
+  return PE_OK;
+}
 
 }  // namespace pe
 
@@ -230,6 +263,25 @@ pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int
                            rest_bytes, st));
   }
   return sweep(g, n_slices, d_EG, d_r, d_corr, d_Uprev, d_Fout, d_U, d_norms, partials, st);
+}
+
+pe_status pe_coarse_sweep_noalloc(pe_grid g, int32_t n_slices, const double *d_EG,
+                                  const void *d_r, const void *d_corr, const void *d_Uprev,
+                                  const void *d_Fout, void *d_U, double *d_norms, void *stream) {
+  clear_error();
+  if (!g || !d_EG || !d_r || !d_U) return set_error(PE_E_ARG, "null argument");
+  if (n_slices < 1) return set_error(PE_E_ARG, "n_slices must be >= 1");
+  if (g->dof > PE_NOALLOC_MAX_DOF)
+    return set_error(PE_E_ARG, "grid of %lld coefficients exceeds the no-allocation limit %d",
+                     (long long)g->dof, PE_NOALLOC_MAX_DOF);
+  if ((d_Uprev == nullptr) != (d_Fout == nullptr))
+    return set_error(PE_E_ARG, "d_Uprev and d_Fout must be given together");
+  if (d_Uprev == d_U || d_r == d_U || (d_Fout && d_Fout == d_U) || (d_corr && d_corr == d_U))
+    return set_error(PE_E_ARG, "d_U must not overlap d_r, d_corr, d_Uprev or d_Fout");
+  double *partials = nullptr;
+  if (d_norms) PE_TRY(sweep_scratch_setup(&partials));
+  return sweep(g, n_slices, d_EG, d_r, d_corr, d_Uprev, d_Fout, d_U, d_norms, partials,
+               as_stream(stream), false);
 }
 
 }  // extern "C"

@@ -631,6 +631,9 @@ static pe_status init_grid(pe_grid *out, int32_t dim, const int32_t *n, const do
     if (ps != PE_OK) return fail(ps);
     g->transform = PE_TRANSFORM_FFT;
   }
+  // the device address of pe_coarse_sweep_noalloc's static scratch
+  pe_status ps = sweep_scratch_setup(nullptr);
+  if (ps != PE_OK) return fail(ps);
   *out = g;
   return PE_OK;
 }

@@ -318,21 +318,26 @@ inline bool has_periodic(pe_grid g) {
 size_t field_bytes(pe_grid g);
 
 // Coarse / correction sweep over N slices (see pe_coarse_sweep) with the
-// norm partials in `partials` (needed when d_norms is given).
+// norm partials in `partials` (needed when d_norms is given); timed = false
+// skips the kernel-timing events.
 pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const void *d_corr,
                 const void *d_Uprev, const void *d_Fout, void *d_U, double *d_norms,
-                double *partials, hipStream_t st);
+                double *partials, hipStream_t st, bool timed = true);
 size_t coarse_partials_bytes(pe_grid g);
 
+// Device address, on the current device, of the static norm-partials array
+// of pe_coarse_sweep_noalloc (looked up once per device; *out may be null).
+pe_status sweep_scratch_setup(double **out);
+
 // Brackets the launches made during its lifetime with HIP events when the
-// grid's timing is enabled (no-op otherwise).
+// grid's timing is enabled (no-op otherwise, and for a null grid).
 struct TimedScope {
   pe_grid g;
   hipStream_t st;
   PendingTiming pt{};
   bool on;
   TimedScope(pe_grid g_, int cls, double flops, double bytes, hipStream_t s)
-      : g(g_), st(s), on(g_->timing) {
+      : g(g_), st(s), on(g_ && g_->timing) {
     if (!on) return;
     pt.cls = cls;
     pt.flops = flops;

@@ -26,6 +26,7 @@ PE_MAX_DIM = 3
 PE_MAX_STAGES = 8
 PE_MAX_TERMS = 64
 PE_MAX_ITERS = 64
+PE_NOALLOC_MAX_DOF = 1 << 25
 PE_FP64 = 0
 PE_SPLIT_BF16 = 1
 PE_TRANSFORM_DENSE = 0
@@ -36,7 +37,7 @@ EXPORTS = [
     "pe_set_moving_sources",
     "pe_phi_tables", "pe_project_workspace_bytes", "pe_project", "pe_project_state",
     "pe_fine_workspace_bytes",
-    "pe_fine_propagate", "pe_coarse_workspace_bytes", "pe_coarse_sweep",
+    "pe_fine_propagate", "pe_coarse_workspace_bytes", "pe_coarse_sweep", "pe_coarse_sweep_noalloc",
     "pe_solve_workspace_bytes", "pe_parareal_solve", "pe_grid_dof",
     "pe_grid_precision", "pe_last_error", "pe_set_timing", "pe_get_timing",
     "pe_mlp_create", "pe_mlp_free", "pe_mlp_get_params", "pe_mlp_set_params", "pe_mlp_forward",
@@ -134,6 +135,7 @@ def load_library():
     L.pe_coarse_workspace_bytes.restype = sz
     L.pe_coarse_sweep.argtypes = [vp, i32, dbl, dbl, i32, dp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
                                   vp, sz, vp]
+    L.pe_coarse_sweep_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.pe_solve_workspace_bytes.argtypes = [vp, ctypes.POINTER(SolveParams)]
     L.pe_solve_workspace_bytes.restype = sz
     L.pe_parareal_solve.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, vp, sz,
@@ -168,7 +170,8 @@ def load_library():
     for name in ("pe_init_grid", "pe_init_grid_periodic", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
                  "pe_set_moving_sources",
                  "pe_project_state", "pe_phi_tables", "pe_project",
-                 "pe_fine_propagate", "pe_coarse_sweep", "pe_parareal_solve", "pe_set_timing",
+                 "pe_fine_propagate", "pe_coarse_sweep", "pe_coarse_sweep_noalloc",
+                 "pe_parareal_solve", "pe_set_timing",
                  "pe_get_timing", "pe_mlp_create", "pe_mlp_get_params", "pe_mlp_set_params",
                  "pe_mlp_forward", "pe_mlp_train_step", "pe_learned_samples", "pe_learned_rows",
                  "pe_learned_correction"):
@@ -393,6 +396,16 @@ class Grid:
                                       _ptr(E), _ptr(B), 1 if compute_r else 0, _ptr(r),
                                       _ptr(corr), _ptr(Uprev), _ptr(Fout), _ptr(U), _ptr(norms),
                                       _ptr(work), work.numel(), _stream(self.stream)))
+        return U
+
+    def coarse_sweep_noalloc(self, U, E, r, corr=None, Uprev=None, Fout=None, norms=None):
+        """pe_coarse_sweep with r given, no workspace (static norm partials)."""
+        N = U.shape[0] - 1
+        if norms is not None and norms.numel() < 3:
+            raise ValueError("norms must hold 3 doubles (jump, norm, residual)")
+        _check(self.L.pe_coarse_sweep_noalloc(self.h, N, _ptr(E), _ptr(r), _ptr(corr),
+                                              _ptr(Uprev), _ptr(Fout), _ptr(U), _ptr(norms),
+                                              _stream(self.stream)))
         return U
 
     def learned_samples(self, N: int, t0: float, dT: float, out=None, work=None):
