@@ -446,7 +446,9 @@ typedef enum {
   PE_K_UPDATE = 3,    /* fused diagonal update */
   PE_K_SWEEP = 4,     /* coarse / correction sweep with norms */
   PE_K_MID_UPDATE = 5,  /* axis-0 DST pass fused with the diagonal update */
-  PE_K_COUNT = 6
+  PE_K_COARSE_FORCING = 6, /* every launch computing the coarse forcing r_n (its
+                              quadrature, transform and update kernels) */
+  PE_K_COUNT = 7
 } pe_kernel_class;
 
 typedef struct {

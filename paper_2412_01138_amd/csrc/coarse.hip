@@ -259,6 +259,7 @@ pe_status pe_coarse_sweep(pe_grid g, int32_t n_slices, double t0, double dT, int
     size_t off = (ar.off + 255) & ~size_t(255);
     void *rest = d_work ? static_cast<char *>(d_work) + off : nullptr;
     size_t rest_bytes = work_bytes > off ? work_bytes - off : 0;
+    TimingClassScope tc(g, PE_K_COARSE_FORCING);
     PE_TRY(run_propagation(g, n_slices, t0, dT, dT, 1, p, cG, d_EG, d_BG, nullptr, d_r, rest,
                            rest_bytes, st));
   }

@@ -395,6 +395,12 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
                      overhead + pf * size_t(s));
   int64_t fit = int64_t((work_bytes - overhead) / pf);
   int64_t total = int64_t(N) * J * s;
+  // batches of equal size (the last one never much smaller than the rest):
+  // `count` items in ceil(count / most) batches
+  auto even = [](int count, int64_t most) {
+    const int64_t nb = (count + most - 1) / most;
+    return int((count + nb - 1) / nb);
+  };
   int Nb, Jc;
   if (fit >= total) {
     Nb = N;
@@ -403,13 +409,13 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
     // the fused update walks a slice's fields in one block: whole slices
     // (all J steps) per batch, so each block amortises its operator load
     // over the slice's J s fields and the states never leave its registers
-    Nb = int(fit / (int64_t(J) * s));
+    Nb = even(N, fit / (int64_t(J) * s));
     Jc = J;
   } else if (fit >= int64_t(N) * s) {
     Nb = N;
-    Jc = int(fit / (int64_t(N) * s));
+    Jc = even(J, fit / (int64_t(N) * s));
   } else {
-    Nb = int(fit / s);
+    Nb = even(N, fit / s);
     Jc = 1;
   }
   int64_t maxf = int64_t(Nb) * Jc * s;

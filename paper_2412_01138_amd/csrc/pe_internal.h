@@ -159,8 +159,10 @@ struct pe_grid_s {
   uint16_t *d_Cft = nullptr;     // split-bf16 grids: d_Cf as the generating pass reads it
   // spec_a[m][k] = sig_a(k) (S_a^T C_a[m])_k: spectral 1D loads of each term
   double *d_spec[PE_MAX_DIM] = {nullptr, nullptr, nullptr};  // [n_terms][n_a]
-  // kernel timing (benchmark instrumentation)
+  // kernel timing (benchmark instrumentation); timing_class >= 0 books every
+  // launch into that class (the coarse forcing's launches)
   bool timing = false;
+  int timing_class = -1;
   std::vector<pe::PendingTiming> pending;
   pe_kernel_stat stats[PE_K_COUNT] = {};
 };
@@ -325,6 +327,14 @@ pe_status sweep(pe_grid g, int N, const double *d_EG, const void *d_r, const voi
                 double *partials, hipStream_t st, bool timed = true);
 size_t coarse_partials_bytes(pe_grid g);
 
+// Books the timed launches made during its lifetime into one class.
+struct TimingClassScope {
+  pe_grid g;
+  int prev;
+  TimingClassScope(pe_grid g_, int cls) : g(g_), prev(g_->timing_class) { g->timing_class = cls; }
+  ~TimingClassScope() { g->timing_class = prev; }
+};
+
 // Device address, on the current device, of the static norm-partials array
 // of pe_coarse_sweep_noalloc (looked up once per device; *out may be null).
 pe_status sweep_scratch_setup(double **out);
@@ -339,7 +349,7 @@ struct TimedScope {
   TimedScope(pe_grid g_, int cls, double flops, double bytes, hipStream_t s)
       : g(g_), st(s), on(g_ && g_->timing) {
     if (!on) return;
-    pt.cls = cls;
+    pt.cls = g_->timing_class >= 0 ? g_->timing_class : cls;
     pt.flops = flops;
     pt.bytes = bytes;
     if (hipEventCreate(&pt.start) != hipSuccess || hipEventCreate(&pt.stop) != hipSuccess ||

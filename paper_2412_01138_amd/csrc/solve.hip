@@ -59,11 +59,13 @@ extern "C" {
 
 size_t pe_solve_workspace_bytes(pe_grid g, const pe_solve_params *P) {
   if (!g || check_params(g, P) != PE_OK) return 0;
-  // batch space: all fields of one fine pass, capped at 32 GiB but never
-  // below one step of all slices (or one stage field set)
+  // batch space: all fields of one fine pass, capped at 32 GiB of stage
+  // fields (two buffers) but never below one step of all slices (or one
+  // stage field set)
   int64_t all = int64_t(P->N) * P->J * P->q;
   size_t pf = pe_fine_workspace_bytes(g, 2) - pe_fine_workspace_bytes(g, 1);
-  int64_t cap = int64_t((size_t(32) << 30) / std::max<size_t>(pf, 1));
+  size_t pf_fields = 2 * field_bytes(g);
+  int64_t cap = int64_t((size_t(32) << 30) / std::max<size_t>(pf_fields, 1));
   int64_t want = std::min(all, std::max<int64_t>(cap, int64_t(P->N) * std::max(P->q, P->p)));
   want = std::max<int64_t>(want, std::max(P->q, P->p));
   return fixed_bytes(g, P) + pe_fine_workspace_bytes(g, want);
@@ -128,7 +130,11 @@ pe_status pe_parareal_solve(pe_grid g, const pe_solve_params *P, const void *d_U
     PE_HIP(hipMemsetAsync(cur, 0, sb * dof, st));
   // U^(0): r_n for all slices (and the learned correction), then the
   // sequential coarse sweep
-  PE_TRY(run_propagation(g, N, P->t0, dT, dT, 1, p, P->cG, EG, BG, nullptr, r, fwork, fbytes, st));
+  {
+    TimingClassScope tc(g, PE_K_COARSE_FORCING);
+    PE_TRY(run_propagation(g, N, P->t0, dT, dT, 1, p, P->cG, EG, BG, nullptr, r, fwork, fbytes,
+                           st));
+  }
   if (learn) {
     hipEvent_t l0, l1;
     PE_HIP(hipEventCreate(&l0));

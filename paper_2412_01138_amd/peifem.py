@@ -47,8 +47,9 @@ EXPORTS = [
 ]
 PE_MLP_INPUTS, PE_MLP_WIDTH, PE_MLP_PARAMS, PE_MLP_SAMPLES = 12, 64, 9217, 8
 (PE_K_DST_LAST, PE_K_DST_MID, PE_K_LOAD, PE_K_UPDATE, PE_K_SWEEP, PE_K_MID_UPDATE,
- PE_K_COUNT) = 0, 1, 2, 3, 4, 5, 6
-KERNEL_CLASSES = ("dst_last", "dst_mid", "load", "update", "sweep", "mid_update")
+ PE_K_COARSE_FORCING, PE_K_COUNT) = 0, 1, 2, 3, 4, 5, 6, 7
+KERNEL_CLASSES = ("dst_last", "dst_mid", "load", "update", "sweep", "mid_update",
+                  "coarse_forcing")
 
 
 class PeifemError(RuntimeError):

@@ -58,6 +58,9 @@ def test_struct_layouts_match_header(tmp_path):
         lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
         for field, _ in getattr(peifem, pyname)._fields_:
             lines.append(f'printf("{pyname} {field} %zu\\n", offsetof({cname}, {field}));')
+    for const in ("PE_K_COUNT", "PE_MAX_ITERS", "PE_MAX_STAGES", "PE_MAX_TERMS", "PE_MAX_DIM",
+                  "PE_MLP_PARAMS"):
+        lines.append(f'printf("const {const} %d\\n", (int){const});')
     lines.append("return 0; }")
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines))
@@ -67,6 +70,9 @@ def test_struct_layouts_match_header(tmp_path):
     seen = 0
     for line in filter(None, out):
         pyname, field, val = line.split()
+        if pyname == "const":
+            assert getattr(peifem, field) == int(val), (field, val)
+            continue
         cls = getattr(peifem, pyname)
         got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
         assert got == int(val), (pyname, field, got, val)

@@ -38,3 +38,20 @@ def test_flat_index_is_c_order():
     prob = wl.tiny_problem(3, (4, 5, 6), seed=1)
     modes = np.array([[0, 0, 0], [1, 2, 3], [3, 4, 5]])
     np.testing.assert_array_equal(modal.flat_index(prob, modes), [0, 1 * 30 + 2 * 6 + 3, 119])
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_stored_fullsize_reference_is_the_oracles(cfg):
+    """tests/golden/fullsize_modal_reference.json (read by the benchmark to
+    state each answer's error) holds exactly what the selected-mode oracle
+    computes for the workload."""
+    from conftest import load_golden
+    rec = load_golden("fullsize_modal_reference.json")["workloads"][str(cfg)]
+    prob = wl.config(cfg)
+    modes = modal.sample_modes(prob, 32, seed=100 + cfg)
+    assert modes.tolist() == rec["modes"]
+    assert modal.flat_index(prob, modes).tolist() == rec["flat_index"]
+    assert modal.flat_index(prob, modal.forced_modes(prob)).tolist() == rec["forced_flat_index"]
+    ref = modal.sequential_fine_modes(prob, modes)
+    stored = np.array([[float.fromhex(v) for v in row] for row in rec["W"]])
+    np.testing.assert_array_equal(stored, ref)
