@@ -35,18 +35,13 @@
 
 namespace pe {
 
-#ifndef FUSED_FPB
-#define FUSED_FPB 1          // fields per barrier (two measured slower)
-#endif
-#ifndef SPLIT_DEPTH
-#define SPLIT_DEPTH 2        // strips in flight per block, split-bf16 fused update (3+ costs Kh = 64 its second block per CU)
-#endif
-#ifndef FUSED_STRIP_MAJOR
-#define FUSED_STRIP_MAJOR 1
-#endif
-#ifndef FUSED_HB2_MAX_Q
-#define FUSED_HB2_MAX_Q 64   // both halves per block up to this Q
-#endif
+// fields per barrier of the FP64 kernel (two measured slower)
+constexpr int FUSED_FPB = 1;
+// strips in flight per block in the split-bf16 fused update (three or more
+// cost the Kh = 64 kernel its second block per CU)
+constexpr int SPLIT_DEPTH = 2;
+// both halves of axis 0 in one block up to this Q (one half per block above)
+constexpr int FUSED_HB2_MAX_Q = 64;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -92,7 +87,6 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
   constexpr int KH = 2 * Q;             // folded rows per half
   constexpr int ITEMS = KH * 8 / NTH;   // (row, column pair) loader items per thread
   static_assert(ITEMS * NTH == KH * 8, "loader items must tile the strip");
-  constexpr bool LATE_TABLES = HB == 1;   // one half per block: four loader items
   // [stage][field of the group][half][parity][jj][column]
   __shared__ __attribute__((aligned(16))) double F[2][FPB][HB][2][Q][16];
 
@@ -105,13 +99,8 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     hb = int(bid % 2);
     bid /= 2;
   }
-#if FUSED_STRIP_MAJOR
   const int nl = int(bid % a.nslices);
   const int strip = int(bid / a.nslices);
-#else
-  const int strip = int(bid % a.strips);
-  const int nl = int(bid / a.strips);
-#endif
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int hl = HB == 2 ? wave / RT : 0;
   const int h = HB == 2 ? hl : hb;
@@ -217,7 +206,9 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
     const int nxt = e0 + FPB;
     // tables of the group (16-byte loads, contiguous across the wave): the
     // decay once per group (it does not depend on the stage), a weight set
-    // per field; ahead of the products where the registers allow it, and
+    // per field; ahead of the products (also with one half per block, where
+    // it costs a few spilled registers but no longer exposes the tables'
+    // latency after the products), and
     // issued before the next strip's loads: memory loads complete in issue
     // order, so the update's wait for its tables then leaves the strip in
     // flight
@@ -234,7 +225,7 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
       for (int f = 0; f < FPB; ++f) load2(Tl + (1 + ist[f]) * 512, bw[f]);
       if (need_e) load2(Tl, ew);
     };
-    if (!LATE_TABLES) tables();
+    tables();
 #pragma unroll
     for (int f = 0; f < FPB; ++f)
       if (nxt + f < nf) load(S[f], nxt + f, 0);
@@ -258,7 +249,6 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
 #pragma unroll
     for (int f = 0; f < FPB; ++f)
       if (nxt + f < nf) stash(S[f], stage ^ 1, f, PARTS - 1);
-    if (LATE_TABLES) tables();
 #pragma unroll
     for (int f = 0; f < FPB; ++f) {
       if (e0 + f >= nf) break;   // a short last group (its LDS slot holds no field)
