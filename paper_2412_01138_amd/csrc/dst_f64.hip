@@ -504,16 +504,6 @@ __global__ __launch_bounds__(NT) void k_pass_mid2(Mid2Args a) {
 // rows r x jj, or generated from the quadrature tables at those p), the B
 // operand is SqT[h][g] (jj x i); the row of outputs gets y_i = C_0 + C_1
 // and y_i' = C_0 - C_1.
-//
-// Generating pass with Q = 2 BN and the third-level operands (a.L3): half 1
-// takes the third fold level of its two products (see the three-level
-// generating pass below: C_0 is a DST-II, whose even rows see the sums
-// u_jj + u_{Q-1-jj} and odd rows the differences; C_1 a DST-I of size Q-1,
-// likewise with u_jj and u_{Q-2-jj}).  Its column tile tn then selects the
-// even (tn = 0) or odd (tn = 1) output rows i = 2 n + tn, n < Q/2, and both
-// of its products contract Q/2 inputs instead of Q: half the work of half 1.
-// The input combinations are linear in the quadrature table, so they are
-// applied to the table columns the quadrature products read.
 template <int BM, int BN, int GM>
 __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   constexpr bool GEN = GM > 0;
@@ -527,9 +517,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   const int h = int(bid % 2);
   const int64_t tm = bid / 2;
   const int64_t m0 = tm * BM;
-  const bool l3 = GEN && a.L3 != nullptr && h == 1 && Q == 2 * BN;
-  const int n0 = l3 ? 0 : tn * BN;
-  const int Qk = l3 ? Q / 2 : Q;   // inputs per product
+  const int n0 = tn * BN;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
 
@@ -578,18 +566,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   double ra_a[GEN ? 1 : 2][GEN ? 1 : C::CPT], ra_b[GEN ? 1 : 2][GEN ? 1 : C::CPT];
   double rb[2][C::B_PER];
   const double *xrow = GEN ? nullptr : a.X + (row_ok ? grow : a.R - 1) * a.np;
-  // B operands [K][N] per parity: SqT[h][g] (Q x Q), or with the third level
-  // the half-1 operands P1gS / P1gD (Q/2 x Q/2) after half 0's 3 Q^2 / 2
-  const double *Bop[2];
-  int ldb;
-  if (l3) {
-    ldb = Q / 2;
-    for (int g = 0; g < 2; ++g)
-      Bop[g] = a.L3 + int64_t(3) * Q * Q / 2 + int64_t(2 * g + tn) * (Q / 2) * (Q / 2);
-  } else {
-    ldb = Q;
-    for (int g = 0; g < 2; ++g) Bop[g] = a.ShT + int64_t(2 * h + g) * Q * Q;
-  }
+  const double *SqT = a.ShT;   // [2][2][Q][Q] when set up for this pass
   auto load = [&](int k0) {
     if constexpr (!GEN) {
 #pragma unroll
@@ -608,7 +585,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
         const int e = t + q * NT;
         const int k = e / BN, nl = e % BN;
         const int col = n0 + nl;
-        rb[g][q] = Bop[g][int64_t(k0 + k) * ldb + (col < ldb ? col : ldb - 1)];
+        rb[g][q] = SqT[(int64_t(2 * h + g) * Q + k0 + k) * Q + (col < Q ? col : Q - 1)];
       }
   };
   auto store = [&](int buf, int k0) {
@@ -620,18 +597,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
 #pragma unroll
         for (int kk = 0; kk < GK; ++kk) {
           const int term = lk + 4 * kk;
-          const double *c = cf_half + (term < Mm1 ? term : Mm1) * a.Kh;
-          const int jj = k0 + lr;
-          if (!l3) {
-            cfb[kk] = c[2 * jj + g];
-          } else {
-            // the partner input of jj: Q-1-jj (g = 0), Q-2-jj (g = 1; the
-            // middle input Q/2-1 enters the sums once, the differences never)
-            const bool mid = g == 1 && jj == Q / 2 - 1;
-            const double x = c[2 * jj + g];
-            const double y = mid ? 0.0 : c[2 * (Q - 1 - g - jj) + g];
-            cfb[kk] = tn == 0 ? x + y : (mid ? 0.0 : x - y);
-          }
+          cfb[kk] = cf_half[(term < Mm1 ? term : Mm1) * a.Kh + 2 * (k0 + lr) + g];
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
@@ -663,7 +629,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
       for (int q = 0; q < C::B_PER; ++q) {
         const int e = t + q * NT;
         const int col = n0 + e % BN;
-        sm.B[buf][g][e / BN][e % BN] = col < ldb ? rb[g][q] : 0.0;
+        sm.B[buf][g][e / BN][e % BN] = col < Q ? rb[g][q] : 0.0;
       }
   };
 
@@ -678,7 +644,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   // (with the prefetch made conditional the compiler copied them out to
   // plain registers and back around every k-tile, which also made each
   // k-tile wait for all of its products)
-  const int nk = Qk / KB;
+  const int nk = Q / KB;
   load(0);
   store(0, 0);
   __syncthreads();
@@ -699,9 +665,8 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
     for (int j = 0; j < C::TN; ++j) {
-      const int cn = n0 + wn * (BN / 2) + j * 16 + lr;
-      if (cn >= (l3 ? Q / 2 : Q)) continue;
-      const int col = l3 ? 2 * cn + tn : cn;   // output row i of the half
+      const int col = n0 + wn * (BN / 2) + j * 16 + lr;
+      if (col >= Q) continue;
       int pos2;
       bool diff;
       if (h == 0) {
@@ -1118,12 +1083,11 @@ pe_status dst_fields_f64(pe_grid g, int64_t count, const GenSrc *gen, double *bu
     // algorithmic work per line of n nodes: one fold level,
     // ceil(n/2)^2 + floor(n/2)^2 multiply-adds; two levels, 4 (Kh/2)^2
     double lines = double(count) * double(g->dof) / ax.n;
-    // (the generating pass on a three-level axis: 5/8 Kh^2 in the
-    // three-level kernel, 3/4 Kh^2 with the third level on half 1 only)
-    const bool l3_pass = gen && ax_i == d - 1 && ax.l3 && gen->M <= GEN_MAX_TERMS &&
-                         (ax.Kh == 256 || outer % 16 == 0);
-    const double l3_frac = ax.Kh == 256 ? 0.75 : 0.625;
-    double fl = l3_pass  ? 2.0 * lines * l3_frac * double(ax.Kh) * ax.Kh
+    // (the generating pass on a three-level axis: 5/8 Kh^2; a batch whose
+    // row count is not a multiple of 16 takes the two-level kernel)
+    const bool l3_pass =
+        gen && ax_i == d - 1 && ax.l3 && gen->M <= GEN_MAX_TERMS && outer % 16 == 0;
+    double fl = l3_pass  ? 2.0 * lines * 0.625 * double(ax.Kh) * ax.Kh
                 : ax.l2 ? 2.0 * lines * double(ax.Kh) * ax.Kh
                         : 2.0 * lines * (double((ax.n + 1) / 2) * ((ax.n + 1) / 2) + double(ax.H) * ax.H);
     // a generating pass writes its field and reads only the per-field

@@ -605,9 +605,8 @@ static pe_status init_grid(pe_grid *out, int32_t dim, const int32_t *n, const do
       e = hipMalloc(&ax.d_Sq, sizeof(double) * q2);
       if (e == hipSuccess) e = hipMalloc(&ax.d_SqT, sizeof(double) * q2);
     }
-    // third level for the generating pass of the last axis (Kh = 64, 128:
-    // every product; Kh = 256: the products of half 1)
-    ax.l3 = ax.l2 && a == dim - 1 && (ax.Kh == 64 || ax.Kh == 128 || ax.Kh == 256);
+    // third level for the generating pass of the last axis
+    ax.l3 = ax.l2 && a == dim - 1 && (ax.Kh == 64 || ax.Kh == 128);
     if (e == hipSuccess && ax.l3)
       e = hipMalloc(&ax.d_L3, sizeof(double) * 3 * size_t(ax.Kh / 2) * (ax.Kh / 2));
     if (e != hipSuccess)
