@@ -14,7 +14,9 @@ from dataclasses import dataclass
 from typing import List, Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpeifem.so")
+# PEIFEM_LIB selects another build of the same library (the host-sanitizer
+# build); there is no other implementation behind this binding
+LIB_PATH = os.environ.get("PEIFEM_LIB") or os.path.join(HERE, "libpeifem.so")
 
 PE_OK = 0
 PE_E_ARG = -1
