@@ -716,6 +716,10 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
 // amortised over its tiles), fewer for small launches so that about 1024
 // blocks fill the chip
 constexpr int LG_TILES_MAX = 128;
+// 8 waves per block: two blocks (the LDS of two) per compute unit then keep
+// four waves on each SIMD to hide the latency of the chained products
+constexpr int L3_NT = 512;
+constexpr int L3_NW = L3_NT / 64;
 static int64_t lg_tiles(int64_t tiles) {
   return std::max<int64_t>(4, std::min<int64_t>(LG_TILES_MAX, tiles / 512));
 }
@@ -758,7 +762,8 @@ __device__ inline void l3_product(const double *sb, int Boff, const double (*cfl
 }
 
 template <int Q, int GK>
-__global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles, int64_t per_block) {
+__global__ __launch_bounds__(L3_NT) __attribute__((amdgpu_waves_per_eu(GK <= 4 ? 4 : 2)))
+void k_last3_gen(LastArgs a, int64_t tiles, int64_t per_block) {
   constexpr int Q2 = Q / 2;
   constexpr int NACC = Q / 8;          // accumulator tiles of a row tile
   constexpr int PER = 3 * Q * Q / 2;   // B operands per half
@@ -775,7 +780,7 @@ __global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles, int
   {
     const double *src = a.L3 + int64_t(h) * PER;
     const int nb = h == 0 ? PER : Q * Q;
-    for (int e = 2 * t; e < nb; e += 2 * NT) {
+    for (int e = 2 * t; e < nb; e += 2 * L3_NT) {
       int base, N, r;
       if (h == 0 && e < Q * Q) {
         base = 0;
@@ -796,7 +801,7 @@ __global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles, int
   // K-column table of this half (input-side folds applied to the table)
   {
     const double *cf = a.gen.Cf + int64_t(h) * M * a.Kh;
-    for (int e = t; e < 4 * GK * 2 * Q; e += NT) {
+    for (int e = t; e < 4 * GK * 2 * Q; e += L3_NT) {
       const int m = e / (2 * Q), kc = e - m * 2 * Q;
       double v = 0.0;
       if (m < M) {
@@ -854,8 +859,8 @@ __global__ __launch_bounds__(NT) void k_last3_gen(LastArgs a, int64_t tiles, int
   int64_t tile = tile0 + wave;
   double rf[GK], rfn[GK];
   if (tile < tend) row_factors(tile, rf);
-  for (; tile < tend; tile += 4) {
-    if (tile + 4 < tend) row_factors(tile + 4, rfn);
+  for (; tile < tend; tile += L3_NW) {
+    if (tile + L3_NW < tend) row_factors(tile + L3_NW, rfn);
     d4 acc[NACC];
 #pragma unroll
     for (int j = 0; j < NACC; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
@@ -923,7 +928,7 @@ static pe_status launch_last3_gen(const LastArgs &a, hipStream_t st) {
   const int64_t per = lg_tiles(tiles);
   const int64_t blocks = 2 * ((tiles + per - 1) / per);
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: LAST3 grid too large");
-  k_last3_gen<Q, GK><<<dim3(unsigned(blocks)), NT, 0, st>>>(a, tiles, per);
+  k_last3_gen<Q, GK><<<dim3(unsigned(blocks)), L3_NT, 0, st>>>(a, tiles, per);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }
