@@ -153,6 +153,19 @@ void pe_free_grid(pe_grid g);
 typedef enum { PE_TRANSFORM_DENSE = 0, PE_TRANSFORM_FFT = 1 } pe_transform;
 pe_status pe_set_transform(pe_grid g, int32_t kind);
 
+/* Whether the stage-load transform of pe_fine_propagate (Section 2.3, the
+ * tensor-product sine transform of the load vectors of eq. (2.6)) runs its
+ * generating last-axis pass and its middle-axis pass as one kernel (enable
+ * != 0, the default) or as two passes with the intermediate in device memory
+ * (enable = 0).  It applies to 3D split-bf16 grids whose axis-0 pass is
+ * fused with the update and whose axes 1 and 2 have Kh = 64 or 128 (n from
+ * 65 to 255), with at most 32 separable forcing terms and no moving
+ * sources; elsewhere the setting has no effect.  Both forms compute the same
+ * products; the fused one orders each 32-wide k-step of the axis-2 product
+ * differently, so results agree to fp32 rounding, not bitwise.  Errors:
+ * PE_E_ARG for a null grid.  No device work. */
+pe_status pe_set_fusion(pe_grid g, int32_t enable);
+
 /* Set the forcing f (paper eq. (2.1)) as n_terms (0..PE_MAX_TERMS) separable
  * terms (host array).  Builds on the device the 1D load tables
  * C_{m,a}[j] = int X_{m,a}(x) phi_j(x) dx by the grid's Gauss rule (the load

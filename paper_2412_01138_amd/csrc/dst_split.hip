@@ -346,6 +346,279 @@ __global__ __launch_bounds__(SNT) __attribute__((amdgpu_waves_per_eu(GEN ? 3 : 1
   }
 }
 
+// ------------------------------- generating + middle-axis pass, fused (3D)
+// On 3D grids whose axis-0 pass is fused with the update, the first two
+// passes run as one: for a stage field f and an axis-0 node i0 (a "plane")
+// a block generates the load, transforms it along axis 2 and then along
+// axis 1, and writes the plane once,
+//     X1[i1][P2] = sum_p Sh2[h2][j][p] Lf_h2[i1][p]            (P2 = h2 Kh2 + j)
+//     Z[P1][P2]  = sum_p Sh1[h1][i][p] fold_h1(X1[.][P2])[p]   (P1 = h1 Kh1 + i)
+//     Y[f][i0][P1][P2] = Z[P1][P2],
+// so the axis-2 results never travel through HBM.  The output keeps the
+// natural axis order (axis 0 outermost); the fused axis-0 pass reads it that
+// way.  A block owns one 64-wide chunk of P2 (its Sh2 rows, permuted as below,
+// and this half's quadrature table stay in LDS) and walks planes.
+//   Axis-2 step: a wave takes the 16 rows i1 = 16 t + x and their mirrors
+//   n1 - 1 - (16 t + x) (x = 0..15): the quadrature MFMA leaves lane (x, q) the
+//   loads of p = 4 q + r and 16 + 4 q + r (r = 0..3) of each 32-wide k-step,
+//   and those eight values are the lane's A operand as they are (k slot
+//   8 q + e holds p = 4 q + e for e < 4, 16 + 4 q + e - 4 above), the Sh2
+//   rows being staged with the same order of p.  Lane (x, q) then holds
+//   X1[p][P2] and X1[n1 - 1 - p][P2] for p = 16 t + 4 q + r, folds them for
+//   both halves of axis 1 (as the separate middle pass does) and stores the
+//   bf16 hi / lo parts to LDS.
+//   Axis-1 step: A = Sh1 (the wave's mode rows, in registers for the whole
+//   kernel), B = the folded plane from LDS, three products per k-step in the
+//   order of the separate pass.
+template <int KH1, int KH2>
+struct alignas(16) GmSmem {
+  uint16_t S2[2][64][KH2 + 8];         // [hi/lo][P2 of the chunk][p, permuted]
+  uint16_t Cg[2][KH2][SGEN_MAX_TERMS + 8];   // [hi/lo][p][m] of this half's table
+  uint16_t U[2][2][64][KH1 + 8];       // [h1][hi/lo][P2 of the chunk][p]
+};
+
+struct GmArgs {
+  float *Y;                 // [F][np0][np1][np2]
+  int64_t planes;           // F * n0
+  int n0, np0;
+  int n1, H1, np1;          // axis 1 (Kh1 = np1 / 2)
+  int np2;                  // axis 2 (Kh2 = np2 / 2)
+  const uint16_t *S1hi, *S1lo, *S2hi, *S2lo;   // [2][Kh][Kh] of axes 1 and 2
+  GenSrcF gen;
+};
+
+constexpr int GM_NT = 512;
+
+template <int KH1, int KH2>
+__global__ __launch_bounds__(GM_NT) void k_split_gen_mid(GmArgs a) {
+  constexpr int NCH = KH2 / 32;        // 64-wide chunks of P2 (both halves)
+  constexpr int KT1 = KH1 / 32, KT2 = KH2 / 32;
+  constexpr int NPAIR = KH1 / 16;      // row tiles (with their mirrors)
+  constexpr int WPP = 8 / NPAIR;       // waves per row tile (2 at Kh1 = 64)
+  constexpr int JA = 4 / WPP;          // P2 tiles per wave, axis-2 step
+  constexpr int IB = KH1 / 64;         // mode tiles per wave, axis-1 step
+  static_assert(NPAIR * WPP == 8 && KH2 % 64 == 0, "shape");
+  __shared__ GmSmem<KH1, KH2> sm;
+
+  const int chunk = int(blockIdx.x % NCH);
+  const int h2 = chunk / (KH2 / 64);
+  const int c0 = (chunk % (KH2 / 64)) * 64;        // first j of the chunk in half h2
+  const int P2b = h2 * KH2 + c0;
+  const int64_t pstride = gridDim.x / NCH;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int M = a.gen.M;
+
+  // Sh2 rows of the chunk, p permuted within each 32-wide k-step
+  for (int e = t; e < 2 * 64 * KT2 * 8; e += GM_NT) {
+    const int part = e & 1, g8 = (e >> 1) & 3, kp = (e >> 3) % KT2;
+    const int n = (e >> 3) / KT2 % 64, hl = (e >> 3) / KT2 / 64;
+    const int p = 32 * kp + 16 * part + 4 * g8;      // four p of this piece
+    const uint16_t *src = (hl ? a.S2lo : a.S2hi) + (int64_t(h2) * KH2 + c0 + n) * KH2 + p;
+    *reinterpret_cast<uint2 *>(&sm.S2[hl][n][32 * kp + 8 * g8 + 4 * part]) =
+        *reinterpret_cast<const uint2 *>(src);
+  }
+  // this half's quadrature table Cf^T (bf16 hi / lo, [p][m])
+  const uint16_t *cft = a.gen.Cft;
+  for (int e = t; e < 2 * KH2 * 4; e += GM_NT) {
+    const int q = e & 3, p = (e >> 2) % KH2, hl = (e >> 2) / KH2;
+    const int64_t o = (int64_t(hl) * 2 * KH2 + int64_t(h2) * KH2 + p) * SGEN_MAX_TERMS + 8 * q;
+    *reinterpret_cast<uint4 *>(&sm.Cg[hl][p][8 * q]) = *reinterpret_cast<const uint4 *>(cft + o);
+  }
+  // the wave's rows of Sh1 (axis-1 step A operands), kept for all planes
+  const int h1 = wave >> 2;
+  bf16x8 ah1[IB][KT1], al1[IB][KT1];
+#pragma unroll
+  for (int ii = 0; ii < IB; ++ii)
+#pragma unroll
+    for (int kp = 0; kp < KT1; ++kp) {
+      const int64_t o = (int64_t(h1) * KH1 + 16 * ((wave & 3) * IB + ii) + lr) * KH1 + 32 * kp + 8 * lk;
+      ah1[ii][kp] = *reinterpret_cast<const bf16x8 *>(a.S1hi + o);
+      al1[ii][kp] = *reinterpret_cast<const bf16x8 *>(a.S1lo + o);
+    }
+  __syncthreads();
+
+  const int rt = wave / WPP;               // row tile of the axis-2 step
+  const int ja0 = (wave % WPP) * JA;       // its first P2 tile
+  const double *C0 = a.gen.C0, *C1 = a.gen.C1;
+  for (int64_t pl = blockIdx.x / NCH; pl < a.planes; pl += pstride) {
+    const int64_t f = pl / a.n0;
+    const int i0 = int(pl - f * a.n0);
+    // row factors of the tile's rows and of their mirrors (MFMA B operands)
+    bf16x8 rfh[2], rfl[2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+      const int i1 = mi == 0 ? 16 * rt + lr : a.n1 - 1 - (16 * rt + lr);
+      f8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int m = 8 * lk + e;
+        const int mm = m < M ? m : M - 1;
+        const double x = a.gen.coef[f * M + mm] * C0[int64_t(mm) * a.np0 + i0] *
+                         C1[int64_t(mm) * a.np1 + i1];
+        v[e] = m < M ? float(x) : 0.0f;
+      }
+      split8(v, rfh[mi], rfl[mi]);
+    }
+    // axis 2: generated loads times the chunk's Sh2 rows
+    f4 acc[2][JA];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int j = 0; j < JA; ++j) acc[mi][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kp = 0; kp < KT2; ++kp) {
+      bf16x8 gh[2], gl[2];
+#pragma unroll
+      for (int pt = 0; pt < 2; ++pt) {
+        gh[pt] = *reinterpret_cast<const bf16x8 *>(&sm.Cg[0][32 * kp + 16 * pt + lr][8 * lk]);
+        gl[pt] = *reinterpret_cast<const bf16x8 *>(&sm.Cg[1][32 * kp + 16 * pt + lr][8 * lk]);
+      }
+      bf16x8 lh[2], ll[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        f8 v;
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt) {
+          f4 c = f4{0.f, 0.f, 0.f, 0.f};
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[pt], rfh[mi], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gh[pt], rfl[mi], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl[pt], rfh[mi], c, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[4 * pt + r] = c[r];
+        }
+        split8(v, lh[mi], ll[mi]);
+      }
+#pragma unroll
+      for (int j = 0; j < JA; ++j) {
+        const int n = 16 * (ja0 + j) + lr;
+        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sm.S2[0][n][32 * kp + 8 * lk]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sm.S2[1][n][32 * kp + 8 * lk]);
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+          acc[mi][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lh[mi], bh, acc[mi][j], 0, 0, 0);
+          acc[mi][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ll[mi], bh, acc[mi][j], 0, 0, 0);
+          acc[mi][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lh[mi], bl, acc[mi][j], 0, 0, 0);
+        }
+      }
+    }
+    // fold along axis 1 (p = 16 rt + 4 lk + r: x_p from the tile, x_{n1-1-p}
+    // from the mirror tile), split, into the LDS plane
+#pragma unroll
+    for (int j = 0; j < JA; ++j) {
+      f4 u, w;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = 16 * rt + 4 * lk + r;
+        const bool has_b = p < a.H1;
+        const bool has_a0 = has_b || (p == a.H1 && (a.n1 & 1));
+        const float xa = acc[0][j][r], xb = acc[1][j][r];
+        u[r] = (has_a0 ? xa : 0.0f) + (has_b ? xb : 0.0f);
+        w[r] = (has_b ? xa : 0.0f) + (has_b ? -xb : 0.0f);
+      }
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      const bf16x4 uh = __builtin_convertvector(u, bf16x4);
+      const bf16x4 ul = __builtin_convertvector(u - __builtin_convertvector(uh, f4), bf16x4);
+      const bf16x4 wh = __builtin_convertvector(w, bf16x4);
+      const bf16x4 wl = __builtin_convertvector(w - __builtin_convertvector(wh, f4), bf16x4);
+      const int n = 16 * (ja0 + j) + lr, p0 = 16 * rt + 4 * lk;
+      *reinterpret_cast<bf16x4 *>(&sm.U[0][0][n][p0]) = uh;
+      *reinterpret_cast<bf16x4 *>(&sm.U[0][1][n][p0]) = ul;
+      *reinterpret_cast<bf16x4 *>(&sm.U[1][0][n][p0]) = wh;
+      *reinterpret_cast<bf16x4 *>(&sm.U[1][1][n][p0]) = wl;
+    }
+    __syncthreads();
+
+    // axis 1: the wave's mode rows of half h1 times the folded plane
+    f4 z[IB][4];
+#pragma unroll
+    for (int ii = 0; ii < IB; ++ii)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) z[ii][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kp = 0; kp < KT1; ++kp) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sm.U[h1][0][16 * j + lr][32 * kp + 8 * lk]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sm.U[h1][1][16 * j + lr][32 * kp + 8 * lk]);
+#pragma unroll
+        for (int ii = 0; ii < IB; ++ii) {
+          z[ii][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1[ii][kp], bh, z[ii][j], 0, 0, 0);
+          z[ii][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1[ii][kp], bl, z[ii][j], 0, 0, 0);
+          z[ii][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1[ii][kp], bh, z[ii][j], 0, 0, 0);
+        }
+      }
+    }
+    // lane (x, q) holds modes 4 q + r of the tile at column x of each P2 tile
+    float *Yp = a.Y + (f * a.np0 + i0) * int64_t(a.np1) * a.np2 + P2b + lr;
+#pragma unroll
+    for (int ii = 0; ii < IB; ++ii)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int P1 = h1 * KH1 + 16 * ((wave & 3) * IB + ii) + 4 * lk + r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          __builtin_nontemporal_store(z[ii][j][r], Yp + int64_t(P1) * a.np2 + 16 * j);
+      }
+    __syncthreads();   // the plane buffer is the next plane's
+  }
+}
+
+bool split_gen_mid_supported(pe_grid g, int n_terms) {
+  if (g->dim != 3 || g->precision != PE_SPLIT_BF16 || !g->fuse_gen_mid) return false;
+  if (!gen_supported_split(g, n_terms) || !fused_update_supported(g)) return false;
+  const int k1 = g->ax[1].Kh, k2 = g->ax[2].Kh;
+  return (k1 == 64 || k1 == 128) && (k2 == 64 || k2 == 128);
+}
+
+template <int KH1, int KH2>
+static pe_status launch_gen_mid(const GmArgs &a, hipStream_t st) {
+  constexpr int NCH = KH2 / 32;
+  int dev = 0, cus = 0, per_cu = 0;
+  PE_HIP(hipGetDevice(&dev));
+  PE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  PE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split_gen_mid<KH1, KH2>, GM_NT, 0));
+  // persistent blocks, as many as fit at once (the LDS of one or two per
+  // compute unit), each chunk served by the same number of them
+  const int64_t per_chunk =
+      std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * std::max(per_cu, 1) / NCH, a.planes));
+  k_split_gen_mid<KH1, KH2><<<dim3(unsigned(per_chunk * NCH)), GM_NT, 0, st>>>(a);
+  PE_HIP(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status split_gen_mid(pe_grid g, int64_t count, const GenSrcF *gen, float *out, hipStream_t st) {
+  const Axis &x0 = g->ax[0], &x1 = g->ax[1], &x2 = g->ax[2];
+  GmArgs a{};
+  a.Y = out;
+  a.planes = count * x0.n;
+  a.n0 = x0.n;
+  a.np0 = x0.np;
+  a.n1 = x1.n;
+  a.H1 = x1.H;
+  a.np1 = x1.np;
+  a.np2 = x2.np;
+  a.S1hi = x1.d_Shi;
+  a.S1lo = x1.d_Slo;
+  a.S2hi = x2.d_Shi;
+  a.S2lo = x2.d_Slo;
+  a.gen = *gen;
+  // work: both transforms (three bf16 products each, folded); bytes: one
+  // write of the axis-0 nodes' planes plus the per-field coefficients
+  const double lines2 = double(count) * x0.n * x1.n, lines1 = double(count) * x0.n * x2.n;
+  const double fl = 3.0 * 2.0 *
+                    (lines2 * (double((x2.n + 1) / 2) * ((x2.n + 1) / 2) + double(x2.H) * x2.H) +
+                     lines1 * (double((x1.n + 1) / 2) * ((x1.n + 1) / 2) + double(x1.H) * x1.H));
+  const double bytes = double(count) * x0.n * double(x1.np) * x2.np * sizeof(float) +
+                       double(count) * gen->M * sizeof(double);
+  TimedScope ts(g, PE_K_DST_LAST, fl, bytes, st);
+  if (x1.Kh == 128 && x2.Kh == 128) return launch_gen_mid<128, 128>(a, st);
+  if (x1.Kh == 128 && x2.Kh == 64) return launch_gen_mid<128, 64>(a, st);
+  if (x1.Kh == 64 && x2.Kh == 128) return launch_gen_mid<64, 128>(a, st);
+  if (x1.Kh == 64 && x2.Kh == 64) return launch_gen_mid<64, 64>(a, st);
+  return set_error(PE_E_ARG, "internal: no fused generating pass for Kh %d / %d", x1.Kh, x2.Kh);
+}
+
 // ------------------------------------------------------------------ dispatch
 constexpr int64_t SMAX_BLOCKS = (int64_t(1) << 24) - 1;
 
@@ -407,8 +680,16 @@ pe_status split_gen_table(pe_grid g, const double *Cf, int M, uint16_t *Cft, hip
 }
 
 pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,
-                           float **result, hipStream_t st, int stop_axis) {
+                           float **result, hipStream_t st, int stop_axis, bool *axis0_outer) {
   if (!g->ax[0].d_Shi) return set_error(PE_E_UNSUPPORTED, "grid has no split-bf16 tables");
+  if (axis0_outer) *axis0_outer = false;
+  if (gen && stop_axis == 1 && axis0_outer && split_gen_mid_supported(g, gen->M)) {
+    if (!gen->Cft) return set_error(PE_E_ARG, "internal: split generating pass without its table");
+    PE_TRY(split_gen_mid(g, count, gen, buf0, st));
+    *result = buf0;
+    *axis0_outer = true;
+    return PE_OK;
+  }
   float *in = buf0, *out = buf1;
   const int d = g->dim;
   // axis contracted by pass q: d-1, d-2, ..., 0 (rotating layout)

@@ -283,7 +283,9 @@ static pe_status launch_load(pe_grid g, double *const *C, int n_terms, const dou
 }
 
 static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *work0, void *work1,
-                           void **result, hipStream_t st, int stop_axis = 0) {
+                           void **result, hipStream_t st, int stop_axis = 0,
+                           bool *axis0_outer = nullptr) {
+  if (axis0_outer) *axis0_outer = false;
   if (g->transform == PE_TRANSFORM_FFT) {
     double *r = nullptr;
     PE_TRY(dst_fields_fft(g, count, gen, static_cast<double *>(work0), static_cast<double *>(work1),
@@ -306,14 +308,16 @@ static pe_status transform(pe_grid g, int64_t count, const GenSrc *gen, void *wo
       gf.M = gen->M;
     }
     PE_TRY(dst_fields_split(g, count, gen ? &gf : nullptr, static_cast<float *>(work0),
-                            static_cast<float *>(work1), &r, st, stop_axis));
+                            static_cast<float *>(work1), &r, st, stop_axis, axis0_outer));
     *result = r;
   }
   return PE_OK;
 }
 
 pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
-                             double *coef, void **result, hipStream_t st, int stop_axis) {
+                             double *coef, void **result, hipStream_t st, int stop_axis,
+                             bool *axis0_outer) {
+  if (axis0_outer) *axis0_outer = false;
   int64_t count = b.count();
   int64_t nc = count * g->n_terms;
   k_time_coefs<<<blocks_for(nc), 256, 0, st>>>(b, g->d_terms, g->n_terms, coef, count);
@@ -333,7 +337,7 @@ pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *
     gs.Cft = g->d_Cft;
     gs.Cl = g->d_C[g->dim - 1];
     gs.M = g->n_terms;
-    return transform(g, count, &gs, work0, work1, result, st, stop_axis);
+    return transform(g, count, &gs, work0, work1, result, st, stop_axis, axis0_outer);
   }
   PE_TRY(launch_load(g, g->d_C, g->n_terms, coef, work0, count, st));
   if (hats) {
@@ -443,13 +447,14 @@ pe_status run_propagation(pe_grid g, int N, double t0, double dT, double dt, int
       b.dt = dt;
       for (int i = 0; i < s; ++i) b.c[i] = c[i];
       void *res = nullptr;
-      PE_TRY(load_and_transform(g, b, w0, w1, coef, &res, st, fused ? 1 : 0));
+      bool outer = false;
+      PE_TRY(load_and_transform(g, b, w0, w1, coef, &res, st, fused ? 1 : 0, &outer));
       const char *uin = (j0 == 0) ? static_cast<const char *>(d_Uin)
                                   : static_cast<const char *>(d_Uout);
       if (uin) uin += size_t(n0) * dof * sbytes;
       char *uout = static_cast<char *>(d_Uout) + size_t(n0) * dof * sbytes;
       if (fused) {
-        PE_TRY(final_pass_update(g, b, res, Tp, uin, uout, st));
+        PE_TRY(final_pass_update(g, b, res, Tp, uin, uout, st, outer));
         continue;
       }
       const int chunk = update_chunk(nb, dof);

@@ -331,6 +331,9 @@ __global__ void k_update_tables(FuArgs a, int RT, const double *__restrict__ sig
 // Waves: half h = wave / 4 and TM = Kh/64 mode tiles each; lane l holds
 // C[4 (l/16) + r][l%16], i.e. 4 TM modes of row l%16, whose states stay in
 // FP64 registers for the whole slice (as the separate update computes them).
+// AXIS0_OUTER: the input is X[f][p][r] instead (the fused generating and
+// middle-axis pass writes axis 0 outermost); a loader item then reads its
+// four p of one row r as single values, sixteen consecutive rows per p.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -338,7 +341,7 @@ typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4_t __attribute__((ext_vector_type(4)));
 
-template <int KH, int DEPTH>
+template <int KH, int DEPTH, bool AXIS0_OUTER>
 __global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
   constexpr int NTH = 512;
   constexpr int TM = KH / 64;     // mode tiles per wave
@@ -386,10 +389,12 @@ __global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
   // field e + 1 is stashed), so each load has DEPTH fields of time to land.
   // The strips are read once: streaming (nontemporal) loads leave L2 to the
   // update tables, which every step of the slice reads again.
-  const int lrow = t / CPR, lc = t % CPR, p0 = 4 * lc;
+  const int lrow = AXIS0_OUTER ? t % 16 : t / CPR, lc = AXIS0_OUTER ? t / 16 : t % CPR;
+  const int p0 = 4 * lc;
   const bool active = t < ITEMS;
   const int64_t fstride = int64_t(a.I) * (2 * KH);
-  const float *Xr = a.Xs + int64_t(nl) * nf * fstride + (int64_t(rt) * 16 + (active ? lrow : 0)) * (2 * KH);
+  const float *Xr = a.Xs + int64_t(nl) * nf * fstride +
+                    (int64_t(rt) * 16 + (active ? lrow : 0)) * (AXIS0_OUTER ? 1 : 2 * KH);
   struct Raw {
     f4_t xa, xb;
   };
@@ -397,6 +402,15 @@ __global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
   auto load = [&](Raw &R, int e) {
     if (!active || e >= nf) return;
     const float *x = Xr + e * fstride;
+    if constexpr (AXIS0_OUTER) {
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        const int i = a.n0 - 1 - p0 - e2;
+        R.xa[e2] = __builtin_nontemporal_load(x + int64_t(p0 + e2) * a.I);
+        R.xb[e2] = __builtin_nontemporal_load(x + int64_t(i > 0 ? i : 0) * a.I);
+      }
+      return;
+    }
     R.xa = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(x + p0));
     const int mb = a.n0 - 4 - p0;   // x[n-1-p0-e], e = 0..3: one ascending run
     if (mb >= 0) {
@@ -624,7 +638,16 @@ static void launch_q(const FuArgs &a, int64_t nslices, hipStream_t st) {
   k_final_update<Q, HB, FPB><<<dim3(unsigned(blocks)), HB * Q * 4, 0, st>>>(a);
 }
 
-static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, hipStream_t st) {
+template <int KH>
+static void launch_split_final(const FuArgs &a, int64_t blocks, bool axis0_outer, hipStream_t st) {
+  if (axis0_outer)
+    k_split_final_update<KH, SPLIT_DEPTH, true><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
+  else
+    k_split_final_update<KH, SPLIT_DEPTH, false><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
+}
+
+static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, bool axis0_outer,
+                                    hipStream_t st) {
   const Axis &x0 = g->ax[0];
   a.Shi = x0.d_Shi;
   a.Slo = x0.d_Slo;
@@ -641,15 +664,15 @@ static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, hi
                        double(1 + b.s) * double(g->dof) * 8.0;
   TimedScope ts(g, PE_K_MID_UPDATE, flops, bytes, st);
   if (x0.Kh == 128)
-    k_split_final_update<128, SPLIT_DEPTH><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
+    launch_split_final<128>(a, blocks, axis0_outer, st);
   else
-    k_split_final_update<64, SPLIT_DEPTH><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
+    launch_split_final<64>(a, blocks, axis0_outer, st);
   PE_HIP(hipGetLastError());
   return PE_OK;
 }
 
 pe_status final_pass_update(pe_grid g, const FieldBatch &b, const void *X, const double *Tp,
-                            const void *Uin, void *Uout, hipStream_t st) {
+                            const void *Uin, void *Uout, hipStream_t st, bool axis0_outer) {
   if (!fused_update_supported(g)) return set_error(PE_E_ARG, "internal: no fused update here");
   if (g->transform == PE_TRANSFORM_FFT)
     return fft_final_update(g, b, static_cast<const double *>(X), Tp,
@@ -663,7 +686,7 @@ pe_status final_pass_update(pe_grid g, const FieldBatch &b, const void *X, const
     a.Xs = static_cast<const float *>(X);
     a.Uins = static_cast<const float *>(Uin);
     a.Uouts = static_cast<float *>(Uout);
-    return split_final_update(g, b, a, st);
+    return split_final_update(g, b, a, axis0_outer, st);
   }
   a.X = static_cast<const double *>(X);
   a.Sq = x0.d_Sq;

@@ -682,6 +682,13 @@ pe_status pe_set_transform(pe_grid g, int32_t kind) {
   return PE_OK;
 }
 
+pe_status pe_set_fusion(pe_grid g, int32_t enable) {
+  clear_error();
+  if (!g) return set_error(PE_E_ARG, "null grid");
+  g->fuse_gen_mid = enable != 0;
+  return PE_OK;
+}
+
 // The internal term list: the forcing (loads by the grid's Gauss rule)
 // followed by the derived terms of the Dirichlet data (explicit tables).
 static pe_status rebuild_terms(pe_grid g, hipStream_t st) {

@@ -138,6 +138,8 @@ struct pe_grid_s {
   int precision = PE_FP64;
   int quad_q = 3;
   int transform = PE_TRANSFORM_DENSE;
+  // 3D split-bf16 grids: generating and middle-axis passes as one kernel
+  bool fuse_gen_mid = true;
   double D = 0;
   int64_t dof = 0;               // prod n_a
   int64_t dofp = 0;              // prod np_a (padded field size)
@@ -229,8 +231,11 @@ struct FieldBatch {
 // coefficients (before the 1/sqrt(mu) scaling).  work0/work1 each hold
 // batch.count() padded fields of the grid's stage type; coef holds
 // count * n_terms doubles.  Returns the buffer holding the result.
+// (axis0_outer, when given, receives the layout of a stop_axis = 1 result:
+// false [count][R][np_0], true [count][np_0][R]; see dst_fields_split)
 pe_status load_and_transform(pe_grid g, const FieldBatch &b, void *work0, void *work1,
-                             double *coef, void **result, hipStream_t st, int stop_axis = 0);
+                             double *coef, void **result, hipStream_t st, int stop_axis = 0,
+                             bool *axis0_outer = nullptr);
 
 // Axis-0 pass fused with the diagonal update (d >= 2): FP64 grids whose
 // axis 0 has two fold levels and Q = Kh/2 a multiple of 16 up to 128;
@@ -241,10 +246,11 @@ bool fused_update_supported(pe_grid g);
 size_t fused_update_table_bytes(pe_grid g);
 pe_status fused_update_tables(pe_grid g, int s, const double *E, const double *B, double *Tp,
                               hipStream_t st);
-// X: the batch after the passes over axes d-1..1 (stage type of the grid);
+// X: the batch after the passes over axes d-1..1 (stage type of the grid;
+// split grids: [count][R][np_0], or [count][np_0][R] with axis0_outer);
 // Uin (nullable) / Uout: the batch's slice states (state type).
 pe_status final_pass_update(pe_grid g, const FieldBatch &b, const void *X, const double *Tp,
-                            const void *Uin, void *Uout, hipStream_t st);
+                            const void *Uin, void *Uout, hipStream_t st, bool axis0_outer = false);
 
 // Load-vector generation inside the first (last-axis) transform pass: the
 // nodal load of field f at node (j_0, .., j_{d-1}) is
@@ -285,9 +291,16 @@ size_t split_gen_table_bytes(pe_grid g);
 pe_status split_gen_table(pe_grid g, const double *Cf, int M, uint16_t *Cft, hipStream_t st);
 // (stop_axis = 1 leaves out the last pass, the one that contracts axis 0:
 // the batch is then [count][R][np_0] with the other axes transformed)
+// With gen, stop_axis = 1 and axis0_outer set, 3D grids that qualify
+// (split_gen_mid_supported) run the generating and middle-axis passes as one
+// kernel whose result is [count][np_0][R] (axis 0 outermost, *axis0_outer =
+// true); otherwise *axis0_outer = false.
 pe_status dst_fields_split(pe_grid g, int64_t count, const GenSrcF *gen, float *buf0, float *buf1,
-                           float **result, hipStream_t st, int stop_axis = 0);
+                           float **result, hipStream_t st, int stop_axis = 0,
+                           bool *axis0_outer = nullptr);
 bool gen_supported_split(pe_grid g, int n_terms);
+bool split_gen_mid_supported(pe_grid g, int n_terms);
+pe_status split_gen_mid(pe_grid g, int64_t count, const GenSrcF *gen, float *out, hipStream_t st);
 // true when the fused generation path can take n_terms terms
 bool gen_supported(pe_grid g, int n_terms);
 // Cf[h][m][p] from C[m][j] of the last axis (device)

@@ -35,7 +35,8 @@ PE_TRANSFORM_DENSE = 0
 PE_TRANSFORM_FFT = 1
 
 EXPORTS = [
-    "pe_init_grid", "pe_init_grid_periodic", "pe_free_grid", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+    "pe_init_grid", "pe_init_grid_periodic", "pe_free_grid", "pe_set_transform", "pe_set_fusion",
+    "pe_set_forcing", "pe_set_boundary",
     "pe_set_moving_sources",
     "pe_phi_tables", "pe_project_workspace_bytes", "pe_project", "pe_project_state",
     "pe_fine_workspace_bytes",
@@ -123,6 +124,7 @@ def load_library():
     L.pe_free_grid.argtypes = [vp]
     L.pe_free_grid.restype = None
     L.pe_set_transform.argtypes = [vp, i32]
+    L.pe_set_fusion.argtypes = [vp, i32]
     L.pe_set_forcing.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
     L.pe_set_boundary.argtypes = [vp, i32, ctypes.POINTER(Term), vp]
     L.pe_set_moving_sources.argtypes = [vp, i32, ctypes.POINTER(MovingHat), vp]
@@ -170,7 +172,8 @@ def load_library():
                                         vp, sz, vp]
     L.pe_last_error.argtypes = []
     L.pe_last_error.restype = ctypes.c_char_p
-    for name in ("pe_init_grid", "pe_init_grid_periodic", "pe_set_transform", "pe_set_forcing", "pe_set_boundary",
+    for name in ("pe_init_grid", "pe_init_grid_periodic", "pe_set_transform", "pe_set_fusion",
+                 "pe_set_forcing", "pe_set_boundary",
                  "pe_set_moving_sources",
                  "pe_project_state", "pe_phi_tables", "pe_project",
                  "pe_fine_propagate", "pe_coarse_sweep", "pe_coarse_sweep_noalloc",
@@ -276,6 +279,11 @@ class Grid:
         if getattr(prob, "moving", None):
             g.set_moving_sources(prob.moving)
         return g
+
+    def set_fusion(self, enable: bool):
+        """Generating and middle-axis passes as one kernel on 3D split-bf16
+        grids (the default) or as two passes."""
+        _check(self.L.pe_set_fusion(self.h, 1 if enable else 0))
 
     def set_transform(self, kind: str):
         """"dense" (matrix-core products) or "fft" (LDS FFT of the odd extension)."""

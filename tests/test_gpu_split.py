@@ -98,6 +98,90 @@ def test_split_fused_update_matches_separate_kernels(dim, n, N, J, s):
     assert rel(fused, sep) <= 2e-6
 
 
+def _every_chunk_sines(prob, seed):
+    """Sine terms whose modes fall in every 64-wide chunk of both halves of
+    axes 1 and 2 (k = 1, 2: first chunk of each half; 129, 130: the second
+    chunk when Kh = 128; n - 1, n: the last)."""
+    rng = np.random.default_rng(seed)
+    n0, n1, n2 = prob.n
+    box = list(zip(prob.lo, prob.hi))
+    ks = [(1, 1, 2), (2, 2, 1), (n0, n1, n2), (n0 - 1, n1 - 1, n2 - 1),
+          (3, min(129, n1), min(129, n2)), (4, min(130, n1), min(130, n2)),
+          (5, min(n1, 2 * 64 - 1), 3), (6, 4, min(n2, 2 * 64))]
+    terms = [wl.Term(float(rng.uniform(0.5, 1.5)) * (-1) ** i,
+                     wl.TimeFactor(omega=float(rng.uniform(1.0, 20.0))),
+                     tuple(wl.sine_factor(k, lo, hi) for k, (lo, hi) in zip(kk, box)))
+             for i, kk in enumerate(ks)]
+    return terms
+
+
+@pytest.mark.parametrize("n,s", [((65, 67, 69), 3), ((100, 200, 90), 4), ((66, 100, 255), 3),
+                                 ((70, 193, 200), 3), ((128, 256, 193), 2)])
+def test_split_gen_mid_sampled(n, s):
+    """3D split grids whose axes 1 and 2 have Kh = 64 / 128 (odd and even n):
+    the generating and middle-axis passes run as one kernel.  From a zero
+    state, so that the output is the transformed loads' share alone, with
+    sine terms forcing modes in every chunk and half of axes 1 and 2 and a
+    polynomial term reaching every mode: each sine-forced mode against the
+    selected-mode oracle (relative error 1e-3 each, 2e-5 in L2), and 400
+    random modes to the split path's absolute error (relative to the largest
+    coefficient)."""
+    from oracle import modal
+    pe = _peifem()
+    prob = wl.tiny_problem(3, n, seed=23, s=s, N=2, J=2, n_modes=1, T=0.9,
+                           precision="split_bf16")
+    prob.forcing[:] = _every_chunk_sines(prob, 25)
+    forced = modal.forced_modes(prob)                 # the sine terms' modes
+    # a polynomial term reaches every mode
+    prob.forcing.append(wl.Term(0.8, wl.TimeFactor(omega=3.0, poly=(1.0, 0.5, 0.0, 0.0)),
+                                (wl.poly_factor(0.2, 1.0, -0.7), wl.poly_factor(1.0, -0.3, 0.1),
+                                 wl.poly_factor(0.5, 0.2, 0.3))))
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    zero = np.zeros((prob.N,) + prob.n)
+    out = g.fine_propagate(_dev32(zero), prob.t0, prob.dT, prob.J, prob.c_fine, E, B).cpu().numpy()
+    rng = np.random.default_rng(24)
+    extra = np.stack([rng.integers(0, prob.n[a], 400) for a in range(3)], axis=1)
+    sel = np.unique(np.concatenate([forced, extra]), axis=0)
+    fine = modal.ModalFine(prob, sel)
+    is_forced = np.isin(sel.view([("", sel.dtype)] * 3), forced.view([("", forced.dtype)] * 3)).ravel()
+    idx = tuple(sel.T)
+    for k in range(prob.N):
+        ref = fine.propagate(zero[k][idx], prob.t0 + k * prob.dT)
+        got = out[k][idx]
+        # each sine-forced mode on its own (their values span four decades:
+        # the split products' error is relative to the loads, not to the
+        # decayed coefficient of a high mode)
+        rel_each = np.abs(got[is_forced] - ref[is_forced]) / np.abs(ref[is_forced])
+        assert rel_each.max() <= 1e-3, (k, rel_each)
+        assert rel(got[is_forced], ref[is_forced]) <= SPLIT_TOL, k
+        assert np.abs(got - ref).max() <= SPLIT_TOL * np.abs(ref).max(), k
+
+
+@pytest.mark.parametrize("n,N,J,s,modes", [((65, 67, 69), 2, 3, 3, 4), ((100, 200, 90), 2, 2, 4, 9),
+                                           ((66, 100, 255), 1, 2, 3, 32), ((128, 256, 193), 1, 1, 3, 5)])
+def test_split_gen_mid_fused_matches_two_passes(n, N, J, s, modes):
+    """3D split grids: the generating and middle-axis passes as one kernel
+    (axis-2 results kept on chip, output with axis 0 outermost, read so by the
+    fused axis-0 pass) against the two separate passes (pe_set_fusion(0)).
+    Same products; the fused kernel orders each 32-wide k-step of the axis-2
+    product differently, so the two agree to fp32 rounding."""
+    pe = _peifem()
+    prob = wl.tiny_problem(3, n, seed=21, s=s, N=N, J=J, n_modes=modes, T=0.9,
+                           precision="split_bf16")
+    rng = np.random.default_rng(22)
+    Uin = _dev32(rng.normal(size=(N,) + prob.n))
+    g = pe.Grid.from_problem(prob)
+    E, B = g.phi_tables(prob.dt, prob.c_fine)
+    fused = g.fine_propagate(Uin, prob.t0, prob.dT, J, prob.c_fine, E, B).cpu().numpy()
+    g.set_fusion(False)
+    two = g.fine_propagate(Uin, prob.t0, prob.dT, J, prob.c_fine, E, B).cpu().numpy()
+    g.set_fusion(True)
+    again = g.fine_propagate(Uin, prob.t0, prob.dT, J, prob.c_fine, E, B).cpu().numpy()
+    assert np.array_equal(fused, again)
+    assert rel(fused, two) <= 1e-6
+
+
 @pytest.mark.parametrize("dim,n", [(2, (45, 38)), (3, (15, 31, 9)), (2, (127, 20))])
 def test_split_parareal(dim, n):
     pe = _peifem()
