@@ -45,10 +45,12 @@ sys.path.insert(0, ROOT)
 METRIC = "fine DOF·stage updates/s + Parareal wall time to 1e-8 jump, learned vs plain G"
 UNIT = "fine DOF·stage updates/s"
 PEAK_FP64_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
+PEAK_BF16_TFLOPS = 2500.0     # MI355X dense bf16 matrix peak (split-bf16 products)
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 
 KERNEL_NAMES = {
-    "dst_last": "last-axis DST-I pass with the fused load quadrature (generating pass)",
+    "dst_last": "last-axis DST-I pass with the fused load quadrature (generating pass; 3D "
+                "split grids: fused with the middle-axis pass)",
     "dst_mid": "DST-I pass along another axis",
     "mid_update": "axis-0 DST-I pass fused with the diagonal update",
     "load": "separate load quadrature", "update": "separate diagonal update",
@@ -229,11 +231,13 @@ def roofline(stats, tag, peak_tflops=PEAK_FP64_TFLOPS):
     return roof
 
 
-def solve_entry(prob, cfg, steps, warmup, tag=None, mlp=None):
+def solve_entry(prob, cfg, steps, warmup, tag=None, mlp=None, fusion=True):
     """Timed plain- (or learned-) G solves of a workload with the kernel
-    table and the error against the oracle."""
+    table and the error against the oracle (fusion=False: the generating
+    and middle-axis passes of 3D split grids as two kernels)."""
     from paper_2412_01138_amd import peifem
     g = peifem.Grid.from_problem(prob)
+    g.set_fusion(fusion)
     P = g.solve_params(prob.t0, prob.T, prob.N, prob.J, prob.c_coarse, prob.c_fine,
                        prob.K_max, prob.tol, None, mlp)
     sec, reports, stats, U = timed_solves(g, P, steps, warmup, timing=True)
@@ -244,7 +248,8 @@ def solve_entry(prob, cfg, steps, warmup, tag=None, mlp=None):
            "fine_updates_per_s": upd / (ms / 1e3), **report_summary(rep),
            "kernels": kernel_table(stats), **oracle_error(cfg, U)}
     if tag:
-        out["roofline"] = roofline(stats, tag)
+        peak = PEAK_FP64_TFLOPS if prob.precision == "fp64" else PEAK_BF16_TFLOPS
+        out["roofline"] = roofline(stats, tag, peak)
     del U, g
     return out
 
@@ -334,6 +339,11 @@ def split_workloads(steps, learned_forcings, learned_steps):
         prob = wl.config(cfg)
         out[prob.name] = solve_entry(prob, cfg, steps, 1, tag=f"w{cfg}")
         torch.cuda.empty_cache()
+    # the same 255^3 solve with the generating and middle-axis passes as two
+    # kernels (the axis-2 results through HBM)
+    prob = wl.config(5)
+    out[prob.name + " two-pass"] = solve_entry(prob, 5, steps, 1, fusion=False)
+    torch.cuda.empty_cache()
     if learned_forcings > 0:
         prob = wl.config(5)
         t0 = time.perf_counter()
