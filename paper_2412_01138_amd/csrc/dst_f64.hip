@@ -68,6 +68,37 @@ __device__ inline void mma_stage(const double (&As)[KB][BM + 1], const double (&
   }
 }
 
+// Tile layout of the two-level last pass for NTH threads: 2 x NW/2 waves,
+// each (BM/2) x (BN/(NW/2)) outputs of both parities.
+template <int BM, int BN, int NTH>
+struct Cfg2 {
+  static constexpr int NW = NTH / 64;
+  static constexpr int WN = NW / 2;
+  static constexpr int TM = BM / 2 / 16;       // MFMA tiles per wave along M
+  static constexpr int TN = BN / WN / 16;      // ... along N
+  static constexpr int B_PER = KB * BN / NTH;  // B elements per thread per k-step
+  static constexpr int TPR = NTH / BM;         // threads per A row
+  static constexpr int CPT = KB / TPR;         // A columns per thread
+};
+
+template <int TM, int TN, int LDA, int LDB>
+__device__ inline void mma_tile(const double (&As)[KB][LDA], const double (&Bs)[KB][LDB],
+                                d4 (&acc)[TM][TN], int mb, int nb, int lr, int lk) {
+#pragma unroll
+  for (int kk = 0; kk < KB; kk += 4) {
+    double av[TM], bv[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) av[i] = As[kk + lk][mb + i * 16 + lr];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bv[j] = Bs[kk + lk][nb + j * 16 + lr];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+}
+
 // Even/odd fold of a nodal line at folded index p, split into the two raw
 // loads (issued early, in-bounds clamped indices, no dependent arithmetic)
 // and the combination (done later, when the k-step is written to LDS).
@@ -504,10 +535,16 @@ __global__ __launch_bounds__(NT) void k_pass_mid2(Mid2Args a) {
 // rows r x jj, or generated from the quadrature tables at those p), the B
 // operand is SqT[h][g] (jj x i); the row of outputs gets y_i = C_0 + C_1
 // and y_i' = C_0 - C_1.
-template <int BM, int BN, int GM>
-__global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
+// NTH = 512 (the generating pass): 8 waves of (BM/2) x (BN/4) outputs, two
+// blocks per CU (the LDS of two), so four waves share each SIMD; a wave
+// generates one 16-row tile of one parity.  NTH = 256: 4 waves of
+// (BM/2) x (BN/2), a wave generates one row tile of both parities.
+template <int BM, int BN, int GM, int NTH>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == 512 ? 4 : 1)))
+void k_pass_last2(LastArgs a) {
   constexpr bool GEN = GM > 0;
-  using C = Cfg<BM, BN>;
+  using C = Cfg2<BM, BN, NTH>;
+  static_assert(BM == 64 && (NTH == 256 || NTH == 512), "tile layout");
   __shared__ Smem2<BM, BN> sm;
 
   const int Q = a.Kh / 2;
@@ -519,15 +556,18 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   const int64_t m0 = tm * BM;
   const int n0 = tn * BN;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+  const int wm = wave / C::WN, wn = wave % C::WN, lr = lane & 15, lk = lane >> 4;
 
   const int ra = t / C::TPR;
   const int ca0 = (t % C::TPR) * C::CPT;
   const int64_t grow = m0 + ra;
   const bool row_ok = grow < a.R;
 
-  constexpr int RW = BM / 4;                 // rows generated per wave
-  constexpr int RT = RW / 16 > 0 ? RW / 16 : 1;
+  // generation: the wave's 16-row tile and its parities [g0, g0 + GPW)
+  constexpr int RTILES = BM / 16;
+  constexpr int GPW = 2 * RTILES / C::NW;
+  const int grt = wave % RTILES, g0 = GPW == 2 ? 0 : wave / RTILES;
+  constexpr int RT = 1;
   constexpr int GK = GM > 0 ? GM / 4 : 1;    // MFMA k-steps over the terms
   double rfa[RT][GK];
   if constexpr (GEN) {
@@ -536,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
     const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      const int64_t gr0 = m0 + wave * RW + rt * 16 + lr;
+      const int64_t gr0 = m0 + grt * 16 + lr;
       const bool ok = gr0 < a.R;
       const int64_t gr = ok ? gr0 : a.R - 1;
       const int64_t f = gr / a.rows_per_field;
@@ -582,7 +622,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
     for (int g = 0; g < 2; ++g)
 #pragma unroll
       for (int q = 0; q < C::B_PER; ++q) {
-        const int e = t + q * NT;
+        const int e = t + q * NTH;
         const int k = e / BN, nl = e % BN;
         const int col = n0 + nl;
         rb[g][q] = SqT[(int64_t(2 * h + g) * Q + k0 + k) * Q + (col < Q ? col : Q - 1)];
@@ -592,7 +632,8 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
     if constexpr (GEN) {
       const int Mm1 = a.gen.M - 1;
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
+      for (int gg = 0; gg < GPW; ++gg) {
+        const int g = g0 + gg;
         double cfb[GK];
 #pragma unroll
         for (int kk = 0; kk < GK; ++kk) {
@@ -606,7 +647,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
           for (int kk = 0; kk < GK; ++kk)
             gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(rfa[rt][kk], cfb[kk], gacc, 0, 0, 0);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sm.A[buf][g][lr][wave * RW + rt * 16 + lk + 4 * r] = gacc[r];
+          for (int r = 0; r < 4; ++r) sm.A[buf][g][lr][grt * 16 + rt * 16 + lk + 4 * r] = gacc[r];
         }
       }
     } else {
@@ -627,7 +668,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
     for (int g = 0; g < 2; ++g)
 #pragma unroll
       for (int q = 0; q < C::B_PER; ++q) {
-        const int e = t + q * NT;
+        const int e = t + q * NTH;
         const int col = n0 + e % BN;
         sm.B[buf][g][e / BN][e % BN] = col < Q ? rb[g][q] : 0.0;
       }
@@ -645,27 +686,28 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
   // plain registers and back around every k-tile, which also made each
   // k-tile wait for all of its products)
   const int nk = Q / KB;
+  const int mb = wm * (BM / 2), nb = wn * (BN / C::WN);
   load(0);
   store(0, 0);
   __syncthreads();
   int buf = 0;
   for (int kt = 0; kt + 1 < nk; ++kt) {
     load((kt + 1) * KB);
-    mma_stage<BM, BN>(sm.A[buf][0], sm.B[buf][0], acc0, wm, wn, lr, lk);
-    mma_stage<BM, BN>(sm.A[buf][1], sm.B[buf][1], acc1, wm, wn, lr, lk);
+    mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][0], sm.B[buf][0], acc0, mb, nb, lr, lk);
+    mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][1], sm.B[buf][1], acc1, mb, nb, lr, lk);
     store(buf ^ 1, (kt + 1) * KB);
     __syncthreads();
     buf ^= 1;
   }
-  mma_stage<BM, BN>(sm.A[buf][0], sm.B[buf][0], acc0, wm, wn, lr, lk);
-  mma_stage<BM, BN>(sm.A[buf][1], sm.B[buf][1], acc1, wm, wn, lr, lk);
+  mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][0], sm.B[buf][0], acc0, mb, nb, lr, lk);
+  mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][1], sm.B[buf][1], acc1, mb, nb, lr, lk);
 
   const int M = a.Kh;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
     for (int j = 0; j < C::TN; ++j) {
-      const int col = n0 + wn * (BN / 2) + j * 16 + lr;
+      const int col = n0 + nb + j * 16 + lr;
       if (col >= Q) continue;
       int pos2;
       bool diff;
@@ -681,7 +723,7 @@ __global__ __launch_bounds__(NT) void k_pass_last2(LastArgs a) {
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm * (BM / 2) + i * 16 + lk + 4 * r;
+        const int64_t row = m0 + mb + i * 16 + lk + 4 * r;
         if (row >= a.R) continue;
         const double A = acc0[i][j][r], B = acc1[i][j][r];
         __builtin_nontemporal_store(A + B, &a.Y[row * a.np + h * a.Kh + col]);
@@ -1012,7 +1054,7 @@ static pe_status launch_mid(MidArgs a, hipStream_t st) {
   return set_error(PE_E_ARG, "internal: no MID tile for %d x %d", bm, bn);
 }
 
-template <int BM, int BN, int GM>
+template <int BM, int BN, int GM, int NTH>
 static pe_status launch_last2_t(LastArgs a, size_t dyn, hipStream_t st) {
   constexpr bool GEN = GM > 0;
   const int64_t per_row_tile = int64_t(a.tiles_n) * 2;
@@ -1034,7 +1076,7 @@ static pe_status launch_last2_t(LastArgs a, size_t dyn, hipStream_t st) {
     if (!GEN) b.X = a.X + r0 * a.np;
     b.Y = a.Y + r0 * a.np;
     if (GEN) b.gen.coef = a.gen.coef + (r0 / a.rows_per_field) * a.gen.M;
-    k_pass_last2<BM, BN, GM><<<dim3(unsigned(ntm * per_row_tile)), NT, dyn, st>>>(b);
+    k_pass_last2<BM, BN, GM, NTH><<<dim3(unsigned(ntm * per_row_tile)), NTH, dyn, st>>>(b);
     PE_HIP(hipGetLastError());
   }
   return PE_OK;
@@ -1050,7 +1092,7 @@ static pe_status launch_last2(LastArgs a, hipStream_t st) {
   }
   a.tiles_m = int((a.R + BM - 1) / BM);
   a.tiles_n = (a.Kh / 2 + BN - 1) / BN;
-  return launch_last2_t<BM, BN, GM>(a, 0, st);
+  return launch_last2_t<BM, BN, GM, (GM > 0 ? 512 : NT)>(a, 0, st);
 }
 
 static pe_status launch_mid2(Mid2Args a, hipStream_t st) {
