@@ -331,13 +331,9 @@ __global__ void k_update_tables(FuArgs a, int RT, const double *__restrict__ sig
 // Waves: half h = wave / 4 and TM = Kh/64 mode tiles each; lane l holds
 // C[4 (l/16) + r][l%16], i.e. 4 TM modes of row l%16, whose states stay in
 // FP64 registers for the whole slice (as the separate update computes them).
-// AXIS0_OUTER: the input is X[f][p][r] instead (the fused generating and
-// middle-axis pass writes axis 0 outermost); a loader item then reads its
-// four p of one row r as single values, sixteen consecutive rows (64 bytes)
-// per p.  These loads go through the cache: the other half of each 128-byte
-// line belongs to the neighbouring strip, which a block on the same XCD
-// reads at about the same time (127x255x127: 6.6 -> 5.0 ms per launch
-// against streaming loads).
+// AXIS0_OUTER: the input is X[f][p][r] (the fused generating and
+// middle-axis pass writes axis 0 outermost); a block then owns 32 rows, two
+// row tiles, so that it reads whole 128-byte lines.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -346,19 +342,25 @@ typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4_t __attribute__((ext_vector_type(4)));
 
 template <int KH, int DEPTH, bool AXIS0_OUTER>
-__global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KH == 64 ? 4 : 1)))
+void k_split_final_update(FuArgs a) {
   constexpr int NTH = 512;
   constexpr int TM = KH / 64;     // mode tiles per wave
   constexpr int KT = KH / 32;     // k-steps
   constexpr int LDB = KH + 8;     // bf16 per LDS row (16-byte pad)
   constexpr int CPR = KH / 4;     // 4-wide p chunks per row
-  constexpr int ITEMS = 16 * CPR; // loader items (one per thread at most)
-  static_assert(TM >= 1 && ITEMS <= NTH, "Kh of 64 or 128");
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][2][2][16][LDB];   // [buf][h][hi/lo][row][p]
+  // AXIS0_OUTER: two adjacent 16-row tiles per block, so that every p of a
+  // field is read as whole 128-byte lines (32 rows)
+  constexpr int NR = AXIS0_OUTER ? 2 : 1;
+  constexpr int ROWS = 16 * NR;
+  constexpr int ITEMS = ROWS * CPR;                // loader items
+  constexpr int IPT = (ITEMS + NTH - 1) / NTH;     // ... per thread
+  static_assert(TM >= 1 && ITEMS <= IPT * NTH && (IPT == 1 || ITEMS % NTH == 0), "Kh of 64 or 128");
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][2][2][ROWS][LDB];   // [buf][h][hi/lo][row][p]
 
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nl = int(bid % a.nslices);
-  const int rt = int(bid / a.nslices);     // 16-row tile (strip-major: shared tables per XCD)
+  const int rt0 = int(bid / a.nslices) * NR;   // first 16-row tile (strip-major: shared tables per XCD)
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int h = wave >> 2, wt = wave & 3;
   const int lr = lane & 15, lk = lane >> 4;
@@ -374,126 +376,150 @@ __global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
       al[tm][kt] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t *>(a.Slo + o));
     }
 
-  // the lane's modes: m = 4 tm + q -> folded position (h Kh + i, row)
-  const int64_t row = int64_t(rt) * 16 + lr;
+  // the lane's modes in tile n: m = 4 tm + q -> folded position (h Kh + i, row)
   const int nf = a.jc * a.s;
   const float *Uin = a.Uins ? a.Uins + int64_t(nl) * a.dof : nullptr;
-  double W[4 * TM];
+  double W[NR][4 * TM];
 #pragma unroll
-  for (int m = 0; m < 4 * TM; ++m) {
-    const int i = 16 * (wt * TM + m / 4) + 4 * lk + (m % 4);
-    const int64_t k = mode_index(a, h * KH + i, row);
-    W[m] = (Uin && k >= 0) ? double(Uin[k]) : 0.0;
-  }
-  const double *Tl = a.Tp + (int64_t(rt) * 8 + wave) * (1 + a.s) * (2 * TM * 128) + 2 * lane;
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int m = 0; m < 4 * TM; ++m) {
+      const int i = 16 * (wt * TM + m / 4) + 4 * lk + (m % 4);
+      const int64_t k = mode_index(a, h * KH + i, int64_t(rt0 + n) * 16 + lr);
+      W[n][m] = (Uin && k >= 0) ? double(Uin[k]) : 0.0;
+    }
+  const double *Tl = a.Tp + (int64_t(rt0) * 8 + wave) * (1 + a.s) * (2 * TM * 128) + 2 * lane;
+  const int64_t tstride = int64_t(8) * (1 + a.s) * (2 * TM * 128);   // next tile's tables
 
-  // loader item (one per thread): row lrow of the tile, p = 4 c .. 4 c + 3.
+  // loader items: row lrow of the block's rows, p = 4 c .. 4 c + 3.
   // The kernel is bound by HBM: DEPTH register sets keep the strips of the
   // next DEPTH fields in flight (field e + 1 + DEPTH is loaded right after
   // field e + 1 is stashed), so each load has DEPTH fields of time to land.
   // The strips are read once: streaming (nontemporal) loads leave L2 to the
-  // update tables, which every step of the slice reads again.
-  const int lrow = AXIS0_OUTER ? t % 16 : t / CPR, lc = AXIS0_OUTER ? t / 16 : t % CPR;
-  const int p0 = 4 * lc;
-  const bool active = t < ITEMS;
+  // update tables, which every step of the slice reads again.  AXIS0_OUTER:
+  // the input is X[f][p][r] instead (the fused generating and middle-axis
+  // pass writes axis 0 outermost); an item then reads its four p of one row
+  // as single values, 32 consecutive rows (one 128-byte line) per p.
   const int64_t fstride = int64_t(a.I) * (2 * KH);
-  const float *Xr = a.Xs + int64_t(nl) * nf * fstride +
-                    (int64_t(rt) * 16 + (active ? lrow : 0)) * (AXIS0_OUTER ? 1 : 2 * KH);
+  int lrow[IPT], p0[IPT];
+  bool active[IPT];
+  const float *Xr[IPT];
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    const int it = t + q * NTH;
+    lrow[q] = AXIS0_OUTER ? it % ROWS : it / CPR;
+    p0[q] = 4 * (AXIS0_OUTER ? it / ROWS : it % CPR);
+    active[q] = it < ITEMS;
+    Xr[q] = a.Xs + int64_t(nl) * nf * fstride +
+            (int64_t(rt0) * 16 + (active[q] ? lrow[q] : 0)) * (AXIS0_OUTER ? 1 : 2 * KH);
+  }
   struct Raw {
-    f4_t xa, xb;
+    f4_t xa[IPT], xb[IPT];
   };
   Raw S[DEPTH];
   auto load = [&](Raw &R, int e) {
-    if (!active || e >= nf) return;
-    const float *x = Xr + e * fstride;
-    if constexpr (AXIS0_OUTER) {
+    if (e >= nf) return;
 #pragma unroll
-      for (int e2 = 0; e2 < 4; ++e2) {
-        const int i = a.n0 - 1 - p0 - e2;
-        R.xa[e2] = x[int64_t(p0 + e2) * a.I];
-        R.xb[e2] = x[int64_t(i > 0 ? i : 0) * a.I];
+    for (int q = 0; q < IPT; ++q) {
+      if (!active[q]) continue;
+      const float *x = Xr[q] + e * fstride;
+      if constexpr (AXIS0_OUTER) {
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const int i = a.n0 - 1 - p0[q] - e2;
+          R.xa[q][e2] = x[int64_t(p0[q] + e2) * a.I];
+          R.xb[q][e2] = x[int64_t(i > 0 ? i : 0) * a.I];
+        }
+        continue;
       }
-      return;
-    }
-    R.xa = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(x + p0));
-    const int mb = a.n0 - 4 - p0;   // x[n-1-p0-e], e = 0..3: one ascending run
-    if (mb >= 0) {
-      const f4u_t v = __builtin_nontemporal_load(reinterpret_cast<const f4u_t *>(x + mb));
-      R.xb = f4_t{v.w, v.z, v.y, v.x};
-    } else {
+      R.xa[q] = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(x + p0[q]));
+      const int mb = a.n0 - 4 - p0[q];   // x[n-1-p0-e], e = 0..3: one ascending run
+      if (mb >= 0) {
+        const f4u_t v = __builtin_nontemporal_load(reinterpret_cast<const f4u_t *>(x + mb));
+        R.xb[q] = f4_t{v.w, v.z, v.y, v.x};
+      } else {
 #pragma unroll
-      for (int e2 = 0; e2 < 4; ++e2) {
-        const int i = a.n0 - 1 - p0 - e2;
-        R.xb[e2] = x[i > 0 ? i : 0];
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const int i = a.n0 - 1 - p0[q] - e2;
+          R.xb[q][e2] = x[i > 0 ? i : 0];
+        }
       }
     }
   };
   auto stash = [&](const Raw &R, int buf) {
-    if (!active) return;
-    f4_t u, v;
 #pragma unroll
-    for (int e2 = 0; e2 < 4; ++e2) {
-      const int p = p0 + e2;
-      const bool has_b = p < a.H0;
-      const bool has_a0 = has_b || (p == a.H0 && (a.n0 & 1));
-      u[e2] = (has_a0 ? R.xa[e2] : 0.0f) + (has_b ? R.xb[e2] : 0.0f);
-      v[e2] = (has_b ? R.xa[e2] : 0.0f) + (has_b ? -R.xb[e2] : 0.0f);
+    for (int q = 0; q < IPT; ++q) {
+      if (!active[q]) continue;
+      f4_t u, v;
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        const int p = p0[q] + e2;
+        const bool has_b = p < a.H0;
+        const bool has_a0 = has_b || (p == a.H0 && (a.n0 & 1));
+        u[e2] = (has_a0 ? R.xa[q][e2] : 0.0f) + (has_b ? R.xb[q][e2] : 0.0f);
+        v[e2] = (has_b ? R.xa[q][e2] : 0.0f) + (has_b ? -R.xb[q][e2] : 0.0f);
+      }
+      const bf16x4_t uh = __builtin_convertvector(u, bf16x4_t);
+      const bf16x4_t ul = __builtin_convertvector(u - __builtin_convertvector(uh, f4_t), bf16x4_t);
+      const bf16x4_t vh = __builtin_convertvector(v, bf16x4_t);
+      const bf16x4_t vl = __builtin_convertvector(v - __builtin_convertvector(vh, f4_t), bf16x4_t);
+      *reinterpret_cast<u16x4_t *>(&Bs[buf][0][0][lrow[q]][p0[q]]) = __builtin_bit_cast(u16x4_t, uh);
+      *reinterpret_cast<u16x4_t *>(&Bs[buf][0][1][lrow[q]][p0[q]]) = __builtin_bit_cast(u16x4_t, ul);
+      *reinterpret_cast<u16x4_t *>(&Bs[buf][1][0][lrow[q]][p0[q]]) = __builtin_bit_cast(u16x4_t, vh);
+      *reinterpret_cast<u16x4_t *>(&Bs[buf][1][1][lrow[q]][p0[q]]) = __builtin_bit_cast(u16x4_t, vl);
     }
-    const bf16x4_t uh = __builtin_convertvector(u, bf16x4_t);
-    const bf16x4_t ul = __builtin_convertvector(u - __builtin_convertvector(uh, f4_t), bf16x4_t);
-    const bf16x4_t vh = __builtin_convertvector(v, bf16x4_t);
-    const bf16x4_t vl = __builtin_convertvector(v - __builtin_convertvector(vh, f4_t), bf16x4_t);
-    *reinterpret_cast<u16x4_t *>(&Bs[buf][0][0][lrow][p0]) = __builtin_bit_cast(u16x4_t, uh);
-    *reinterpret_cast<u16x4_t *>(&Bs[buf][0][1][lrow][p0]) = __builtin_bit_cast(u16x4_t, ul);
-    *reinterpret_cast<u16x4_t *>(&Bs[buf][1][0][lrow][p0]) = __builtin_bit_cast(u16x4_t, vh);
-    *reinterpret_cast<u16x4_t *>(&Bs[buf][1][1][lrow][p0]) = __builtin_bit_cast(u16x4_t, vl);
   };
 
-  // one field: products from LDS buffer e & 1, the next field stashed from
-  // its register set (then refilled DEPTH fields ahead), the update
+  // one field: per row tile the products from LDS buffer e & 1 and the
+  // update; after the last tile's products the next field is stashed from
+  // its register set (then refilled DEPTH fields ahead)
   auto field = [&](int e, Raw &nextset) {
     const int buf = e & 1;
     const int i_st = e % a.s;
-    double bw[4 * TM], ew[4 * TM];
 #pragma unroll
-    for (int pp = 0; pp < 2 * TM; ++pp) {
-      const double2 w2 = *reinterpret_cast<const double2 *>(Tl + ((1 + i_st) * 2 * TM + pp) * 128);
-      bw[2 * pp] = w2.x;
-      bw[2 * pp + 1] = w2.y;
-    }
-    if (i_st == 0) {
+    for (int n = 0; n < NR; ++n) {
+      const double *Tn = Tl + n * tstride;
+      double bw[4 * TM], ew[4 * TM];
 #pragma unroll
       for (int pp = 0; pp < 2 * TM; ++pp) {
-        const double2 w2 = *reinterpret_cast<const double2 *>(Tl + pp * 128);
-        ew[2 * pp] = w2.x;
-        ew[2 * pp + 1] = w2.y;
+        const double2 w2 = *reinterpret_cast<const double2 *>(Tn + ((1 + i_st) * 2 * TM + pp) * 128);
+        bw[2 * pp] = w2.x;
+        bw[2 * pp + 1] = w2.y;
       }
-    }
-    f4_t acc[TM];
+      if (i_st == 0) {
 #pragma unroll
-    for (int tm = 0; tm < TM; ++tm) acc[tm] = f4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kt = 0; kt < KT; ++kt) {
-      const bf16x8_t bh = __builtin_bit_cast(
-          bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][0][lr][32 * kt + 8 * lk]));
-      const bf16x8_t bl = __builtin_bit_cast(
-          bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][1][lr][32 * kt + 8 * lk]));
-#pragma unroll
-      for (int tm = 0; tm < TM; ++tm) {
-        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bh, acc[tm], 0, 0, 0);
-        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bl, acc[tm], 0, 0, 0);
-        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm][kt], bh, acc[tm], 0, 0, 0);
+        for (int pp = 0; pp < 2 * TM; ++pp) {
+          const double2 w2 = *reinterpret_cast<const double2 *>(Tn + pp * 128);
+          ew[2 * pp] = w2.x;
+          ew[2 * pp + 1] = w2.y;
+        }
       }
-    }
-    if (e + 1 < nf) {
-      stash(nextset, buf ^ 1);
-      load(nextset, e + 1 + DEPTH);
-    }
+      f4_t acc[TM];
 #pragma unroll
-    for (int m = 0; m < 4 * TM; ++m) {
-      double w = W[m];
-      if (i_st == 0) w = ew[m] * w;
-      W[m] = w + bw[m] * double(acc[m / 4][m % 4]);
+      for (int tm = 0; tm < TM; ++tm) acc[tm] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const bf16x8_t bh = __builtin_bit_cast(
+            bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][0][16 * n + lr][32 * kt + 8 * lk]));
+        const bf16x8_t bl = __builtin_bit_cast(
+            bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][1][16 * n + lr][32 * kt + 8 * lk]));
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+          acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bh, acc[tm], 0, 0, 0);
+          acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bl, acc[tm], 0, 0, 0);
+          acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm][kt], bh, acc[tm], 0, 0, 0);
+        }
+      }
+      if (n == NR - 1 && e + 1 < nf) {
+        stash(nextset, buf ^ 1);
+        load(nextset, e + 1 + DEPTH);
+      }
+#pragma unroll
+      for (int m = 0; m < 4 * TM; ++m) {
+        double w = W[n][m];
+        if (i_st == 0) w = ew[m] * w;
+        W[n][m] = w + bw[m] * double(acc[m / 4][m % 4]);
+      }
     }
     __syncthreads();
   };
@@ -515,11 +541,13 @@ __global__ __launch_bounds__(512) void k_split_final_update(FuArgs a) {
 
   float *Uout = a.Uouts + int64_t(nl) * a.dof;
 #pragma unroll
-  for (int m = 0; m < 4 * TM; ++m) {
-    const int i = 16 * (wt * TM + m / 4) + 4 * lk + (m % 4);
-    const int64_t k = mode_index(a, h * KH + i, row);
-    if (k >= 0) Uout[k] = float(W[m]);
-  }
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int m = 0; m < 4 * TM; ++m) {
+      const int i = 16 * (wt * TM + m / 4) + 4 * lk + (m % 4);
+      const int64_t k = mode_index(a, h * KH + i, int64_t(rt0 + n) * 16 + lr);
+      if (k >= 0) Uout[k] = float(W[n][m]);
+    }
 }
 
 // Update tables in the split kernel's lane order: entry (rt, wave, t, pair,
@@ -644,8 +672,9 @@ static void launch_q(const FuArgs &a, int64_t nslices, hipStream_t st) {
 
 template <int KH>
 static void launch_split_final(const FuArgs &a, int64_t blocks, bool axis0_outer, hipStream_t st) {
+  // (32 rows per block: one strip in flight holds as many bytes as two of 16)
   if (axis0_outer)
-    k_split_final_update<KH, SPLIT_DEPTH, true><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
+    k_split_final_update<KH, SPLIT_DEPTH / 2, true><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
   else
     k_split_final_update<KH, SPLIT_DEPTH, false><<<dim3(unsigned(blocks)), 512, 0, st>>>(a);
 }
@@ -656,7 +685,9 @@ static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, bo
   a.Shi = x0.d_Shi;
   a.Slo = x0.d_Slo;
   a.H0 = x0.H;
-  const int64_t blocks = int64_t(b.nslices) * (a.I / 16);
+  if (axis0_outer && (a.I / 16) % 2 != 0)
+    return set_error(PE_E_ARG, "internal: odd tile count for the axis-0-outer fused update");
+  const int64_t blocks = int64_t(b.nslices) * (a.I / 16) / (axis0_outer ? 2 : 1);
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: fused grid too large");
   // axis-0 products (three bf16 products of the folded pass) plus the update
   const double fields = double(b.count());
