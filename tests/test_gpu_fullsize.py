@@ -48,3 +48,28 @@ def test_fullsize_parareal_answer(cfg):
     outside = float(torch.linalg.vector_norm(rest.double()))
     print(f"  norm outside the forced modes / inside: {outside / inside:.3e}")
     assert outside <= TOL[cfg] * inside
+
+
+@pytest.mark.parametrize("cfg", [4, 5])
+def test_fullsize_learned_answer(cfg):
+    """The learned coarse correction at full size (workload 5 on the
+    split-bf16 path): a network trained with the library's kernels on 64
+    forcings of the workload's family on a 31^d grid, then the full-size
+    solve with it: converged, the network used (no fallback), and the answer
+    against the same oracle values as the plain solve."""
+    from paper_2412_01138_amd import learned_g as lg, peifem as pe
+    prob = wl.config(cfg)
+    X, T, S = lg.training_rows(prob, [10000 + i for i in range(64)], (31,) * prob.dim)
+    W = lg.row_weights(X, S, prob.N, 0.0)
+    m, _ = lg.train(X, T, 3000, batch=16384, lr=2e-3, weights=W)
+    modes = modal.sample_modes(prob, 32, seed=100 + cfg)
+    ref = modal.sequential_fine_modes(prob, modes)
+    g, U, rep = pe.solve_problem(prob, mlp=m)
+    print(f"workload {cfg} learned: iterations {rep.iterations}, jumps {list(rep.jumps[:rep.iterations])}, "
+          f"learned part {rep.ms_learned:.1f} ms", flush=True)
+    assert rep.converged and rep.fallback == 0 and rep.ms_learned > 0
+    flat = U.reshape(prob.N + 1, -1)
+    idx = torch.as_tensor(modal.flat_index(prob, modes), device=U.device)
+    err = rel(flat[:, idx].double().cpu().numpy(), ref)
+    print(f"  relative L2 error on {len(modes)} modes: {err:.3e}")
+    assert err <= TOL[cfg]
