@@ -178,7 +178,13 @@ __global__ __launch_bounds__(HB * Q * 4) void k_final_update(FuArgs a) {
         *reinterpret_cast<double2 *>(&F[stage][slot][0][g][jj][c]) = u;
         *reinterpret_cast<double2 *>(&F[stage][slot][HB - 1][g][jj][c]) = v;
       } else {
-        *reinterpret_cast<double2 *>(&F[stage][slot][0][g][jj][c]) = hb == 0 ? u : v;
+        // a select per component (as a select of the two structs the
+        // compiler went through scratch memory, whose reload then waited
+        // behind the strip prefetch)
+        double2 w;
+        w.x = hb == 0 ? u.x : v.x;
+        w.y = hb == 0 ? u.y : v.y;
+        *reinterpret_cast<double2 *>(&F[stage][slot][0][g][jj][c]) = w;
       }
     }
   };
