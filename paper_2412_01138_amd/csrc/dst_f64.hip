@@ -901,8 +901,11 @@ void k_last3_gen(LastArgs a, int64_t tiles, int64_t per_block) {
   int64_t tile = tile0 + wave;
   double rf[GK], rfn[GK];
   if (tile < tend) row_factors(tile, rf);
+  // the next tile's row factors are loaded after this tile's products:
+  // their use waits for every older memory operation, and by then the
+  // previous tile's output stores have drained (loaded before the products,
+  // each tile waited for the stores just issued)
   for (; tile < tend; tile += L3_NW) {
-    if (tile + L3_NW < tend) row_factors(tile + L3_NW, rfn);
     d4 acc[NACC];
 #pragma unroll
     for (int j = 0; j < NACC; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
@@ -911,6 +914,7 @@ void k_last3_gen(LastArgs a, int64_t tiles, int64_t per_block) {
       l3_product<Q, GK, Q / 16, Q / 32, Q2, Q / 16, NACC>(sb, Q * Q, cfl, rf, acc, lr, lk);
       l3_product<Q, GK, 3 * Q / 32, Q / 32, Q2, 3 * Q / 32, NACC>(sb, Q * Q + Q2 * Q2, cfl, rf,
                                                                    acc, lr, lk);
+      if (tile + L3_NW < tend) row_factors(tile + L3_NW, rfn);
       // outputs: A from P00 (upper slots reversed), B from E +- O
 #pragma unroll
       for (int tt = 0; tt < Q / 32; ++tt) {
@@ -934,6 +938,7 @@ void k_last3_gen(LastArgs a, int64_t tiles, int64_t per_block) {
       l3_product<Q, GK, Q / 16, Q / 32, Q2, Q / 16, NACC>(sb, 2 * Q2 * Q2, cfl, rf, acc, lr, lk);
       l3_product<Q, GK, 3 * Q / 32, Q / 32, Q2, 3 * Q / 32, NACC>(sb, 3 * Q2 * Q2, cfl, rf, acc,
                                                                    lr, lk);
+      if (tile + L3_NW < tend) row_factors(tile + L3_NW, rfn);
       // outputs: even rows from the sums, odd rows from the differences.
       // Lane k (= 16 tt + l%16) writes the pair (2k, 2k+1) and the partner
       // pair (M-2-2k, M-1-2k); the second partner is lane k-1's odd one
