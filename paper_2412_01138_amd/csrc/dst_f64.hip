@@ -539,12 +539,17 @@ __global__ __launch_bounds__(NT) void k_pass_mid2(Mid2Args a) {
 // blocks per CU (the LDS of two), so four waves share each SIMD; a wave
 // generates one 16-row tile of one parity.  NTH = 256: 4 waves of
 // (BM/2) x (BN/2), a wave generates one row tile of both parities.
-template <int BM, int BN, int GM, int NTH>
+// RTB > 1 (generating pass): a block walks RTB consecutive 64-row tiles,
+// loading the next tile's row factors while the current one finishes, so
+// the set-up latency of a short block (row factors, first k-tile) is paid
+// once per RTB tiles.
+template <int BM, int BN, int GM, int NTH, int RTB>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == 512 ? 4 : 1)))
 void k_pass_last2(LastArgs a) {
   constexpr bool GEN = GM > 0;
   using C = Cfg2<BM, BN, NTH>;
   static_assert(BM == 64 && (NTH == 256 || NTH == 512), "tile layout");
+  static_assert(RTB == 1 || GEN, "several row tiles per block only when generating");
   __shared__ Smem2<BM, BN> sm;
 
   const int Q = a.Kh / 2;
@@ -552,184 +557,193 @@ void k_pass_last2(LastArgs a) {
   const int tn = int(bid % a.tiles_n);
   bid /= a.tiles_n;
   const int h = int(bid % 2);
-  const int64_t tm = bid / 2;
-  const int64_t m0 = tm * BM;
+  const int64_t tmb = bid / 2;   // group of RTB row tiles
   const int n0 = tn * BN;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave / C::WN, wn = wave % C::WN, lr = lane & 15, lk = lane >> 4;
 
   const int ra = t / C::TPR;
   const int ca0 = (t % C::TPR) * C::CPT;
-  const int64_t grow = m0 + ra;
-  const bool row_ok = grow < a.R;
 
   // generation: the wave's 16-row tile and its parities [g0, g0 + GPW)
   constexpr int RTILES = BM / 16;
   constexpr int GPW = 2 * RTILES / C::NW;
   const int grt = wave % RTILES, g0 = GPW == 2 ? 0 : wave / RTILES;
-  constexpr int RT = 1;
   constexpr int GK = GM > 0 ? GM / 4 : 1;    // MFMA k-steps over the terms
-  double rfa[RT][GK];
-  if constexpr (GEN) {
+  // row factors of the wave's generated rows of the tile starting at row m0
+  auto row_factors = [&](int64_t m0, double (&rf)[GK]) {
     const int M = a.gen.M;
     const double *C0 = a.d >= 2 ? a.gen.C0 : nullptr;
     const double *C1 = a.d == 3 ? a.gen.C1 : nullptr;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int64_t gr0 = m0 + grt * 16 + lr;
-      const bool ok = gr0 < a.R;
-      const int64_t gr = ok ? gr0 : a.R - 1;
-      const int64_t f = gr / a.rows_per_field;
-      const int64_t rem = gr - f * a.rows_per_field;
-      int j0 = 0, j1 = 0;
-      if (a.d == 2) j0 = int(rem);
-      if (a.d == 3) {
-        j0 = int(rem / a.np1);
-        j1 = int(rem - int64_t(j0) * a.np1);
-      }
-#pragma unroll
-      for (int kk = 0; kk < GK; ++kk) {
-        const int m = lk + 4 * kk;
-        const int mm = m < M ? m : M - 1;
-        double v = a.gen.coef[f * M + mm];
-        if (C0) v *= C0[int64_t(mm) * a.np0 + j0];
-        if (C1) v *= C1[int64_t(mm) * a.np1 + j1];
-        rfa[rt][kk] = (m < M && ok) ? v : 0.0;
-      }
+    const int64_t gr0 = m0 + grt * 16 + lr;
+    const bool ok = gr0 < a.R;
+    const int64_t gr = ok ? gr0 : a.R - 1;
+    const int64_t f = gr / a.rows_per_field;
+    const int64_t rem = gr - f * a.rows_per_field;
+    int j0 = 0, j1 = 0;
+    if (a.d == 2) j0 = int(rem);
+    if (a.d == 3) {
+      j0 = int(rem / a.np1);
+      j1 = int(rem - int64_t(j0) * a.np1);
     }
-  }
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      const int m = lk + 4 * kk;
+      const int mm = m < M ? m : M - 1;
+      double v = a.gen.coef[f * M + mm];
+      if (C0) v *= C0[int64_t(mm) * a.np0 + j0];
+      if (C1) v *= C1[int64_t(mm) * a.np1 + j1];
+      rf[kk] = (m < M && ok) ? v : 0.0;
+    }
+  };
   // GEN: the folded last-axis table of this half, [M][Kh], read through the
   // cache (a copy in LDS would leave room for one block per CU only)
   const double *cf_half = GEN ? a.gen.Cf + int64_t(h) * a.gen.M * a.Kh : nullptr;
-
-  // raw prefetch: input rows at p = 2 jj + g and their mirrors (p <= H)
-  double ra_a[GEN ? 1 : 2][GEN ? 1 : C::CPT], ra_b[GEN ? 1 : 2][GEN ? 1 : C::CPT];
-  double rb[2][C::B_PER];
-  const double *xrow = GEN ? nullptr : a.X + (row_ok ? grow : a.R - 1) * a.np;
   const double *SqT = a.ShT;   // [2][2][Q][Q] when set up for this pass
-  auto load = [&](int k0) {
-    if constexpr (!GEN) {
+  const int nk = Q / KB;
+  const int mb = wm * (BM / 2), nb = wn * (BN / C::WN);
+  const int M = a.Kh;
+
+  double rfa[GK], rfn[GK];
+  if constexpr (GEN) row_factors(tmb * RTB * BM, rfa);
+  for (int rtb = 0; rtb < RTB; ++rtb) {
+    const int64_t tm = tmb * RTB + rtb;
+    if (tm >= a.tiles_m) break;
+    const int64_t m0 = tm * BM;
+    const int64_t grow = m0 + ra;
+    const bool row_ok = grow < a.R;
+    if (rtb > 0) {
+#pragma unroll
+      for (int kk = 0; kk < GK; ++kk) rfa[kk] = rfn[kk];
+      __syncthreads();   // the last products of the previous tile read the LDS tiles
+    }
+
+    // raw prefetch: input rows at p = 2 jj + g and their mirrors (p <= H)
+    double ra_a[GEN ? 1 : 2][GEN ? 1 : C::CPT], ra_b[GEN ? 1 : 2][GEN ? 1 : C::CPT];
+    double rb[2][C::B_PER];
+    const double *xrow = GEN ? nullptr : a.X + (row_ok ? grow : a.R - 1) * a.np;
+    auto load = [&](int k0) {
+      if constexpr (!GEN) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int c = 0; c < C::CPT; ++c) {
+            const int p = 2 * (k0 + ca0 + c) + g;
+            ra_a[g][c] = xrow[p];
+            ra_b[g][c] = xrow[a.n - 1 - p];
+          }
+      }
 #pragma unroll
       for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int c = 0; c < C::CPT; ++c) {
-          const int p = 2 * (k0 + ca0 + c) + g;
-          ra_a[g][c] = xrow[p];
-          ra_b[g][c] = xrow[a.n - 1 - p];
+        for (int q = 0; q < C::B_PER; ++q) {
+          const int e = t + q * NTH;
+          const int k = e / BN, nl = e % BN;
+          const int col = n0 + nl;
+          rb[g][q] = SqT[(int64_t(2 * h + g) * Q + k0 + k) * Q + (col < Q ? col : Q - 1)];
         }
-    }
+    };
+    auto store = [&](int buf, int k0) {
+      if constexpr (GEN) {
+        const int Mm1 = a.gen.M - 1;
 #pragma unroll
-    for (int g = 0; g < 2; ++g)
+        for (int gg = 0; gg < GPW; ++gg) {
+          const int g = g0 + gg;
+          double cfb[GK];
 #pragma unroll
-      for (int q = 0; q < C::B_PER; ++q) {
-        const int e = t + q * NTH;
-        const int k = e / BN, nl = e % BN;
-        const int col = n0 + nl;
-        rb[g][q] = SqT[(int64_t(2 * h + g) * Q + k0 + k) * Q + (col < Q ? col : Q - 1)];
-      }
-  };
-  auto store = [&](int buf, int k0) {
-    if constexpr (GEN) {
-      const int Mm1 = a.gen.M - 1;
-#pragma unroll
-      for (int gg = 0; gg < GPW; ++gg) {
-        const int g = g0 + gg;
-        double cfb[GK];
-#pragma unroll
-        for (int kk = 0; kk < GK; ++kk) {
-          const int term = lk + 4 * kk;
-          cfb[kk] = cf_half[(term < Mm1 ? term : Mm1) * a.Kh + 2 * (k0 + lr) + g];
-        }
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
+          for (int kk = 0; kk < GK; ++kk) {
+            const int term = lk + 4 * kk;
+            cfb[kk] = cf_half[(term < Mm1 ? term : Mm1) * a.Kh + 2 * (k0 + lr) + g];
+          }
           d4 gacc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int kk = 0; kk < GK; ++kk)
-            gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(rfa[rt][kk], cfb[kk], gacc, 0, 0, 0);
+            gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(rfa[kk], cfb[kk], gacc, 0, 0, 0);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sm.A[buf][g][lr][grt * 16 + rt * 16 + lk + 4 * r] = gacc[r];
+          for (int r = 0; r < 4; ++r) sm.A[buf][g][lr][grt * 16 + lk + 4 * r] = gacc[r];
         }
+      } else {
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int c = 0; c < C::CPT; ++c) {
+            const int p = 2 * (k0 + ca0 + c) + g;
+            double v;
+            if (p < a.H)
+              v = h == 0 ? ra_a[g][c] + ra_b[g][c] : ra_a[g][c] - ra_b[g][c];
+            else
+              v = h == 0 ? ra_a[g][c] : 0.0;
+            sm.A[buf][g][ca0 + c][ra] = row_ok ? v : 0.0;
+          }
       }
-    } else {
 #pragma unroll
       for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int c = 0; c < C::CPT; ++c) {
-          const int p = 2 * (k0 + ca0 + c) + g;
-          double v;
-          if (p < a.H)
-            v = h == 0 ? ra_a[g][c] + ra_b[g][c] : ra_a[g][c] - ra_b[g][c];
-          else
-            v = h == 0 ? ra_a[g][c] : 0.0;
-          sm.A[buf][g][ca0 + c][ra] = row_ok ? v : 0.0;
+        for (int q = 0; q < C::B_PER; ++q) {
+          const int e = t + q * NTH;
+          const int col = n0 + e % BN;
+          sm.B[buf][g][e / BN][e % BN] = col < Q ? rb[g][q] : 0.0;
         }
+    };
+
+    d4 acc0[C::TM][C::TN], acc1[C::TM][C::TN];
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) acc0[i][j] = acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    // the last k-tile is peeled off the loop: a loop body without branches
+    // keeps the accumulators in the matrix-core registers across iterations
+    // (with the prefetch made conditional the compiler copied them out to
+    // plain registers and back around every k-tile, which also made each
+    // k-tile wait for all of its products)
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int kt = 0; kt + 1 < nk; ++kt) {
+      load((kt + 1) * KB);
+      mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][0], sm.B[buf][0], acc0, mb, nb, lr, lk);
+      mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][1], sm.B[buf][1], acc1, mb, nb, lr, lk);
+      store(buf ^ 1, (kt + 1) * KB);
+      __syncthreads();
+      buf ^= 1;
     }
-#pragma unroll
-    for (int g = 0; g < 2; ++g)
-#pragma unroll
-      for (int q = 0; q < C::B_PER; ++q) {
-        const int e = t + q * NTH;
-        const int col = n0 + e % BN;
-        sm.B[buf][g][e / BN][e % BN] = col < Q ? rb[g][q] : 0.0;
-      }
-  };
-
-  d4 acc0[C::TM][C::TN], acc1[C::TM][C::TN];
-#pragma unroll
-  for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-    for (int j = 0; j < C::TN; ++j) acc0[i][j] = acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-  // the last k-tile is peeled off the loop: a loop body without branches
-  // keeps the accumulators in the matrix-core registers across iterations
-  // (with the prefetch made conditional the compiler copied them out to
-  // plain registers and back around every k-tile, which also made each
-  // k-tile wait for all of its products)
-  const int nk = Q / KB;
-  const int mb = wm * (BM / 2), nb = wn * (BN / C::WN);
-  load(0);
-  store(0, 0);
-  __syncthreads();
-  int buf = 0;
-  for (int kt = 0; kt + 1 < nk; ++kt) {
-    load((kt + 1) * KB);
+    // the next tile's row factors (their loads land during the last
+    // products and the stores)
+    if constexpr (GEN)
+      if (rtb + 1 < RTB && tm + 1 < a.tiles_m) row_factors(m0 + BM, rfn);
     mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][0], sm.B[buf][0], acc0, mb, nb, lr, lk);
     mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][1], sm.B[buf][1], acc1, mb, nb, lr, lk);
-    store(buf ^ 1, (kt + 1) * KB);
-    __syncthreads();
-    buf ^= 1;
-  }
-  mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][0], sm.B[buf][0], acc0, mb, nb, lr, lk);
-  mma_tile<C::TM, C::TN, BM + 1, BN + 1>(sm.A[buf][1], sm.B[buf][1], acc1, mb, nb, lr, lk);
 
-  const int M = a.Kh;
 #pragma unroll
-  for (int i = 0; i < C::TM; ++i)
+    for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-    for (int j = 0; j < C::TN; ++j) {
-      const int col = n0 + nb + j * 16 + lr;
-      if (col >= Q) continue;
-      int pos2;
-      bool diff;
-      if (h == 0) {
-        pos2 = M - 1 - col;
-        diff = true;
-      } else if (col < Q - 1) {
-        pos2 = M - 2 - col;
-        diff = true;
-      } else {
-        pos2 = M - 1;   // pad position of half 1
-        diff = false;
+      for (int j = 0; j < C::TN; ++j) {
+        const int col = n0 + nb + j * 16 + lr;
+        if (col >= Q) continue;
+        int pos2;
+        bool diff;
+        if (h == 0) {
+          pos2 = M - 1 - col;
+          diff = true;
+        } else if (col < Q - 1) {
+          pos2 = M - 2 - col;
+          diff = true;
+        } else {
+          pos2 = M - 1;   // pad position of half 1
+          diff = false;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + mb + i * 16 + lk + 4 * r;
+          if (row >= a.R) continue;
+          const double A = acc0[i][j][r], B = acc1[i][j][r];
+          __builtin_nontemporal_store(A + B, &a.Y[row * a.np + h * a.Kh + col]);
+          __builtin_nontemporal_store(diff ? A - B : 0.0, &a.Y[row * a.np + h * a.Kh + pos2]);
+        }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + mb + i * 16 + lk + 4 * r;
-        if (row >= a.R) continue;
-        const double A = acc0[i][j][r], B = acc1[i][j][r];
-        __builtin_nontemporal_store(A + B, &a.Y[row * a.np + h * a.Kh + col]);
-        __builtin_nontemporal_store(diff ? A - B : 0.0, &a.Y[row * a.np + h * a.Kh + pos2]);
-      }
-    }
+  }
 }
 
 // ------------------------------ generating LAST pass, three fold levels
@@ -1059,7 +1073,7 @@ static pe_status launch_mid(MidArgs a, hipStream_t st) {
   return set_error(PE_E_ARG, "internal: no MID tile for %d x %d", bm, bn);
 }
 
-template <int BM, int BN, int GM, int NTH>
+template <int BM, int BN, int GM, int NTH, int RTB>
 static pe_status launch_last2_t(LastArgs a, size_t dyn, hipStream_t st) {
   constexpr bool GEN = GM > 0;
   const int64_t per_row_tile = int64_t(a.tiles_n) * 2;
@@ -1081,11 +1095,15 @@ static pe_status launch_last2_t(LastArgs a, size_t dyn, hipStream_t st) {
     if (!GEN) b.X = a.X + r0 * a.np;
     b.Y = a.Y + r0 * a.np;
     if (GEN) b.gen.coef = a.gen.coef + (r0 / a.rows_per_field) * a.gen.M;
-    k_pass_last2<BM, BN, GM, NTH><<<dim3(unsigned(ntm * per_row_tile)), NTH, dyn, st>>>(b);
+    const int64_t groups = (ntm + RTB - 1) / RTB;
+    k_pass_last2<BM, BN, GM, NTH, RTB><<<dim3(unsigned(groups * per_row_tile)), NTH, dyn, st>>>(b);
     PE_HIP(hipGetLastError());
   }
   return PE_OK;
 }
+
+// row tiles per block of the generating two-level pass
+constexpr int LAST2_RTB = 4;
 
 // a.ShT must point at the axis' SqT blocks
 template <int GM>
@@ -1097,7 +1115,10 @@ static pe_status launch_last2(LastArgs a, hipStream_t st) {
   }
   a.tiles_m = int((a.R + BM - 1) / BM);
   a.tiles_n = (a.Kh / 2 + BN - 1) / BN;
-  return launch_last2_t<BM, BN, GM, (GM > 0 ? 512 : NT)>(a, 0, st);
+  if constexpr (GM > 0)
+    return launch_last2_t<BM, BN, GM, 512, LAST2_RTB>(a, 0, st);
+  else
+    return launch_last2_t<BM, BN, GM, NT, 1>(a, 0, st);
 }
 
 static pe_status launch_mid2(Mid2Args a, hipStream_t st) {
