@@ -529,7 +529,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FFT, Dirichlet, periodic and Example 5.4 solves")
     ap.add_argument("--learned-forcings", type=int, default=4096)
-    ap.add_argument("--learned-steps", type=int, default=60000)
+    ap.add_argument("--learned-steps", type=int, default=300000)
     ap.add_argument("--learned3d-forcings", type=int, default=1024)
     ap.add_argument("--learned3d-steps", type=int, default=40000)
     ap.add_argument("--copy-calibration", action="store_true",
