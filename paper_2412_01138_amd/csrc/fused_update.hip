@@ -346,6 +346,9 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4_t __attribute__((ext_vector_type(4)));
+// the fourth word of a raw (unswizzled, stride 0) buffer resource on gfx950:
+// 32-bit data format, no index swizzle; loads past num_records return zero
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
 
 template <int KH, int DEPTH, bool AXIS0_OUTER>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KH == 64 ? 4 : 1)))
@@ -362,24 +365,36 @@ void k_split_final_update(FuArgs a) {
   constexpr int ITEMS = ROWS * CPR;                // loader items
   constexpr int IPT = (ITEMS + NTH - 1) / NTH;     // ... per thread
   static_assert(TM >= 1 && ITEMS <= IPT * NTH && (IPT == 1 || ITEMS % NTH == 0), "Kh of 64 or 128");
+  constexpr bool ALL_ACTIVE = ITEMS == IPT * NTH;  // every thread loads every item
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][2][2][ROWS][LDB];   // [buf][h][hi/lo][row][p]
+  // Kh = 128 with two row tiles: the lo halves of the Sh fragments live in
+  // LDS (each wave its own, lane-contiguous 16-byte entries), which leaves
+  // the registers to the prefetched tables of both tiles
+  constexpr bool AL_LDS = KH == 128 && AXIS0_OUTER;
+  __shared__ __attribute__((aligned(16))) u16x8_t AlS[AL_LDS ? 8 * TM * KT * 64 : 1];
 
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nl = int(bid % a.nslices);
   const int rt0 = int(bid / a.nslices) * NR;   // first 16-row tile (strip-major: shared tables per XCD)
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int h = wave >> 2, wt = wave & 3;
   const int lr = lane & 15, lk = lane >> 4;
 
   // bf16 hi / lo of the wave's rows of Sh[h] as MFMA A fragments
-  bf16x8_t ah[TM][KT], al[TM][KT];
+  bf16x8_t ah[TM][KT], al[AL_LDS ? 1 : TM][AL_LDS ? 1 : KT];
+  auto al_slot = [&](int tm, int kt) -> u16x8_t & { return AlS[((wave * TM + tm) * KT + kt) * 64 + lane]; };
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
       const int64_t o = (int64_t(h) * KH + 16 * (wt * TM + tm) + lr) * KH + 32 * kt + 8 * lk;
       ah[tm][kt] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t *>(a.Shi + o));
-      al[tm][kt] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t *>(a.Slo + o));
+      const u16x8_t lo = *reinterpret_cast<const u16x8_t *>(a.Slo + o);
+      if constexpr (AL_LDS)
+        al_slot(tm, kt) = lo;   // read back by this lane only
+      else
+        al[tm][kt] = __builtin_bit_cast(bf16x8_t, lo);
     }
 
   // the lane's modes in tile n: m = 4 tm + q -> folded position (h Kh + i, row)
@@ -394,8 +409,17 @@ void k_split_final_update(FuArgs a) {
       const int64_t k = mode_index(a, h * KH + i, int64_t(rt0 + n) * 16 + lr);
       W[n][m] = (Uin && k >= 0) ? double(Uin[k]) : 0.0;
     }
-  const double *Tl = a.Tp + (int64_t(rt0) * 8 + wave) * (1 + a.s) * (2 * TM * 128) + 2 * lane;
+  // the wave's tables of tile n as a buffer (base and size uniform); the lane
+  // reads its 16 bytes of each 1 KiB row
+  const double *Tw = a.Tp + (int64_t(rt0) * 8 + wave) * (1 + a.s) * (2 * TM * 128);
   const int64_t tstride = int64_t(8) * (1 + a.s) * (2 * TM * 128);   // next tile's tables
+  const int trows = (1 + a.s) * 2 * TM;
+  __amdgpu_buffer_rsrc_t Tr[NR];
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+    Tr[n] = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(Tw + n * tstride), 0, trows * 1024,
+                                              BUFFER_RSRC_WORD3);
+  const int tlane = lane * 16;
 
   // loader items: row lrow of the block's rows, p = 4 c .. 4 c + 3.
   // The kernel is bound by HBM: DEPTH register sets keep the strips of the
@@ -410,34 +434,55 @@ void k_split_final_update(FuArgs a) {
   int lrow[IPT], p0[IPT];
   bool active[IPT];
   const float *Xr[IPT];
+  // AXIS0_OUTER: each field is read as a buffer from (p = 0, first row of
+  // the block): byte offsets of (p0, row) and of the mirror (n0-4-p0, row)
+  // per lane, and the e2-th value of an item 4 e2 I bytes further (the
+  // mirror: 4 (3 - e2) I), a uniform offset.  No 64-bit address stays live.
+  int oa[IPT], ob[IPT];
+  const float *Xb = a.Xs + int64_t(nl) * nf * fstride + int64_t(rt0) * 16;
+  const int xbytes = int((fstride - int64_t(rt0) * 16) * 4);   // to the field's end
 #pragma unroll
   for (int q = 0; q < IPT; ++q) {
     const int it = t + q * NTH;
     lrow[q] = AXIS0_OUTER ? it % ROWS : it / CPR;
     p0[q] = 4 * (AXIS0_OUTER ? it / ROWS : it % CPR);
-    active[q] = it < ITEMS;
+    active[q] = ALL_ACTIVE || it < ITEMS;
     Xr[q] = a.Xs + int64_t(nl) * nf * fstride +
             (int64_t(rt0) * 16 + (active[q] ? lrow[q] : 0)) * (AXIS0_OUTER ? 1 : 2 * KH);
+    oa[q] = int((int64_t(p0[q]) * a.I + lrow[q]) * 4);
+    ob[q] = int((int64_t(a.n0 - 4 - p0[q]) * a.I + lrow[q]) * 4);
   }
   struct Raw {
     f4_t xa[IPT], xb[IPT];
   };
   Raw S[DEPTH];
+  // (past the last field the last one is loaded again, unused: no branch
+  // around the loads, whose waits would otherwise be merged conservatively
+  // with the path that skips them)
   auto load = [&](Raw &R, int e) {
-    if (e >= nf) return;
+    e = e < nf ? e : nf - 1;
+    if constexpr (AXIS0_OUTER) {
+      // (the mirror index n0-1-p0-e2 >= n0-Kh >= 0 for axes with Kh = 64 or
+      // 128: the host checks it)
+      const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(Xb + int64_t(e) * fstride), 0, xbytes, BUFFER_RSRC_WORD3);
 #pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-      if (!active[q]) continue;
-      const float *x = Xr[q] + e * fstride;
-      if constexpr (AXIS0_OUTER) {
+      for (int q = 0; q < IPT; ++q) {
+        if (!ALL_ACTIVE && !active[q]) continue;
 #pragma unroll
         for (int e2 = 0; e2 < 4; ++e2) {
-          const int i = a.n0 - 1 - p0[q] - e2;
-          R.xa[q][e2] = x[int64_t(p0[q] + e2) * a.I];
-          R.xb[q][e2] = x[int64_t(i > 0 ? i : 0) * a.I];
+          R.xa[q][e2] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(xr, oa[q], int(e2 * a.I * 4), 0));
+          R.xb[q][e2] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(xr, ob[q], int((3 - e2) * a.I * 4), 0));
         }
-        continue;
       }
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      if (!ALL_ACTIVE && !active[q]) continue;
+      const float *x = Xr[q] + e * fstride;
       R.xa[q] = __builtin_nontemporal_load(reinterpret_cast<const f4_t *>(x + p0[q]));
       const int mb = a.n0 - 4 - p0[q];   // x[n-1-p0-e], e = 0..3: one ascending run
       if (mb >= 0) {
@@ -455,15 +500,23 @@ void k_split_final_update(FuArgs a) {
   auto stash = [&](const Raw &R, int buf) {
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      if (!active[q]) continue;
+      if (!ALL_ACTIVE && !active[q]) continue;
       f4_t u, v;
+      // AXIS0_OUTER: a wave's items cover two p0 (known from the wave index);
+      // below the middle node both fold terms exist for every lane
+      const bool interior = AXIS0_OUTER && 4 * ((wave * 64 + q * NTH + 63) / ROWS) + 3 < a.H0;
+      if (interior) {
+        u = R.xa[q] + R.xb[q];
+        v = R.xa[q] - R.xb[q];
+      } else {
 #pragma unroll
-      for (int e2 = 0; e2 < 4; ++e2) {
-        const int p = p0[q] + e2;
-        const bool has_b = p < a.H0;
-        const bool has_a0 = has_b || (p == a.H0 && (a.n0 & 1));
-        u[e2] = (has_a0 ? R.xa[q][e2] : 0.0f) + (has_b ? R.xb[q][e2] : 0.0f);
-        v[e2] = (has_b ? R.xa[q][e2] : 0.0f) + (has_b ? -R.xb[q][e2] : 0.0f);
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const int p = p0[q] + e2;
+          const bool has_b = p < a.H0;
+          const bool has_a0 = has_b || (p == a.H0 && (a.n0 & 1));
+          u[e2] = (has_a0 ? R.xa[q][e2] : 0.0f) + (has_b ? R.xb[q][e2] : 0.0f);
+          v[e2] = (has_b ? R.xa[q][e2] : 0.0f) + (has_b ? -R.xb[q][e2] : 0.0f);
+        }
       }
       const bf16x4_t uh = __builtin_convertvector(u, bf16x4_t);
       const bf16x4_t ul = __builtin_convertvector(u - __builtin_convertvector(uh, f4_t), bf16x4_t);
@@ -476,66 +529,100 @@ void k_split_final_update(FuArgs a) {
     }
   };
 
-  // one field: per row tile the products from LDS buffer e & 1 and the
-  // update; after the last tile's products the next field is stashed from
-  // its register set (then refilled DEPTH fields ahead)
+  // the update tables of tile n: the decay (the same every step, loaded
+  // once) and the weights of field e's stage e % s, loaded one field ahead,
+  // right after the previous field's update of the tile, so that the loads
+  // have a whole field's products to land in instead of stalling the update
+  double bw[NR][4 * TM], ew[NR][4 * TM];
+  auto row = [&](int n, int r) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(Tr[n], tlane, r * 1024, 0));
+  };
+  auto load_tables = [&](int n, int e) {
+    e = e < nf ? e : nf - 1;   // (unconditional, as the field loads)
+    const int i_st = e % a.s;
+#pragma unroll
+    for (int pp = 0; pp < 2 * TM; ++pp) {
+      const double2 w2 = row(n, (1 + i_st) * 2 * TM + pp);
+      bw[n][2 * pp] = w2.x;
+      bw[n][2 * pp + 1] = w2.y;
+    }
+  };
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int pp = 0; pp < 2 * TM; ++pp) {
+      const double2 w2 = row(n, pp);
+      ew[n][2 * pp] = w2.x;
+      ew[n][2 * pp + 1] = w2.y;
+    }
+
+  // one field: the products of both row tiles from LDS buffer e & 1, the
+  // next field stashed from its register set (then refilled DEPTH fields
+  // ahead), the update of each tile and its next tables
   auto field = [&](int e, Raw &nextset) {
     const int buf = e & 1;
     const int i_st = e % a.s;
+    // the products of both row tiles in one k-loop (the A fragments serve both)
+    f4_t acc[NR][TM];
+#pragma unroll
+    for (int n = 0; n < NR; ++n)
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) acc[n][tm] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      bf16x8_t bh[NR], bl[NR];
+#pragma unroll
+      for (int n = 0; n < NR; ++n) {
+        bh[n] = __builtin_bit_cast(
+            bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][0][16 * n + lr][32 * kt + 8 * lk]));
+        bl[n] = __builtin_bit_cast(
+            bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][1][16 * n + lr][32 * kt + 8 * lk]));
+      }
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        bf16x8_t alo;
+        if constexpr (AL_LDS)
+          alo = __builtin_bit_cast(bf16x8_t, al_slot(tm, kt));
+        else
+          alo = al[tm][kt];
+#pragma unroll
+        for (int n = 0; n < NR; ++n) {
+          acc[n][tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bh[n], acc[n][tm], 0, 0, 0);
+          acc[n][tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bl[n], acc[n][tm], 0, 0, 0);
+          acc[n][tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bh[n], acc[n][tm], 0, 0, 0);
+        }
+      }
+    }
+    // (after the last field the stash writes a buffer nobody reads)
+    stash(nextset, buf ^ 1);
+    load(nextset, e + 1 + DEPTH);
+    // the decay once per step (a uniform branch, not a select per mode)
+    if (i_st == 0) {
+#pragma unroll
+      for (int n = 0; n < NR; ++n)
+#pragma unroll
+        for (int m = 0; m < 4 * TM; ++m) W[n][m] = ew[n][m] * W[n][m];
+    }
 #pragma unroll
     for (int n = 0; n < NR; ++n) {
-      const double *Tn = Tl + n * tstride;
-      double bw[4 * TM], ew[4 * TM];
 #pragma unroll
-      for (int pp = 0; pp < 2 * TM; ++pp) {
-        const double2 w2 = *reinterpret_cast<const double2 *>(Tn + ((1 + i_st) * 2 * TM + pp) * 128);
-        bw[2 * pp] = w2.x;
-        bw[2 * pp + 1] = w2.y;
-      }
-      if (i_st == 0) {
-#pragma unroll
-        for (int pp = 0; pp < 2 * TM; ++pp) {
-          const double2 w2 = *reinterpret_cast<const double2 *>(Tn + pp * 128);
-          ew[2 * pp] = w2.x;
-          ew[2 * pp + 1] = w2.y;
-        }
-      }
-      f4_t acc[TM];
-#pragma unroll
-      for (int tm = 0; tm < TM; ++tm) acc[tm] = f4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt) {
-        const bf16x8_t bh = __builtin_bit_cast(
-            bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][0][16 * n + lr][32 * kt + 8 * lk]));
-        const bf16x8_t bl = __builtin_bit_cast(
-            bf16x8_t, *reinterpret_cast<const u16x8_t *>(&Bs[buf][h][1][16 * n + lr][32 * kt + 8 * lk]));
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm) {
-          acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bh, acc[tm], 0, 0, 0);
-          acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm][kt], bl, acc[tm], 0, 0, 0);
-          acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm][kt], bh, acc[tm], 0, 0, 0);
-        }
-      }
-      if (n == NR - 1 && e + 1 < nf) {
-        stash(nextset, buf ^ 1);
-        load(nextset, e + 1 + DEPTH);
-      }
-#pragma unroll
-      for (int m = 0; m < 4 * TM; ++m) {
-        double w = W[n][m];
-        if (i_st == 0) w = ew[m] * w;
-        W[n][m] = w + bw[m] * double(acc[m / 4][m % 4]);
-      }
+      for (int m = 0; m < 4 * TM; ++m) W[n][m] = W[n][m] + bw[n][m] * double(acc[n][m / 4][m % 4]);
+      load_tables(n, e + 1);
     }
     __syncthreads();
   };
 
   // set d holds field d (d < DEPTH); field 0 goes to LDS and its set is
-  // refilled with field DEPTH
+  // refilled with field DEPTH; then field 0's tables.  (The loads leave in
+  // the order of every field's: field loads, then tables, so that the waits
+  // the compiler counts at the loop head hold for the first pass too and
+  // do not fall back to waiting for everything.)
 #pragma unroll
   for (int d = 0; d < DEPTH; ++d) load(S[d], d);
   stash(S[0], 0);
   load(S[0], DEPTH);
+#pragma unroll
+  for (int n = 0; n < NR; ++n) load_tables(n, 0);
   __syncthreads();
   for (int e0 = 0; e0 < nf; e0 += DEPTH) {
 #pragma unroll
@@ -693,6 +780,10 @@ static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, bo
   a.H0 = x0.H;
   if (axis0_outer && (a.I / 16) % 2 != 0)
     return set_error(PE_E_ARG, "internal: odd tile count for the axis-0-outer fused update");
+  // (the axis-0-outer loader reads the mirror node n0-1-p for p < Kh without
+  // a clamp)
+  if (axis0_outer && x0.n < x0.Kh)
+    return set_error(PE_E_ARG, "internal: axis 0 shorter than its half width");
   const int64_t blocks = int64_t(b.nslices) * (a.I / 16) / (axis0_outer ? 2 : 1);
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: fused grid too large");
   // axis-0 products (three bf16 products of the folded pass) plus the update
