@@ -568,7 +568,10 @@ bool split_gen_mid_supported(pe_grid g, int n_terms) {
   if (g->dim != 3 || g->precision != PE_SPLIT_BF16 || !g->fuse_gen_mid) return false;
   if (!gen_supported_split(g, n_terms) || !fused_update_supported(g)) return false;
   const int k1 = g->ax[1].Kh, k2 = g->ax[2].Kh;
-  return (k1 == 64 || k1 == 128) && (k2 == 64 || k2 == 128);
+  // (the fused axis-0 pass addresses a field of this layout with 32-bit
+  // byte offsets)
+  return (k1 == 64 || k1 == 128) && (k2 == 64 || k2 == 128) &&
+         g->dofp * int64_t(sizeof(float)) < (int64_t(1) << 31);
 }
 
 template <int KH1, int KH2>

@@ -781,9 +781,11 @@ static pe_status split_final_update(pe_grid g, const FieldBatch &b, FuArgs a, bo
   if (axis0_outer && (a.I / 16) % 2 != 0)
     return set_error(PE_E_ARG, "internal: odd tile count for the axis-0-outer fused update");
   // (the axis-0-outer loader reads the mirror node n0-1-p for p < Kh without
-  // a clamp)
+  // a clamp, and addresses a field with 32-bit byte offsets)
   if (axis0_outer && x0.n < x0.Kh)
     return set_error(PE_E_ARG, "internal: axis 0 shorter than its half width");
+  if (axis0_outer && g->dofp * int64_t(sizeof(float)) >= (int64_t(1) << 31))
+    return set_error(PE_E_ARG, "internal: field too large for the axis-0-outer fused update");
   const int64_t blocks = int64_t(b.nslices) * (a.I / 16) / (axis0_outer ? 2 : 1);
   if (blocks >= (int64_t(1) << 31)) return set_error(PE_E_ARG, "internal: fused grid too large");
   // axis-0 products (three bf16 products of the folded pass) plus the update
