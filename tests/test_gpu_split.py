@@ -60,6 +60,9 @@ def test_split_project(dim, n):
     (3, (255, 9, 12), 1, 2, 3, 4),
     # a last axis with Kh = 320 (the generating pass at any length)
     (2, (20, 600), 2, 2, 3, 5),
+    # one stage and one step: a single field per slice (the decay and the
+    # weights of every field at once; the prefetch past the last field)
+    (2, (127, 40), 2, 1, 1, 4),
 ])
 def test_split_fine_propagate(dim, n, N, J, s, modes):
     pe = _peifem()
@@ -116,7 +119,7 @@ def _every_chunk_sines(prob, seed):
 
 
 @pytest.mark.parametrize("n,s", [((65, 67, 69), 3), ((100, 200, 90), 4), ((66, 100, 255), 3),
-                                 ((70, 193, 200), 3), ((128, 256, 193), 2)])
+                                 ((70, 193, 200), 3), ((128, 256, 193), 2), ((230, 70, 255), 1)])
 def test_split_gen_mid_sampled(n, s):
     """3D split grids whose axes 1 and 2 have Kh = 64 / 128 (odd and even n):
     the generating and middle-axis passes run as one kernel.  From a zero
@@ -159,7 +162,9 @@ def test_split_gen_mid_sampled(n, s):
 
 
 @pytest.mark.parametrize("n,N,J,s,modes", [((65, 67, 69), 2, 3, 3, 4), ((100, 200, 90), 2, 2, 4, 9),
-                                           ((66, 100, 255), 1, 2, 3, 32), ((128, 256, 193), 1, 1, 3, 5)])
+                                           ((66, 100, 255), 1, 2, 3, 32), ((128, 256, 193), 1, 1, 3, 5),
+                                           # one field per slice (one step, one stage)
+                                           ((100, 200, 90), 2, 1, 1, 4)])
 def test_split_gen_mid_fused_matches_two_passes(n, N, J, s, modes):
     """3D split grids: the generating and middle-axis passes as one kernel
     (axis-2 results kept on chip, output with axis 0 outermost, read so by the
