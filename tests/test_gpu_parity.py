@@ -143,6 +143,9 @@ def _fine_case(dim, n, N, J, s, seed=0, n_modes=4):
     (3, (9, 20, 127), 2, 2, 3),
     # 511-node last axis: the generating pass with Kh = 256 (two fold levels)
     (2, (31, 511), 1, 2, 4),
+    # one stage (every field takes the decay), and one field per slice
+    (2, (127, 40), 2, 3, 1),
+    (2, (63, 255), 2, 1, 1),
 ])
 def test_fine_propagate(dim, n, N, J, s):
     pe = _peifem()
