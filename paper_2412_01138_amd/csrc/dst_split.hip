@@ -375,6 +375,8 @@ struct alignas(16) GmSmem {
   uint16_t S2[2][64][KH2 + 8];         // [hi/lo][P2 of the chunk][p, permuted]
   uint16_t Cg[2][KH2][SGEN_MAX_TERMS + 8];   // [hi/lo][p][m] of this half's table
   uint16_t U[2][2][64][KH1 + 8];       // [h1][hi/lo][P2 of the chunk][p]
+  float C1[SGEN_MAX_TERMS][2 * KH1];   // axis-1 factors of the terms, [m][i1] (fp32)
+  double Pf[8][2][SGEN_MAX_TERMS];     // [wave][plane parity][m]: coef x axis-0 factor
 };
 
 struct GmArgs {
@@ -441,7 +443,32 @@ __global__ __launch_bounds__(GM_NT) void k_split_gen_mid(GmArgs a) {
   const int rt = wave / WPP;               // row tile of the axis-2 step
   const int ja0 = (wave % WPP) * JA;       // its first P2 tile
   const double *C0 = a.gen.C0, *C1 = a.gen.C1;
-  for (int64_t pl = blockIdx.x / NCH; pl < a.planes; pl += pstride) {
+  // Row factors of a plane's rows: coef_f[m] C0[m][i0] C1[m][i1].  The axis-1
+  // factors (the same for every plane) sit in LDS in fp32 (the products are
+  // rounded to fp32 anyway, and split into bf16 hi / lo); each wave keeps the
+  // plane's coef x C0 products in an LDS slot of its own, loaded a plane
+  // ahead (lane m, before the plane's axis-1 step) and written before its
+  // stores: no global load waits at the start of a plane, where it would
+  // also wait for the previous plane's stores (memory operations complete
+  // in issue order).
+  for (int e = t; e < SGEN_MAX_TERMS * 2 * KH1; e += GM_NT) {
+    const int m = e / (2 * KH1), i1 = e - m * (2 * KH1);
+    sm.C1[m][i1] = (m < M && i1 < a.n1) ? float(C1[int64_t(m) * a.np1 + i1]) : 0.0f;
+  }
+  const int mlane = lane < M ? lane : M - 1;   // lane m < 32 loads term m
+  auto plane_factor = [&](int64_t pl) {       // coef x C0 of term mlane, plane pl
+    pl = pl < a.planes ? pl : a.planes - 1;   // (past the last plane: loaded, unused)
+    const int64_t fp = pl / a.n0;
+    const int ip = int(pl - fp * a.n0);
+    return a.gen.coef[fp * M + mlane] * C0[int64_t(mlane) * a.np0 + ip];
+  };
+  {
+    const double pf0 = plane_factor(blockIdx.x / NCH);
+    if (lane < SGEN_MAX_TERMS) sm.Pf[wave][0][lane] = pf0;
+  }
+  __syncthreads();
+  int par = 0;
+  for (int64_t pl = blockIdx.x / NCH; pl < a.planes; pl += pstride, par ^= 1) {
     const int64_t f = pl / a.n0;
     const int i0 = int(pl - f * a.n0);
     // row factors of the tile's rows and of their mirrors (MFMA B operands)
@@ -453,9 +480,7 @@ __global__ __launch_bounds__(GM_NT) void k_split_gen_mid(GmArgs a) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int m = 8 * lk + e;
-        const int mm = m < M ? m : M - 1;
-        const double x = a.gen.coef[f * M + mm] * C0[int64_t(mm) * a.np0 + i0] *
-                         C1[int64_t(mm) * a.np1 + i1];
+        const double x = sm.Pf[wave][par][m] * double(sm.C1[m][i1]);
         v[e] = m < M ? float(x) : 0.0f;
       }
       split8(v, rfh[mi], rfl[mi]);
@@ -528,6 +553,7 @@ __global__ __launch_bounds__(GM_NT) void k_split_gen_mid(GmArgs a) {
       *reinterpret_cast<bf16x4 *>(&sm.U[1][1][n][p0]) = wl;
     }
     __syncthreads();
+    const double pf_next = plane_factor(pl + pstride);
 
     // axis 1: the wave's mode rows of half h1 times the folded plane
     f4 z[IB][4];
@@ -549,6 +575,8 @@ __global__ __launch_bounds__(GM_NT) void k_split_gen_mid(GmArgs a) {
         }
       }
     }
+    // (read by this wave only, at its next plane)
+    if (lane < SGEN_MAX_TERMS) sm.Pf[wave][par ^ 1][lane] = pf_next;
     // lane (x, q) holds modes 4 q + r of the tile at column x of each P2 tile
     float *Yp = a.Y + (f * a.np0 + i0) * int64_t(a.np1) * a.np2 + P2b + lr;
 #pragma unroll
